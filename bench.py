@@ -1,0 +1,196 @@
+"""Benchmark of the batched pentadiagonal solve on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Default workload ``hyperdiff``: 1-D hyperdiffusion, backward Euler,
+A = I + 50*D4 with N = 4096, 65536 independent systems (C^0 uniform[-1, 1),
+seed 2), factor once, every step solves A C^{k+1} = C^k in place.  A step is
+one full solve of all 65536 systems; inputs are resident in HBM before the
+timed region.  Prints one JSON line.
+
+Other workloads (for tuning runs): ``plain`` (N=256, 256 RHS).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RHS-solves/s and HBM GB/s (% peak), FP32+refine vs FP64 at rel resid 1e-12"
+PEAK_HBM_GBS = 8000.0
+BYTES_PER_UNKNOWN_FP64 = 16  # read f once, write x once
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(os.path.join(ROOT, "paper_1807_07382_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1807_07382_amd", "csrc", name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh).get(f"{kernel}@{workload}")
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline_hyperdiff(n, sigma, C0, budget_s=12.0):
+    """The oracle (as it is) on the host cores, on a bounded column sample."""
+    import oracle
+    from oracle import workloads  # noqa: F401
+    cols = 8192
+    sample = np.ascontiguousarray(C0[:, :cols])
+    dg = oracle.assemble_d4(n, sigma)
+    fac = oracle.factor(dg)
+    X = sample.copy()
+    oracle.solve_inplace(dg, fac, X)  # warm-up
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.solve_inplace(dg, fac, X)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return dict(value=cols * steps / el, unit="RHS-solves/s", cores=oracle.threads(),
+                kind="oracle",
+                sample=f"{cols} of the {C0.shape[1]} systems (N={n}), {steps} backward-Euler "
+                       f"steps, {el:.1f} s, OpenMP over systems; factorisation excluded")
+
+
+def run_hyperdiff(args, torch):
+    from paper_1807_07382_amd import inputs
+    from paper_1807_07382_amd import pentbatch as pb
+    import oracle
+    from oracle import workloads
+
+    cfg = inputs.HYPERDIFF
+    n, sigma, batch = cfg["n"], cfg["sigma"], cfg["batch"]
+    w = inputs.hyperdiff()
+    C0 = w["C0"]
+    probe = np.array([0, 1, 63, 64, 4095, 31337, batch - 1])
+    probe0 = C0[:, probe].copy()
+    T = torch.from_numpy(C0).cuda()
+    stream = torch.cuda.current_stream()
+    t_fac0 = time.perf_counter()
+    plan = pb.Plan.factor_d4(n, sigma)
+    fac_s = time.perf_counter() - t_fac0
+    if args.schedule:
+        kind, seg = (int(x) for x in args.schedule.split(","))
+        plan.set_schedule(kind, seg)
+    for _ in range(args.warmup):
+        plan.solve_(T, stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.solve_(T, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    # parity of the probe systems after all warmup + timed steps
+    X = T[:, torch.from_numpy(probe).cuda()].cpu().numpy()
+    ref = workloads.hyperdiffusion(n, sigma, probe0, args.warmup + args.steps)
+    err = float(np.max(np.max(np.abs(X - ref), axis=0) / np.max(np.abs(ref), axis=0)))
+    plan.close()
+    ms_step = ms / args.steps
+    solves_s = batch * args.steps / (ms / 1e3)
+    alg_bytes = BYTES_PER_UNKNOWN_FP64 * n * batch
+    achieved = alg_bytes / (ms_step / 1e3) / 1e9
+    kname = "k_lane" if (not args.schedule or args.schedule.startswith("1")) else "k_part"
+    tr = traffic_for(kname, "hyperdiff")
+    out = dict(
+        metric=METRIC, value=solves_s, unit="RHS-solves/s", n_gpus=1, steps=args.steps,
+        warmup=args.warmup, ms_per_step=ms_step, higher_is_better=True, scaling="weak",
+        vs_baseline=None, dtype="f64", data="synthetic",
+        config=dict(workload="hyperdiff", n=n, systems=batch, sigma=sigma,
+                    implicit_steps=args.steps, layout="interleaved (batch-fastest)",
+                    parallelism="single GPU"),
+        roofline=dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
+                      frac=achieved / PEAK_HBM_GBS,
+                      traffic=tr),
+        row_updates_per_s=solves_s * n,
+        factor_ms=fac_s * 1e3,
+        parity=dict(probe_systems=len(probe), max_rel_err_vs_oracle=err),
+    )
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline_hyperdiff(n, sigma, C0)
+    return out
+
+
+def run_plain(args, torch):
+    from paper_1807_07382_amd import inputs
+    from paper_1807_07382_amd import pentbatch as pb
+    w = inputs.plain()
+    n, sigma, F = w["n"], w["sigma"], w["F"]
+    T = torch.from_numpy(F).cuda()
+    stream = torch.cuda.current_stream()
+    plan = pb.Plan.factor_d4(n, sigma)
+    if args.schedule:
+        kind, seg = (int(x) for x in args.schedule.split(","))
+        plan.set_schedule(kind, seg)
+    for _ in range(args.warmup):
+        plan.solve_(T, stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.solve_(T, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    plan.close()
+    ms_step = ms / args.steps
+    return dict(metric=METRIC, value=F.shape[1] / (ms_step / 1e3), unit="RHS-solves/s",
+                n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms_step,
+                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+                data="synthetic", config=dict(workload="plain", n=n, systems=F.shape[1],
+                                              sigma=sigma))
+
+
+WORKLOADS = {"hyperdiff": run_hyperdiff, "plain": run_plain}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="hyperdiff", choices=sorted(WORKLOADS))
+    ap.add_argument("--schedule", default="", help="force kind,seg_rows (tuning)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards "
+              "by systems with no exchange, see the design notes.", file=sys.stderr)
+        return 2
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    out = WORKLOADS[args.workload](args, torch)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,124 @@
+/*
+ * pentbatch.h -- C ABI of libpentbatch.so, a batched pentadiagonal solver for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Gloster, O Naraigh and Pang, "cuPentBatch -- A batched pentadiagonal
+ * solver for NVIDIA GPUs" (arXiv:1807.07382).  One N x N pentadiagonal matrix
+ * A is factored once, A = L R without pivoting (Sec. 2.4), and the factors
+ * are reused to solve A x_j = f_j for very many right-hand sides held in the
+ * interleaved layout of Sec. 2.6.
+ *
+ * Conventions shared by every entry point
+ *  - Rows are 0-based: row i of this API is row i+1 of the paper.
+ *  - Diagonals are row-indexed (Sec. 2.4): row i holds a[i] (column i-2),
+ *    b[i] (column i-1), c[i] (column i), d[i] (column i+1), e[i] (column i+2).
+ *    a[0], a[1], b[0], d[n-1], e[n-2] and e[n-1] fall outside the matrix and
+ *    are never read.
+ *  - Batch-fastest ("interleaved", Sec. 2.6) right-hand sides: element
+ *    (row i, system j) lives at F[i*ld + j], 0 <= i < n, 0 <= j < batch,
+ *    ld >= batch, in elements (not bytes).
+ *  - Device pointers are HIP device (or managed) memory on the device that
+ *    was current when the handle was made; host pointers are ordinary host
+ *    memory.  The caller owns every buffer it passes and must keep it alive
+ *    until the stream work that uses it has finished.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *    Solves are asynchronous: they only enqueue kernels.
+ *  - Errors are returned as a pent_status; nothing throws across the ABI.
+ *    Argument checks run before any HIP call, so a bad argument never leaves
+ *    work queued.  pent_last_status() repeats the status of the calling
+ *    thread's last call.
+ *  - Stability: no pivoting, as in the paper.  The method is stable for
+ *    symmetric positive definite or diagonally dominant A (Sec. 2.6); other
+ *    matrices with non-zero pivots are solved but may be inaccurate.
+ */
+#ifndef PENTBATCH_H
+#define PENTBATCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pent_plan *pent_handle;
+
+typedef enum pent_status {
+    PENT_OK = 0,
+    PENT_INVALID_VALUE = 1, /* bad argument (null pointer, n < 1, ld < batch, ...) */
+    PENT_ZERO_PIVOT = 2,    /* alpha_i == 0 or non-finite; row in pent_last_pivot_row() */
+    PENT_OUT_OF_MEMORY = 3, /* a device allocation failed */
+    PENT_HIP_ERROR = 4,     /* a HIP runtime call or kernel launch failed */
+    PENT_NOT_CONVERGED = 5, /* refinement did not reach its tolerance */
+    PENT_SIZE_MISMATCH = 6, /* buffers of one call disagree in size */
+    PENT_NOT_SUPPORTED = 7  /* a valid request this build does not handle */
+} pent_status;
+
+/* ---------------------------------------------------------------- factor --
+ * Factor A = L R once (Sec. 2.4, factorisation steps; Sec. 2.6 splits the
+ * factorisation from the solve so a constant matrix is factored only once).
+ * a..e: HOST arrays of n doubles (row-indexed, see above); copied, the caller
+ * keeps ownership.  The factorisation runs on the current device and the call
+ * blocks until it has finished (one synchronisation, to read the pivot
+ * check).  Returns a handle, or NULL with pent_last_status() set to
+ * PENT_INVALID_VALUE, PENT_ZERO_PIVOT (see pent_last_pivot_row()),
+ * PENT_OUT_OF_MEMORY or PENT_HIP_ERROR.  Limits: 1 <= n <= 2^31 - 1. */
+pent_handle pent_factor(int64_t n, const double *a, const double *b, const double *c,
+                        const double *d, const double *e);
+
+/* Same, for the matrix of the implicit hyperdiffusion step I + sigma*D4
+ * (Sec. 2.3, coefficient list a = e = sigma, b = d = -4 sigma,
+ * c = 1 + 6 sigma), non-periodic: the row stencil is truncated at both ends.
+ * The diagonals are assembled on the device. */
+pent_handle pent_factor_d4(int64_t n, double sigma);
+
+/* Free a handle.  NULL is a no-op.  The caller must have synchronised every
+ * stream with work that uses the handle. */
+int pent_destroy(pent_handle h);
+
+/* ----------------------------------------------------------------- solve --
+ * Overwrite F (DEVICE, FP64, batch-fastest, element (i, j) at F[i*ld + j])
+ * with X = A^{-1} F: forward sweep L g = f, then back substitution R x = g
+ * (Sec. 2.4), every system independent (Sec. 2.6).  Asynchronous on
+ * `stream`.  batch == 0 is a no-op (F may then be NULL).  Returns
+ * PENT_INVALID_VALUE for a bad handle, batch < 0, ld < batch or F == NULL.
+ * The schedule (one lane per system, or several lanes per system through a
+ * partitioned sweep) is chosen by the library; it may allocate stream-ordered
+ * scratch memory on `stream`. */
+int pent_solve(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream);
+
+/* Same solve for system-major storage: system j occupies n contiguous
+ * doubles at F + j*ld (element (i, j) at F[j*ld + i]), ld >= n.  This is the
+ * layout of the second direction of an alternating-direction (ADI-style)
+ * sweep over a 2-D grid (Sec. 4 names ADI as the route to 2-D and 3-D
+ * problems). */
+int pent_solve_strided(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream);
+
+/* ----------------------------------------------------------- inspection --
+ * Copy the handle's data to HOST arrays of n doubles each (blocking).
+ * pent_get_factors: alpha, beta, gamma, delta of Sec. 2.4 (epsilon = a).
+ * pent_get_diagonals: the (zero-padded) diagonals the handle factored. */
+int pent_get_factors(pent_handle h, double *alpha, double *beta, double *gamma, double *delta);
+int pent_get_diagonals(pent_handle h, double *a, double *b, double *c, double *d, double *e);
+int64_t pent_size(pent_handle h); /* n, or -1 for a bad handle */
+
+/* Force a schedule for this handle (tests and tuning):
+ *   kind 0: automatic (default);
+ *   kind 1: one lane per system, both sweeps in one kernel (the paper's
+ *           one-thread-per-system schedule, Sec. 2.4 last paragraph);
+ *   kind 2: partitioned: seg_rows consecutive rows per lane, several lanes
+ *           per system, with a reduced interface recurrence between the
+ *           segments (seg_rows in {16, 32, 64}).
+ * Returns PENT_INVALID_VALUE for an unknown kind or seg_rows. */
+int pent_set_schedule(pent_handle h, int kind, int seg_rows);
+
+/* --------------------------------------------------------------- status -- */
+int pent_last_status(void);
+int64_t pent_last_pivot_row(void); /* row of the last PENT_ZERO_PIVOT, else -1 */
+const char *pent_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PENTBATCH_H */

@@ -1,0 +1,321 @@
+// api.hip -- the C ABI of libpentbatch (declared in include/pentbatch.h):
+// argument checks, handle lifetime, schedule choice and kernel launches.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+using namespace pent;
+
+namespace {
+
+thread_local int g_status = PENT_OK;
+thread_local int64_t g_pivot_row = -1;
+
+inline int ret(int st)
+{
+    g_status = st;
+    return st;
+}
+
+inline int hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return PENT_OK;
+    if (e == hipErrorOutOfMemory) return PENT_OUT_OF_MEMORY;
+    return PENT_HIP_ERROR;
+}
+
+inline bool valid(pent_handle h) { return h != nullptr && h->magic == kMagic; }
+
+void free_plan(pent_plan *p)
+{
+    if (!p) return;
+    if (p->d_diag) (void)hipFree(p->d_diag);
+    if (p->d_fac) (void)hipFree(p->d_fac);
+    if (p->d_fwd) (void)hipFree(p->d_fwd);
+    if (p->d_bwd) (void)hipFree(p->d_bwd);
+    for (auto &c : p->seg)
+        if (c.d_seg) (void)hipFree(c.d_seg);
+    p->magic = 0;
+    delete p;
+}
+
+// Allocate a plan whose diagonals (5n doubles, device) the caller fills.
+pent_plan *new_plan(int64_t n, int *st)
+{
+    pent_plan *p = new (std::nothrow) pent_plan();
+    if (!p) {
+        *st = PENT_OUT_OF_MEMORY;
+        return nullptr;
+    }
+    p->magic = 0;
+    p->n = n;
+    p->d_diag = nullptr;
+    p->d_fac = nullptr;
+    p->d_fwd = nullptr;
+    p->d_bwd = nullptr;
+    p->sched_kind = 0;
+    p->sched_seg = 0;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e == hipSuccess) e = hipMalloc(&p->d_diag, sizeof(double) * 5 * n);
+    if (e == hipSuccess) e = hipMalloc(&p->d_fac, sizeof(double) * 4 * n);
+    if (e == hipSuccess) e = hipMalloc(&p->d_fwd, sizeof(FwdRec) * n);
+    if (e == hipSuccess) e = hipMalloc(&p->d_bwd, sizeof(BwdRec) * n);
+    if (e != hipSuccess) {
+        free_plan(p);
+        *st = hip_status(e);
+        return nullptr;
+    }
+    *st = PENT_OK;
+    return p;
+}
+
+// Factor the diagonals already in p->d_diag; blocks.  Consumes p on error.
+pent_handle finish_factor(pent_plan *p)
+{
+    int64_t *d_bad = nullptr;
+    int64_t bad = -1;
+    hipError_t e = hipMalloc(&d_bad, sizeof(int64_t));
+    if (e == hipSuccess) e = launch_factor(p->d_diag, p->n, p->d_fac, p->d_fwd, p->d_bwd, d_bad, 0);
+    if (e == hipSuccess) e = hipMemcpy(&bad, d_bad, sizeof(int64_t), hipMemcpyDeviceToHost);
+    if (d_bad) (void)hipFree(d_bad);
+    if (e != hipSuccess) {
+        free_plan(p);
+        ret(hip_status(e));
+        return nullptr;
+    }
+    if (bad >= 0) {
+        free_plan(p);
+        g_pivot_row = bad;
+        ret(PENT_ZERO_PIVOT);
+        return nullptr;
+    }
+    p->magic = kMagic;
+    ret(PENT_OK);
+    return p;
+}
+
+// Per-segment constants for seg_rows, built once per handle on first use.
+// The build runs on the null stream and synchronises it, so later solves on
+// any stream see the finished constants.
+const SegRec *seg_cache(pent_plan *p, int seg_rows, int *st)
+{
+    int slot = seg_rows == 16 ? 0 : seg_rows == 32 ? 1 : 2;
+    std::lock_guard<std::mutex> lk(p->mu);
+    SegCache &c = p->seg[slot];
+    if (c.d_seg) {
+        *st = PENT_OK;
+        return c.d_seg;
+    }
+    const int64_t nseg = (p->n + seg_rows - 1) / seg_rows;
+    SegRec *d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(SegRec) * nseg);
+    if (e == hipSuccess) e = launch_seg_prep(p->d_fwd, p->d_bwd, p->n, seg_rows, d, 0);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        if (d) (void)hipFree(d);
+        *st = hip_status(e);
+        return nullptr;
+    }
+    c.seg_rows = seg_rows;
+    c.nseg = nseg;
+    c.d_seg = d;
+    *st = PENT_OK;
+    return d;
+}
+
+// Automatic schedule: one lane per system when there are enough systems to
+// give every SIMD of the chip at least one wave; otherwise split the rows.
+void choose_schedule(const pent_plan *p, int64_t batch, int *kind, int *seg_rows)
+{
+    if (p->sched_kind != 0) {
+        *kind = p->sched_kind;
+        *seg_rows = p->sched_seg;
+        return;
+    }
+    const int64_t waves = (batch + 63) / 64;
+    if (waves >= 1024 || p->n < 64) {
+        *kind = 1;
+        *seg_rows = 0;
+    } else {
+        *kind = 2;
+        *seg_rows = 64;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+pent_handle pent_factor(int64_t n, const double *a, const double *b, const double *c,
+                        const double *d, const double *e)
+{
+    g_pivot_row = -1;
+    if (n < 1 || n > INT32_MAX || !a || !b || !c || !d || !e) {
+        ret(PENT_INVALID_VALUE);
+        return nullptr;
+    }
+    int st;
+    pent_plan *p = new_plan(n, &st);
+    if (!p) {
+        ret(st);
+        return nullptr;
+    }
+    // zero-pad the entries that fall outside the matrix, then copy
+    double *h = new (std::nothrow) double[5 * n];
+    if (!h) {
+        free_plan(p);
+        ret(PENT_OUT_OF_MEMORY);
+        return nullptr;
+    }
+    for (int64_t i = 0; i < n; i++) {
+        h[0 * n + i] = (i >= 2) ? a[i] : 0.0;
+        h[1 * n + i] = (i >= 1) ? b[i] : 0.0;
+        h[2 * n + i] = c[i];
+        h[3 * n + i] = (i + 1 < n) ? d[i] : 0.0;
+        h[4 * n + i] = (i + 2 < n) ? e[i] : 0.0;
+    }
+    hipError_t err = hipMemcpy(p->d_diag, h, sizeof(double) * 5 * n, hipMemcpyHostToDevice);
+    delete[] h;
+    if (err != hipSuccess) {
+        free_plan(p);
+        ret(hip_status(err));
+        return nullptr;
+    }
+    return finish_factor(p);
+}
+
+pent_handle pent_factor_d4(int64_t n, double sigma)
+{
+    g_pivot_row = -1;
+    if (n < 1 || n > INT32_MAX || !std::isfinite(sigma)) {
+        ret(PENT_INVALID_VALUE);
+        return nullptr;
+    }
+    int st;
+    pent_plan *p = new_plan(n, &st);
+    if (!p) {
+        ret(st);
+        return nullptr;
+    }
+    hipError_t err = launch_assemble_d4(p->d_diag, n, sigma, 0);
+    if (err != hipSuccess) {
+        free_plan(p);
+        ret(hip_status(err));
+        return nullptr;
+    }
+    return finish_factor(p);
+}
+
+int pent_destroy(pent_handle h)
+{
+    if (h == nullptr) return ret(PENT_OK);
+    if (!valid(h)) return ret(PENT_INVALID_VALUE);
+    free_plan(h);
+    return ret(PENT_OK);
+}
+
+int pent_solve(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream)
+{
+    if (!valid(h) || batch < 0 || ld < batch) return ret(PENT_INVALID_VALUE);
+    if (batch == 0) return ret(PENT_OK);
+    if (!F) return ret(PENT_INVALID_VALUE);
+    hipStream_t s = (hipStream_t)stream;
+    int kind, seg_rows;
+    choose_schedule(h, batch, &kind, &seg_rows);
+    if (kind == 2 && (h->n + seg_rows - 1) / seg_rows > 65535) kind = 1;
+    if (kind == 1) return ret(hip_status(launch_lane_sweep(h->d_fwd, h->d_bwd, h->n, F, batch, ld, s)));
+    int st;
+    const SegRec *seg = seg_cache(h, seg_rows, &st);
+    if (!seg) return ret(st);
+    const int64_t nseg = (h->n + seg_rows - 1) / seg_rows;
+    const int64_t summ_ld = (batch + 63) / 64 * 64;
+    double *summ = nullptr;
+    hipError_t e = hipMallocAsync((void **)&summ, sizeof(double) * 4 * nseg * summ_ld, s);
+    if (e != hipSuccess) return ret(hip_status(e));
+    e = launch_part_sweep(h->d_fwd, h->d_bwd, seg, h->n, seg_rows, F, batch, ld, summ, summ_ld, s);
+    hipError_t e2 = hipFreeAsync(summ, s);
+    if (e == hipSuccess) e = e2;
+    return ret(hip_status(e));
+}
+
+int pent_solve_strided(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream)
+{
+    if (!valid(h) || batch < 0 || ld < h->n) return ret(PENT_INVALID_VALUE);
+    if (batch == 0) return ret(PENT_OK);
+    if (!F) return ret(PENT_INVALID_VALUE);
+    return ret(hip_status(
+        launch_strided_sweep(h->d_fwd, h->d_bwd, h->n, F, batch, ld, (hipStream_t)stream)));
+}
+
+int pent_get_factors(pent_handle h, double *alpha, double *beta, double *gamma, double *delta)
+{
+    if (!valid(h) || !alpha || !beta || !gamma || !delta) return ret(PENT_INVALID_VALUE);
+    const int64_t n = h->n;
+    double *outs[4] = {alpha, beta, gamma, delta};
+    for (int k = 0; k < 4; k++) {
+        hipError_t e = hipMemcpy(outs[k], h->d_fac + k * n, sizeof(double) * n, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return ret(hip_status(e));
+    }
+    return ret(PENT_OK);
+}
+
+int pent_get_diagonals(pent_handle h, double *a, double *b, double *c, double *d, double *e)
+{
+    if (!valid(h) || !a || !b || !c || !d || !e) return ret(PENT_INVALID_VALUE);
+    const int64_t n = h->n;
+    double *outs[5] = {a, b, c, d, e};
+    for (int k = 0; k < 5; k++) {
+        hipError_t err = hipMemcpy(outs[k], h->d_diag + k * n, sizeof(double) * n, hipMemcpyDeviceToHost);
+        if (err != hipSuccess) return ret(hip_status(err));
+    }
+    return ret(PENT_OK);
+}
+
+int64_t pent_size(pent_handle h)
+{
+    if (!valid(h)) {
+        ret(PENT_INVALID_VALUE);
+        return -1;
+    }
+    ret(PENT_OK);
+    return h->n;
+}
+
+int pent_set_schedule(pent_handle h, int kind, int seg_rows)
+{
+    if (!valid(h)) return ret(PENT_INVALID_VALUE);
+    if (kind == 0 || kind == 1) {
+        h->sched_kind = kind;
+        h->sched_seg = 0;
+        return ret(PENT_OK);
+    }
+    if (kind == 2 && (seg_rows == 16 || seg_rows == 32 || seg_rows == 64)) {
+        h->sched_kind = 2;
+        h->sched_seg = seg_rows;
+        return ret(PENT_OK);
+    }
+    return ret(PENT_INVALID_VALUE);
+}
+
+int pent_last_status(void) { return g_status; }
+
+int64_t pent_last_pivot_row(void) { return g_pivot_row; }
+
+const char *pent_status_string(int status)
+{
+    switch (status) {
+    case PENT_OK: return "success";
+    case PENT_INVALID_VALUE: return "invalid argument";
+    case PENT_ZERO_PIVOT: return "zero or non-finite pivot (matrix not factorable without pivoting)";
+    case PENT_OUT_OF_MEMORY: return "device out of memory";
+    case PENT_HIP_ERROR: return "HIP runtime error";
+    case PENT_NOT_CONVERGED: return "iterative refinement did not converge";
+    case PENT_SIZE_MISMATCH: return "buffer sizes disagree";
+    case PENT_NOT_SUPPORTED: return "not supported";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,197 @@
+// factor.hip -- assembly of I + sigma*D4, the A = L R factorisation and the
+// per-segment constants of the partitioned sweep.
+#include "internal.h"
+
+namespace pent {
+namespace {
+
+// I + sigma*D4 (Sec. 2.3 coefficient list), truncated at both ends.  The
+// products and the sum 1 + 6 sigma are rounded separately (no contraction)
+// so the diagonals are the IEEE values of the printed formulas.
+__global__ void k_assemble_d4(double *__restrict__ diag, int64_t n, double sigma)
+{
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double s4 = -4.0 * sigma;
+    diag[0 * n + i] = (i >= 2) ? sigma : 0.0;
+    diag[1 * n + i] = (i >= 1) ? s4 : 0.0;
+    diag[2 * n + i] = 1.0 + 6.0 * sigma;
+    diag[3 * n + i] = (i + 1 < n) ? s4 : 0.0;
+    diag[4 * n + i] = (i + 2 < n) ? sigma : 0.0;
+}
+
+// A = L R (Sec. 2.4).  The recurrence is serial in the row index, so one
+// lane runs it; it touches 9 doubles per row and runs once per matrix.  The
+// paper's first and last rows are the general step with zero padding:
+//   beta_i  = b_i - a_i gamma_{i-2}
+//   alpha_i = c_i - a_i delta_{i-2} - beta_i gamma_{i-1}
+//   gamma_i = (d_i - beta_i delta_{i-1}) / alpha_i
+//   delta_i = e_i / alpha_i
+// Operations are rounded one by one in the written order (no contraction,
+// IEEE division), so the factors are the correctly rounded values of that
+// sequence.  *bad receives the first row with a zero or non-finite pivot,
+// or -1.
+__global__ void k_factor_serial(const double *__restrict__ diag, int64_t n,
+                                double *__restrict__ fac, int64_t *__restrict__ bad)
+{
+#pragma clang fp contract(off)
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const double *a = diag, *b = diag + n, *c = diag + 2 * n, *d = diag + 3 * n,
+                 *e = diag + 4 * n;
+    double *alpha = fac, *beta = fac + n, *gamma = fac + 2 * n, *delta = fac + 3 * n;
+    double gam2 = 0.0, del2 = 0.0, gam1 = 0.0, del1 = 0.0;
+    int64_t badrow = -1;
+    for (int64_t i = 0; i < n; i++) {
+        const double ai = (i >= 2) ? a[i] : 0.0;
+        const double bi = (i >= 1) ? b[i] : 0.0;
+        const double di = (i + 1 < n) ? d[i] : 0.0;
+        const double ei = (i + 2 < n) ? e[i] : 0.0;
+        const double be = bi - ai * gam2;
+        const double al = c[i] - ai * del2 - be * gam1;
+        beta[i] = be;
+        alpha[i] = al;
+        if (!(al != 0.0) || !__builtin_isfinite(al)) {
+            badrow = i;
+            for (int64_t k = i; k < n; k++) {  // leave defined values behind
+                gamma[k] = 0.0;
+                delta[k] = 0.0;
+                if (k > i) { alpha[k] = 1.0; beta[k] = 0.0; }
+            }
+            break;
+        }
+        const double ga = (di - be * del1) / al;
+        const double de = ei / al;
+        gamma[i] = ga;
+        delta[i] = de;
+        gam2 = gam1; del2 = del1;
+        gam1 = ga;   del1 = de;
+    }
+    *bad = badrow;
+}
+
+// Sweep records from the factors (row-parallel).
+__global__ void k_records(const double *__restrict__ diag, const double *__restrict__ fac,
+                          int64_t n, FwdRec *__restrict__ fwd, BwdRec *__restrict__ bwd)
+{
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double al = fac[i];
+    const double be = (i >= 1) ? fac[n + i] : 0.0;
+    const double ai = (i >= 2) ? diag[i] : 0.0;
+    FwdRec r;
+    r.ra = 1.0 / al;
+    r.ap = ai / al;
+    r.bp = be / al;
+    r.pad = 0.0;
+    fwd[i] = r;
+    BwdRec q;
+    q.gm = (i + 1 < n) ? fac[2 * n + i] : 0.0;
+    q.dl = (i + 2 < n) ? fac[3 * n + i] : 0.0;
+    bwd[i] = q;
+}
+
+// Per-segment transfer matrices of the partitioned sweep.  For segment s
+// (rows r0 .. r0+L-1, L = min(K, n-r0)):
+//   u, v  = forward responses to the incoming states (1,0) and (0,1) with f = 0;
+//   tf    = outgoing forward state of u, v;
+//   cg    = outgoing backward state of the zero-incoming back substitution of u, v;
+//   tb    = outgoing backward state of the back substitution of g = 0 from the
+//           incoming states (1,0) and (0,1).
+// The recurrences are the same prescaled ones the sweeps use.
+template <int K>
+__global__ void k_seg_prep(const FwdRec *__restrict__ fwd, const BwdRec *__restrict__ bwd,
+                           int64_t n, int64_t nseg, SegRec *__restrict__ seg)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nseg) return;
+    const int64_t r0 = s * K;
+    const int L = (int)((n - r0) < K ? (n - r0) : K);
+    double u[K], v[K];
+    SegRec out;
+    // forward responses
+    {
+        double up2 = 1.0, up1 = 0.0, vp2 = 0.0, vp1 = 1.0;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            if (k < L) {
+                const FwdRec r = fwd[r0 + k];
+                const double gu = fma(-r.bp, up1, -r.ap * up2);
+                const double gv = fma(-r.bp, vp1, -r.ap * vp2);
+                u[k] = gu; v[k] = gv;
+                up2 = up1; up1 = gu;
+                vp2 = vp1; vp1 = gv;
+            } else {
+                u[k] = 0.0; v[k] = 0.0;
+            }
+        }
+        out.tf[0] = up2; out.tf[1] = up1;
+        out.tf[2] = vp2; out.tf[3] = vp1;
+    }
+    // backward: zero-incoming over u, v; and g = 0 from unit incoming states
+    {
+        double uq1 = 0.0, uq2 = 0.0, vq1 = 0.0, vq2 = 0.0;
+        double aq1 = 1.0, aq2 = 0.0, bq1 = 0.0, bq2 = 1.0;
+#pragma unroll
+        for (int k = K - 1; k >= 0; k--) {
+            if (k < L) {
+                const BwdRec q = bwd[r0 + k];
+                const double xu = fma(-q.gm, uq1, fma(-q.dl, uq2, u[k]));
+                const double xv = fma(-q.gm, vq1, fma(-q.dl, vq2, v[k]));
+                const double xa = fma(-q.gm, aq1, -q.dl * aq2);
+                const double xb = fma(-q.gm, bq1, -q.dl * bq2);
+                uq2 = uq1; uq1 = xu;
+                vq2 = vq1; vq1 = xv;
+                aq2 = aq1; aq1 = xa;
+                bq2 = bq1; bq1 = xb;
+            }
+        }
+        out.cg[0] = uq1; out.cg[1] = uq2;
+        out.cg[2] = vq1; out.cg[3] = vq2;
+        out.tb[0] = aq1; out.tb[1] = aq2;
+        out.tb[2] = bq1; out.tb[3] = bq2;
+    }
+    out.pad[0] = out.pad[1] = out.pad[2] = out.pad[3] = 0.0;
+    seg[s] = out;
+}
+
+}  // namespace
+
+hipError_t launch_assemble_d4(double *d_diag, int64_t n, double sigma, hipStream_t s)
+{
+    const int bs = 256;
+    const int64_t grid = (n + bs - 1) / bs;
+    hipLaunchKernelGGL(k_assemble_d4, dim3((unsigned)grid), dim3(bs), 0, s, d_diag, n, sigma);
+    return hipGetLastError();
+}
+
+hipError_t launch_factor(const double *d_diag, int64_t n, double *d_fac, FwdRec *d_fwd,
+                         BwdRec *d_bwd, int64_t *d_bad, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_factor_serial, dim3(1), dim3(64), 0, s, d_diag, n, d_fac, d_bad);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    const int bs = 256;
+    const int64_t grid = (n + bs - 1) / bs;
+    hipLaunchKernelGGL(k_records, dim3((unsigned)grid), dim3(bs), 0, s, d_diag, d_fac, n,
+                       d_fwd, d_bwd);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_prep(const FwdRec *d_fwd, const BwdRec *d_bwd, int64_t n, int seg_rows,
+                           SegRec *d_seg, hipStream_t s)
+{
+    const int64_t nseg = (n + seg_rows - 1) / seg_rows;
+    const int bs = 64;
+    const dim3 grid((unsigned)((nseg + bs - 1) / bs));
+    switch (seg_rows) {
+    case 16: hipLaunchKernelGGL(k_seg_prep<16>, grid, dim3(bs), 0, s, d_fwd, d_bwd, n, nseg, d_seg); break;
+    case 32: hipLaunchKernelGGL(k_seg_prep<32>, grid, dim3(bs), 0, s, d_fwd, d_bwd, n, nseg, d_seg); break;
+    case 64: hipLaunchKernelGGL(k_seg_prep<64>, grid, dim3(bs), 0, s, d_fwd, d_bwd, n, nseg, d_seg); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pent

@@ -1,0 +1,88 @@
+// internal.h -- shared declarations of libpentbatch's host code and kernel
+// launchers (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <mutex>
+
+#include "../../include/pentbatch.h"
+
+namespace pent {
+
+// Per-row constants of the forward sweep, prescaled by 1/alpha_i so the
+// recurrence g_i = (f_i - a_i g_{i-2} - beta_i g_{i-1}) / alpha_i (Sec. 2.4)
+// becomes g_i = ra*f_i - ap*g_{i-2} - bp*g_{i-1}, one fused multiply-add on
+// the g_{i-1} dependency chain.
+struct alignas(32) FwdRec {
+    double ra;  // 1 / alpha_i
+    double ap;  // a_i / alpha_i      (a_i = epsilon_i)
+    double bp;  // beta_i / alpha_i
+    double pad;
+};
+
+// Per-row constants of the back substitution x_i = g_i - gamma_i x_{i+1}
+// - delta_i x_{i+2} (Sec. 2.4).
+struct alignas(16) BwdRec {
+    double gm;  // gamma_i
+    double dl;  // delta_i
+};
+
+// Per-segment constants of the partitioned sweep (segment = seg_rows
+// consecutive rows).  Forward state entering a segment: (g_{r0-2}, g_{r0-1});
+// leaving it: the last two g's.  Backward state entering from below:
+// (x_{r1}, x_{r1+1}); leaving upward: (x_{r0}, x_{r0+1}).  Each 2x2 matrix is
+// stored column-major: m[0] m[1] = image of the first unit state, m[2] m[3] =
+// image of the second.
+struct alignas(128) SegRec {
+    double tf[4];  // forward state in  -> forward state out   (f = 0)
+    double cg[4];  // forward state in  -> backward state out  (f = 0, x below = 0)
+    double tb[4];  // backward state in -> backward state out  (g = 0)
+    double pad[4];
+};
+
+constexpr int kMaxSegCaches = 3;  // seg_rows 16, 32, 64
+
+struct SegCache {
+    int seg_rows = 0;
+    int64_t nseg = 0;
+    SegRec *d_seg = nullptr;
+};
+
+}  // namespace pent
+
+struct pent_plan {
+    uint64_t magic;
+    int64_t n;
+    int device;
+    double *d_diag;          // 5n: a, b, c, d, e (zero-padded outside the matrix)
+    double *d_fac;           // 4n: alpha, beta, gamma, delta
+    pent::FwdRec *d_fwd;     // n
+    pent::BwdRec *d_bwd;     // n
+    int sched_kind;          // 0 auto, 1 lane, 2 partitioned
+    int sched_seg;           // seg_rows for kind 2
+    std::mutex mu;           // guards seg caches (lazy build)
+    pent::SegCache seg[pent::kMaxSegCaches];
+};
+
+namespace pent {
+
+constexpr uint64_t kMagic = 0x70656e7462617463ull;  // "pentbatc"
+
+// ---- launchers (each returns a hipError_t from the launch) ----
+hipError_t launch_assemble_d4(double *d_diag, int64_t n, double sigma, hipStream_t s);
+hipError_t launch_factor(const double *d_diag, int64_t n, double *d_fac, FwdRec *d_fwd,
+                         BwdRec *d_bwd, int64_t *d_bad, hipStream_t s);
+hipError_t launch_seg_prep(const FwdRec *d_fwd, const BwdRec *d_bwd, int64_t n, int seg_rows,
+                           SegRec *d_seg, hipStream_t s);
+
+hipError_t launch_lane_sweep(const FwdRec *fwd, const BwdRec *bwd, int64_t n, double *F,
+                             int64_t batch, int64_t ld, hipStream_t s);
+hipError_t launch_part_sweep(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg,
+                             int64_t n, int seg_rows, double *F, int64_t batch, int64_t ld,
+                             double *summ, int64_t summ_ld, hipStream_t s);
+hipError_t launch_strided_sweep(const FwdRec *fwd, const BwdRec *bwd, int64_t n, double *F,
+                                int64_t batch, int64_t ld, hipStream_t s);
+
+}  // namespace pent

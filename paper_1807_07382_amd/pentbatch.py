@@ -1,0 +1,195 @@
+"""Thin ctypes binding of libpentbatch.so (C ABI in include/pentbatch.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  torch is used for device memory and streams; a torch tensor of
+shape (n, batch) with unit stride along the batch axis *is* the interleaved,
+batch-fastest layout (ld = tensor.stride(0)).
+
+The library is loaded on first use.  If it is missing this module raises --
+there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpentbatch.so")
+
+OK = 0
+INVALID_VALUE = 1
+ZERO_PIVOT = 2
+OUT_OF_MEMORY = 3
+HIP_ERROR = 4
+NOT_CONVERGED = 5
+SIZE_MISMATCH = 6
+NOT_SUPPORTED = 7
+
+# every symbol include/pentbatch.h declares: name -> (restype, argtypes)
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I = ctypes.c_int
+_D = ctypes.c_double
+SIGNATURES = {
+    "pent_factor": (_P, [_I64, _P, _P, _P, _P, _P]),
+    "pent_factor_d4": (_P, [_I64, _D]),
+    "pent_destroy": (_I, [_P]),
+    "pent_solve": (_I, [_P, _P, _I64, _I64, _P]),
+    "pent_solve_strided": (_I, [_P, _P, _I64, _I64, _P]),
+    "pent_get_factors": (_I, [_P, _P, _P, _P, _P]),
+    "pent_get_diagonals": (_I, [_P, _P, _P, _P, _P, _P]),
+    "pent_size": (_I64, [_P]),
+    "pent_set_schedule": (_I, [_P, _I, _I]),
+    "pent_last_status": (_I, []),
+    "pent_last_pivot_row": (_I64, []),
+    "pent_status_string": (ctypes.c_char_p, [_I]),
+}
+
+_lib = None
+
+
+class PentError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = lib().pent_status_string(status).decode()
+        super().__init__(f"{what}: {msg} (status {status})" if what else msg)
+
+
+class ZeroPivotError(PentError):
+    def __init__(self, row: int):
+        super().__init__(ZERO_PIVOT, f"factorisation stopped at row {row}")
+        self.row = row
+
+
+def lib():
+    """The loaded library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_1807_07382_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st: int, what: str):
+    if st != OK:
+        raise PentError(st, what)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dptr(t, dtype_name: str):
+    import torch
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if t.dtype != getattr(torch, dtype_name):
+        raise ValueError(f"expected {dtype_name}, got {t.dtype}")
+    return t.data_ptr()
+
+
+class Plan:
+    """A factored matrix (pent_handle).  Free with close() or a with-block."""
+
+    def __init__(self, handle: int, n: int):
+        self._h = handle
+        self.n = n
+
+    # -- construction ------------------------------------------------------
+    @classmethod
+    def factor(cls, a, b, c, d, e) -> "Plan":
+        """Factor the matrix with HOST diagonals a..e (float64 sequences of
+        length n, row-indexed)."""
+        import numpy as np
+        arrs = [np.ascontiguousarray(np.asarray(x, dtype=np.float64)) for x in (a, b, c, d, e)]
+        n = arrs[2].shape[0]
+        if any(x.shape != (n,) for x in arrs):
+            raise ValueError("diagonals must all have shape (n,)")
+        h = lib().pent_factor(n, *[x.ctypes.data for x in arrs])
+        return cls._made(h, n)
+
+    @classmethod
+    def factor_d4(cls, n: int, sigma: float) -> "Plan":
+        """Factor I + sigma*D4 (non-periodic), assembled on the device."""
+        h = lib().pent_factor_d4(int(n), float(sigma))
+        return cls._made(h, n)
+
+    @classmethod
+    def _made(cls, h, n):
+        if not h:
+            st = lib().pent_last_status()
+            if st == ZERO_PIVOT:
+                raise ZeroPivotError(int(lib().pent_last_pivot_row()))
+            raise PentError(st, "factor")
+        return cls(h, int(n))
+
+    # -- lifetime ------------------------------------------------------------
+    def close(self):
+        if self._h:
+            _check(lib().pent_destroy(self._h), "destroy")
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- solves --------------------------------------------------------------
+    def solve_(self, F, stream=None):
+        """Overwrite F (cuda float64, shape (n, batch), unit batch stride) with
+        A^{-1} F.  Asynchronous on ``stream`` (default: torch's current)."""
+        if F.dim() != 2 or F.shape[0] != self.n or (F.shape[1] > 1 and F.stride(1) != 1):
+            raise ValueError(f"F must have shape ({self.n}, batch) with unit batch stride")
+        ld = F.stride(0) if F.shape[1] > 0 else F.shape[1]
+        _check(lib().pent_solve(self._h, _dptr(F, "float64"), F.shape[1], max(ld, F.shape[1]),
+                                _stream_ptr(stream)), "solve")
+        return F
+
+    def solve_strided_(self, F, stream=None):
+        """Overwrite F (cuda float64, shape (batch, n), unit stride along n)
+        with the solutions of its rows (system-major storage)."""
+        if F.dim() != 2 or F.shape[1] != self.n or F.stride(1) != 1:
+            raise ValueError(f"F must have shape (batch, {self.n}) with unit stride along n")
+        _check(lib().pent_solve_strided(self._h, _dptr(F, "float64"), F.shape[0],
+                                        max(F.stride(0), self.n), _stream_ptr(stream)),
+               "solve_strided")
+        return F
+
+    # -- inspection ----------------------------------------------------------
+    def factors(self):
+        import numpy as np
+        out = [np.empty(self.n) for _ in range(4)]
+        _check(lib().pent_get_factors(self._h, *[x.ctypes.data for x in out]), "get_factors")
+        return tuple(out)
+
+    def diagonals(self):
+        import numpy as np
+        out = [np.empty(self.n) for _ in range(5)]
+        _check(lib().pent_get_diagonals(self._h, *[x.ctypes.data for x in out]), "get_diagonals")
+        return tuple(out)
+
+    def set_schedule(self, kind: int, seg_rows: int = 0):
+        _check(lib().pent_set_schedule(self._h, int(kind), int(seg_rows)), "set_schedule")

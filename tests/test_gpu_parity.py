@@ -1,0 +1,199 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  Factorisation and assembly are compared bit for bit;
+solves element by element within the tolerance of tests/_gpu.py, plus the
+backward-error gate eta <= 1e-12 (compensated residual)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import workloads
+from paper_1807_07382_amd import inputs
+from paper_1807_07382_amd import pentbatch as pb
+from tests._gpu import colerr, d4_tol, print_case, torch_dev
+from tests.test_oracle_pins import random_dd
+
+pytestmark = pytest.mark.gpu
+
+SCHEDULES = [(1, 0), (2, 16), (2, 32), (2, 64)]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return torch_dev()
+
+
+def solve_gpu(torch, plan, F, kind=0, seg=0, ld=None):
+    """Solve on the GPU with a forced schedule; returns (X, padding after)."""
+    n, m = F.shape
+    ld = m if ld is None else ld
+    buf = np.random.Generator(np.random.PCG64(99)).uniform(-9, 9, (n, ld))
+    buf[:, :m] = F
+    T = torch.from_numpy(buf).cuda()
+    plan.set_schedule(kind, seg)
+    plan.solve_(T[:, :m])
+    torch.cuda.synchronize()
+    out = T.cpu().numpy()
+    return out[:, :m], (out[:, m:], buf[:, m:])
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 64, 257, 4096])
+@pytest.mark.parametrize("sigma", [0.0, 0.1, 50.0, 200.0, 1e4])
+def test_assembly_and_factors_bitwise(torch, n, sigma):
+    print_case(test="factor_d4", n=n, sigma=sigma)
+    with pb.Plan.factor_d4(n, sigma) as p:
+        dg = oracle.assemble_d4(n, sigma)
+        for got, ref in zip(p.diagonals(), dg):
+            assert np.array_equal(got, ref)
+        fac = oracle.factor(dg)
+        for got, ref in zip(p.factors(), fac):
+            assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 300])
+def test_general_factors_bitwise(torch, n):
+    print_case(test="factor_general", n=n)
+    dg = random_dd(n, seed=n)
+    with pb.Plan.factor(*dg) as p:
+        for got, ref in zip(p.factors(), oracle.factor(dg)):
+            assert np.array_equal(got, ref)
+
+
+def test_zero_pivot_rows(torch):
+    print_case(test="zero_pivot")
+    dg = oracle.assemble_d4(6, 1.0)
+    dg.c[0] = 0.0
+    with pytest.raises(pb.ZeroPivotError) as ei:
+        pb.Plan.factor(*dg)
+    assert ei.value.row == 0
+    sing = (np.zeros(2), np.array([0.0, 1.0]), np.array([1.0, 1.0]), np.array([1.0, 0.0]),
+            np.zeros(2))
+    with pytest.raises(pb.ZeroPivotError) as ei:
+        pb.Plan.factor(*sing)
+    assert ei.value.row == 1
+    dg = oracle.assemble_d4(8, 1.0)
+    dg.c[5] = np.inf
+    with pytest.raises(pb.ZeroPivotError) as ei:
+        pb.Plan.factor(*dg)
+    assert ei.value.row == 5
+
+
+@pytest.mark.parametrize("kind,seg", SCHEDULES)
+def test_plain_workload(torch, kind, seg):
+    """N=256, sigma=0.1, 256 RHS: the whole output against the oracle."""
+    w = inputs.plain()
+    print_case(test="plain", kind=kind, seg=seg)
+    ref = oracle.solve(oracle.assemble_d4(w["n"], w["sigma"]), w["F"])
+    with pb.Plan.factor_d4(w["n"], w["sigma"]) as p:
+        X, _ = solve_gpu(torch, p, w["F"], kind, seg)
+    assert np.all(colerr(X, ref) <= d4_tol(w["sigma"]))
+    eta, _ = oracle.residual(oracle.assemble_d4(w["n"], w["sigma"]), X, w["F"])
+    assert np.all(eta <= 1e-12)
+
+
+@pytest.mark.parametrize("kind,seg", SCHEDULES)
+@pytest.mark.parametrize("n,m,pad", [(1, 5, 0), (2, 3, 1), (3, 64, 0), (5, 65, 3), (17, 1, 7),
+                                     (63, 127, 1), (64, 64, 64), (65, 200, 0), (100, 63, 5),
+                                     (257, 129, 0), (1000, 300, 20)])
+def test_ragged_sizes(torch, kind, seg, n, m, pad):
+    print_case(test="ragged", kind=kind, seg=seg, n=n, m=m, pad=pad)
+    sigma = 3.0
+    F = np.random.Generator(np.random.PCG64(n * 1000 + m)).uniform(-1, 1, (n, m))
+    ref = oracle.solve(oracle.assemble_d4(n, sigma), F)
+    with pb.Plan.factor_d4(n, sigma) as p:
+        X, (after, before) = solve_gpu(torch, p, F, kind, seg, ld=m + pad)
+    assert np.all(colerr(X, ref) <= d4_tol(sigma))
+    assert np.array_equal(after, before), "columns past the batch were modified"
+
+
+@pytest.mark.parametrize("kind,seg", SCHEDULES)
+@pytest.mark.parametrize("sigma", [0.1, 50.0, 1e4])
+def test_general_nonsymmetric(torch, kind, seg, sigma):
+    """Non-symmetric diagonally dominant matrix with random-sign diagonal."""
+    n, m = 777, 130
+    print_case(test="general", kind=kind, seg=seg, sigma=sigma)
+    dg = random_dd(n, seed=int(sigma * 10) + 1)
+    F = np.random.Generator(np.random.PCG64(5)).uniform(-1, 1, (n, m))
+    ref = oracle.solve(dg, F)
+    with pb.Plan.factor(*dg) as p:
+        X, _ = solve_gpu(torch, p, F, kind, seg)
+    assert np.all(colerr(X, ref) <= 1e-13)
+    eta, _ = oracle.residual(dg, X, F)
+    assert np.all(eta <= 1e-15)
+
+
+@pytest.mark.parametrize("kind,seg", SCHEDULES)
+def test_column_bits_independent_of_position(torch, kind, seg):
+    """A fixed schedule gives the same bits for a system wherever it sits in
+    the batch and whatever ld is."""
+    n = 300
+    print_case(test="position", kind=kind, seg=seg)
+    g = np.random.Generator(np.random.PCG64(3))
+    col = g.uniform(-1, 1, n)
+    outs = []
+    with pb.Plan.factor_d4(n, 50.0) as p:
+        for m, pos, pad in [(1, 0, 0), (64, 17, 0), (300, 299, 9), (130, 64, 1)]:
+            F = g.uniform(-1, 1, (n, m))
+            F[:, pos] = col
+            X, _ = solve_gpu(torch, p, F, kind, seg, ld=m + pad)
+            outs.append(X[:, pos].copy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_batch_zero_is_noop(torch):
+    with pb.Plan.factor_d4(16, 1.0) as p:
+        assert pb.lib().pent_solve(p.handle, None, 0, 0, None) == pb.OK
+        T = torch.zeros((16, 0), dtype=torch.float64, device="cuda")
+        p.solve_(T)
+
+
+def test_solve_argument_errors(torch):
+    with pb.Plan.factor_d4(16, 1.0) as p:
+        T = torch.zeros((16, 8), dtype=torch.float64, device="cuda")
+        L = pb.lib()
+        assert L.pent_solve(p.handle, T.data_ptr(), 8, 7, None) == pb.INVALID_VALUE
+        assert L.pent_solve(p.handle, T.data_ptr(), -1, 8, None) == pb.INVALID_VALUE
+        assert L.pent_solve(p.handle, None, 8, 8, None) == pb.INVALID_VALUE
+        assert L.pent_solve_strided(p.handle, T.data_ptr(), 1, 15, None) == pb.INVALID_VALUE
+        assert L.pent_set_schedule(p.handle, 2, 48) == pb.INVALID_VALUE
+        assert L.pent_set_schedule(p.handle, 9, 0) == pb.INVALID_VALUE
+
+
+@pytest.mark.parametrize("n,m,pad", [(1, 3, 0), (5, 64, 2), (33, 65, 0), (1024, 100, 8),
+                                     (1000, 130, 3)])
+def test_strided_layout(torch, n, m, pad):
+    """System-major storage: system j = n contiguous values at F + j*ld."""
+    print_case(test="strided", n=n, m=m, pad=pad)
+    sigma = 200.0
+    g = np.random.Generator(np.random.PCG64(n + m))
+    buf = g.uniform(-1, 1, (m, n + pad))
+    ref = oracle.solve(oracle.assemble_d4(n, sigma), np.ascontiguousarray(buf[:, :n].T))
+    T = torch.from_numpy(buf.copy()).cuda()
+    with pb.Plan.factor_d4(n, sigma) as p:
+        p.solve_strided_(T[:, :n])
+        torch.cuda.synchronize()
+    out = T.cpu().numpy()
+    assert np.all(colerr(np.ascontiguousarray(out[:, :n].T), ref) <= d4_tol(sigma))
+    assert np.array_equal(out[:, n:], buf[:, n:])
+
+
+def test_hyperdiff_full_size_sampled(torch):
+    """The hyperdiffusion workload at full size (N=4096, 65536 systems, the
+    automatic schedule the benchmark uses), two backward-Euler steps; 256
+    sampled systems against the oracle and the contraction property on all."""
+    w = inputs.hyperdiff()
+    n, sigma = w["n"], w["sigma"]
+    print_case(test="hyperdiff_full", n=n, batch=w["C0"].shape[1])
+    cols = np.random.Generator(np.random.PCG64(77)).choice(w["C0"].shape[1], 256, replace=False)
+    cols = np.concatenate([cols, [0, 63, 64, w["C0"].shape[1] - 1]])
+    T = torch.from_numpy(w["C0"]).cuda()
+    norm0 = torch.linalg.vector_norm(T, dim=0)
+    with pb.Plan.factor_d4(n, sigma) as p:
+        p.solve_(T)
+        p.solve_(T)
+        torch.cuda.synchronize()
+    norm2 = torch.linalg.vector_norm(T, dim=0)
+    assert bool(torch.all(norm2 <= norm0))
+    X = T[:, torch.from_numpy(cols).cuda()].cpu().numpy()
+    ref = workloads.hyperdiffusion(n, sigma, w["C0"][:, cols], 2)
+    assert np.all(colerr(X, ref) <= 2 * d4_tol(sigma))
