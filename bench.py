@@ -167,7 +167,69 @@ def run_plain(args, torch):
                                               sigma=sigma))
 
 
-WORKLOADS = {"hyperdiff": run_hyperdiff, "plain": run_plain}
+def run_copy(args, torch):
+    """Plain device-to-device copy of a buffer the size of the hyperdiffusion
+    state (torch's copy kernel): the attainable-bandwidth reference, and the
+    known-size kernel the HBM counters are scaled by."""
+    from paper_1807_07382_amd import inputs
+    n, batch = inputs.HYPERDIFF["n"], inputs.HYPERDIFF["batch"]
+    src = torch.empty((n, batch), dtype=torch.float64, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        dst.copy_(src)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    nbytes = 2 * src.numel() * 8
+    return dict(metric="device copy bandwidth", value=nbytes / (ms_step / 1e3) / 1e9,
+                unit="GB/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+                ms_per_step=ms_step, bytes_per_launch=nbytes, higher_is_better=True,
+                dtype="f64", data="synthetic",
+                config=dict(workload="copy", elements=src.numel()))
+
+
+def run_shape(args, torch):
+    """One solve of ``--batch`` systems of size ``--n`` (I + sigma*D4),
+    batch-fastest, repeated ``--steps`` times in place (tuning sweeps)."""
+    from paper_1807_07382_amd import pentbatch as pb
+    n, batch, sigma = args.n, args.batch, args.sigma
+    T = torch.empty((n, batch), dtype=torch.float64, device="cuda").uniform_(-1, 1)
+    stream = torch.cuda.current_stream()
+    plan = pb.Plan.factor_d4(n, sigma)
+    if args.schedule:
+        kind, seg = (int(x) for x in args.schedule.split(","))
+        plan.set_schedule(kind, seg)
+    for _ in range(args.warmup):
+        plan.solve_(T, stream)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        plan.solve_(T, stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    plan.close()
+    gbs = BYTES_PER_UNKNOWN_FP64 * n * batch / (ms_step / 1e3) / 1e9
+    return dict(metric=METRIC, value=batch / (ms_step / 1e3), unit="RHS-solves/s", n_gpus=1,
+                steps=args.steps, warmup=args.warmup, ms_per_step=ms_step,
+                higher_is_better=True, dtype="f64", data="synthetic",
+                config=dict(workload="shape", n=n, systems=batch, sigma=sigma,
+                            schedule=args.schedule or "auto"),
+                roofline=dict(bound="hbm", achieved=gbs, peak=PEAK_HBM_GBS, unit="GB/s",
+                              frac=gbs / PEAK_HBM_GBS, traffic=None))
+
+
+WORKLOADS = {"hyperdiff": run_hyperdiff, "plain": run_plain, "copy": run_copy,
+             "shape": run_shape}
 
 
 def main(argv=None):
@@ -178,6 +240,9 @@ def main(argv=None):
     ap.add_argument("--workload", default="hyperdiff", choices=sorted(WORKLOADS))
     ap.add_argument("--schedule", default="", help="force kind,seg_rows (tuning)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--n", type=int, default=1024, help="shape workload: rows")
+    ap.add_argument("--batch", type=int, default=32768, help="shape workload: systems")
+    ap.add_argument("--sigma", type=float, default=200.0, help="shape workload: sigma")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards "

@@ -108,7 +108,10 @@ int64_t pent_size(pent_handle h); /* n, or -1 for a bad handle */
  *           one-thread-per-system schedule, Sec. 2.4 last paragraph);
  *   kind 2: partitioned: seg_rows consecutive rows per lane, several lanes
  *           per system, with a reduced interface recurrence between the
- *           segments (seg_rows in {16, 32, 64}).
+ *           segments (seg_rows in {16, 32, 64});
+ *   kind 3: resident tile: 8 systems per workgroup held whole in registers
+ *           (n <= 4096), one read of f and one write of x; seg_rows ignored.
+ *           For larger n a solve falls back to kind 2.
  * Returns PENT_INVALID_VALUE for an unknown kind or seg_rows. */
 int pent_set_schedule(pent_handle h, int kind, int seg_rows);
 

@@ -37,6 +37,8 @@ void free_plan(pent_plan *p)
     if (p->d_bwd) (void)hipFree(p->d_bwd);
     for (auto &c : p->seg)
         if (c.d_seg) (void)hipFree(c.d_seg);
+    if (p->d_scan) (void)hipFree(p->d_scan);
+    if (p->d_trec) (void)hipFree(p->d_trec);
     p->magic = 0;
     delete p;
 }
@@ -51,17 +53,21 @@ pent_plan *new_plan(int64_t n, int *st)
     }
     p->magic = 0;
     p->n = n;
+    p->npad = (n + kRecPad - 1) / kRecPad * kRecPad;
     p->d_diag = nullptr;
     p->d_fac = nullptr;
     p->d_fwd = nullptr;
     p->d_bwd = nullptr;
     p->sched_kind = 0;
     p->sched_seg = 0;
+    p->d_scan = nullptr;
+    p->d_trec = nullptr;
+    p->scan_rows = 0;
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipMalloc(&p->d_diag, sizeof(double) * 5 * n);
     if (e == hipSuccess) e = hipMalloc(&p->d_fac, sizeof(double) * 4 * n);
-    if (e == hipSuccess) e = hipMalloc(&p->d_fwd, sizeof(FwdRec) * n);
-    if (e == hipSuccess) e = hipMalloc(&p->d_bwd, sizeof(BwdRec) * n);
+    if (e == hipSuccess) e = hipMalloc(&p->d_fwd, sizeof(FwdRec) * p->npad);
+    if (e == hipSuccess) e = hipMalloc(&p->d_bwd, sizeof(BwdRec) * p->npad);
     if (e != hipSuccess) {
         free_plan(p);
         *st = hip_status(e);
@@ -77,7 +83,7 @@ pent_handle finish_factor(pent_plan *p)
     int64_t *d_bad = nullptr;
     int64_t bad = -1;
     hipError_t e = hipMalloc(&d_bad, sizeof(int64_t));
-    if (e == hipSuccess) e = launch_factor(p->d_diag, p->n, p->d_fac, p->d_fwd, p->d_bwd, d_bad, 0);
+    if (e == hipSuccess) e = launch_factor(p->d_diag, p->n, p->npad, p->d_fac, p->d_fwd, p->d_bwd, d_bad, 0);
     if (e == hipSuccess) e = hipMemcpy(&bad, d_bad, sizeof(int64_t), hipMemcpyDeviceToHost);
     if (d_bad) (void)hipFree(d_bad);
     if (e != hipSuccess) {
@@ -99,10 +105,9 @@ pent_handle finish_factor(pent_plan *p)
 // Per-segment constants for seg_rows, built once per handle on first use.
 // The build runs on the null stream and synchronises it, so later solves on
 // any stream see the finished constants.
-const SegRec *seg_cache(pent_plan *p, int seg_rows, int *st)
+const SegRec *seg_cache_locked(pent_plan *p, int seg_rows, int *st)
 {
     int slot = seg_rows == 16 ? 0 : seg_rows == 32 ? 1 : 2;
-    std::lock_guard<std::mutex> lk(p->mu);
     SegCache &c = p->seg[slot];
     if (c.d_seg) {
         *st = PENT_OK;
@@ -125,20 +130,63 @@ const SegRec *seg_cache(pent_plan *p, int seg_rows, int *st)
     return d;
 }
 
-// Automatic schedule: one lane per system when there are enough systems to
-// give every SIMD of the chip at least one wave; otherwise split the rows.
+const SegRec *seg_cache(pent_plan *p, int seg_rows, int *st)
+{
+    std::lock_guard<std::mutex> lk(p->mu);
+    return seg_cache_locked(p, seg_rows, st);
+}
+
+// Interface-scan constants and record image of the resident-tile schedule
+// (built once per handle).
+bool tile_cache(pent_plan *p, int rows, const ScanRec **scan, const double **trec, int *st)
+{
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (!(p->d_scan && p->scan_rows == rows)) {
+        const SegRec *seg = seg_cache_locked(p, rows, st);
+        if (!seg) return false;
+        ScanRec *d = nullptr;
+        double *t = nullptr;
+        hipError_t e = hipMalloc(&d, sizeof(ScanRec) * 64);
+        if (e == hipSuccess) e = hipMalloc(&t, sizeof(double) * tile_recs_doubles(rows));
+        if (e == hipSuccess) e = launch_scan_prep(seg, (p->n + rows - 1) / rows, d, 0);
+        if (e == hipSuccess) e = launch_tile_recs(p->d_fwd, p->d_bwd, rows, t, 0);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            if (d) (void)hipFree(d);
+            if (t) (void)hipFree(t);
+            *st = hip_status(e);
+            return false;
+        }
+        if (p->d_scan) (void)hipFree(p->d_scan);
+        if (p->d_trec) (void)hipFree(p->d_trec);
+        p->d_scan = d;
+        p->d_trec = t;
+        p->scan_rows = rows;
+    }
+    *scan = p->d_scan;
+    *trec = p->d_trec;
+    *st = PENT_OK;
+    return true;
+}
+
+// Automatic schedule (chosen from measured sweeps over sizes on MI355X): the
+// resident tile for small solves, where launch count and latency dominate
+// (it is one kernel, the partitioned sweep three); the partitioned sweep for
+// large ones, where HBM streaming dominates and the tile's one-workgroup-per-
+// CU residency cannot overlap loads with compute.
 void choose_schedule(const pent_plan *p, int64_t batch, int *kind, int *seg_rows)
 {
     if (p->sched_kind != 0) {
         *kind = p->sched_kind;
         *seg_rows = p->sched_seg;
-        return;
-    }
-    const int64_t waves = (batch + 63) / 64;
-    if (waves >= 1024 || p->n < 64) {
-        *kind = 1;
+    } else if (tile_rows_for(p->n) > 0 && p->n * batch <= (int64_t)8 << 20) {
+        *kind = 3;
         *seg_rows = 0;
     } else {
+        *kind = 2;
+        *seg_rows = p->n <= 2048 ? 32 : 64;
+    }
+    if (*kind == 3 && tile_rows_for(p->n) == 0) {
         *kind = 2;
         *seg_rows = 64;
     }
@@ -227,6 +275,13 @@ int pent_solve(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream
     if (kind == 2 && (h->n + seg_rows - 1) / seg_rows > 65535) kind = 1;
     if (kind == 1) return ret(hip_status(launch_lane_sweep(h->d_fwd, h->d_bwd, h->n, F, batch, ld, s)));
     int st;
+    if (kind == 3) {
+        const int rows = tile_rows_for(h->n);
+        const ScanRec *scan;
+        const double *trec;
+        if (!tile_cache(h, rows, &scan, &trec, &st)) return ret(st);
+        return ret(hip_status(launch_tile_sweep(trec, scan, h->n, rows, F, batch, ld, s)));
+    }
     const SegRec *seg = seg_cache(h, seg_rows, &st);
     if (!seg) return ret(st);
     const int64_t nseg = (h->n + seg_rows - 1) / seg_rows;
@@ -286,7 +341,7 @@ int64_t pent_size(pent_handle h)
 int pent_set_schedule(pent_handle h, int kind, int seg_rows)
 {
     if (!valid(h)) return ret(PENT_INVALID_VALUE);
-    if (kind == 0 || kind == 1) {
+    if (kind == 0 || kind == 1 || kind == 3) {
         h->sched_kind = kind;
         h->sched_seg = 0;
         return ret(PENT_OK);

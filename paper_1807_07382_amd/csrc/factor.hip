@@ -72,11 +72,17 @@ __global__ void k_factor_serial(const double *__restrict__ diag, int64_t n,
 
 // Sweep records from the factors (row-parallel).
 __global__ void k_records(const double *__restrict__ diag, const double *__restrict__ fac,
-                          int64_t n, FwdRec *__restrict__ fwd, BwdRec *__restrict__ bwd)
+                          int64_t n, int64_t npad, FwdRec *__restrict__ fwd,
+                          BwdRec *__restrict__ bwd)
 {
 #pragma clang fp contract(off)
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= npad) return;
+    if (i >= n) {  // padding rows: all zero
+        fwd[i] = FwdRec{0.0, 0.0, 0.0, 0.0};
+        bwd[i] = BwdRec{0.0, 0.0};
+        return;
+    }
     const double al = fac[i];
     const double be = (i >= 1) ? fac[n + i] : 0.0;
     const double ai = (i >= 2) ? diag[i] : 0.0;
@@ -166,15 +172,15 @@ hipError_t launch_assemble_d4(double *d_diag, int64_t n, double sigma, hipStream
     return hipGetLastError();
 }
 
-hipError_t launch_factor(const double *d_diag, int64_t n, double *d_fac, FwdRec *d_fwd,
-                         BwdRec *d_bwd, int64_t *d_bad, hipStream_t s)
+hipError_t launch_factor(const double *d_diag, int64_t n, int64_t npad, double *d_fac,
+                         FwdRec *d_fwd, BwdRec *d_bwd, int64_t *d_bad, hipStream_t s)
 {
     hipLaunchKernelGGL(k_factor_serial, dim3(1), dim3(64), 0, s, d_diag, n, d_fac, d_bad);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     const int bs = 256;
-    const int64_t grid = (n + bs - 1) / bs;
-    hipLaunchKernelGGL(k_records, dim3((unsigned)grid), dim3(bs), 0, s, d_diag, d_fac, n,
+    const int64_t grid = (npad + bs - 1) / bs;
+    hipLaunchKernelGGL(k_records, dim3((unsigned)grid), dim3(bs), 0, s, d_diag, d_fac, n, npad,
                        d_fwd, d_bwd);
     return hipGetLastError();
 }

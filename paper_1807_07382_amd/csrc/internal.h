@@ -42,6 +42,22 @@ struct alignas(128) SegRec {
     double pad[4];
 };
 
+// Interface-scan constants of the resident-tile schedule, one record per
+// segment (64 segments): p[l] and q[l] are the products of 2^l consecutive
+// forward / backward transfer matrices ending (p) or starting (q) at the
+// segment, cg the segment's forward-in -> backward-out matrix.
+struct alignas(64) ScanRec {
+    double p[6][4];
+    double q[6][4];
+    double cg[4];
+    double pad[4];
+};
+
+// Factor records are stored for n rounded up to this many rows; the rows
+// past n are all-zero records, which map a zero right-hand side to zero and
+// let fixed-height kernels run without per-row guards.
+constexpr int64_t kRecPad = 4096;
+
 constexpr int kMaxSegCaches = 3;  // seg_rows 16, 32, 64
 
 struct SegCache {
@@ -58,12 +74,16 @@ struct pent_plan {
     int device;
     double *d_diag;          // 5n: a, b, c, d, e (zero-padded outside the matrix)
     double *d_fac;           // 4n: alpha, beta, gamma, delta
-    pent::FwdRec *d_fwd;     // n
-    pent::BwdRec *d_bwd;     // n
-    int sched_kind;          // 0 auto, 1 lane, 2 partitioned
+    int64_t npad;            // record rows: n rounded up to kRecPad, rows >= n all zero
+    pent::FwdRec *d_fwd;     // npad
+    pent::BwdRec *d_bwd;     // npad
+    int sched_kind;          // 0 auto, 1 lane, 2 partitioned, 3 resident tile
     int sched_seg;           // seg_rows for kind 2
     std::mutex mu;           // guards seg caches (lazy build)
     pent::SegCache seg[pent::kMaxSegCaches];
+    pent::ScanRec *d_scan;   // resident-tile scan constants (64 records), lazily built
+    double *d_trec;          // resident-tile record image (5 x 64 x rows doubles)
+    int scan_rows;           // rows per lane they were built for
 };
 
 namespace pent {
@@ -72,8 +92,8 @@ constexpr uint64_t kMagic = 0x70656e7462617463ull;  // "pentbatc"
 
 // ---- launchers (each returns a hipError_t from the launch) ----
 hipError_t launch_assemble_d4(double *d_diag, int64_t n, double sigma, hipStream_t s);
-hipError_t launch_factor(const double *d_diag, int64_t n, double *d_fac, FwdRec *d_fwd,
-                         BwdRec *d_bwd, int64_t *d_bad, hipStream_t s);
+hipError_t launch_factor(const double *d_diag, int64_t n, int64_t npad, double *d_fac,
+                         FwdRec *d_fwd, BwdRec *d_bwd, int64_t *d_bad, hipStream_t s);
 hipError_t launch_seg_prep(const FwdRec *d_fwd, const BwdRec *d_bwd, int64_t n, int seg_rows,
                            SegRec *d_seg, hipStream_t s);
 
@@ -82,6 +102,13 @@ hipError_t launch_lane_sweep(const FwdRec *fwd, const BwdRec *bwd, int64_t n, do
 hipError_t launch_part_sweep(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg,
                              int64_t n, int seg_rows, double *F, int64_t batch, int64_t ld,
                              double *summ, int64_t summ_ld, hipStream_t s);
+int tile_rows_for(int64_t n);  // rows per lane of the resident tile, 0 if n is too large
+hipError_t launch_scan_prep(const SegRec *seg, int64_t nseg, ScanRec *out, hipStream_t s);
+size_t tile_recs_doubles(int rows);
+hipError_t launch_tile_recs(const FwdRec *fwd, const BwdRec *bwd, int rows, double *out,
+                            hipStream_t s);
+hipError_t launch_tile_sweep(const double *trec, const ScanRec *scan, int64_t n, int rows,
+                             double *F, int64_t batch, int64_t ld, hipStream_t s);
 hipError_t launch_strided_sweep(const FwdRec *fwd, const BwdRec *bwd, int64_t n, double *F,
                                 int64_t batch, int64_t ld, hipStream_t s);
 

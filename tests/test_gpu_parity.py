@@ -14,7 +14,7 @@ from tests.test_oracle_pins import random_dd
 
 pytestmark = pytest.mark.gpu
 
-SCHEDULES = [(1, 0), (2, 16), (2, 32), (2, 64)]
+SCHEDULES = [(1, 0), (2, 16), (2, 32), (2, 64), (3, 0)]
 
 
 @pytest.fixture(scope="module")
@@ -138,6 +138,21 @@ def test_column_bits_independent_of_position(torch, kind, seg):
             outs.append(X[:, pos].copy())
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("n", [1024, 1025, 2048, 2049, 4095, 4096, 4097, 5000])
+@pytest.mark.parametrize("m,pad", [(13, 7), (64, 0), (200, 3)])
+def test_tile_row_boundaries(torch, n, m, pad):
+    """Resident tile at the sizes where rows per lane switch (16/32/64) and
+    just past its limit (n > 4096 falls back to the partitioned sweep)."""
+    print_case(test="tile_bounds", n=n, m=m, pad=pad)
+    sigma = 1e4
+    F = np.random.Generator(np.random.PCG64(n + m)).uniform(-1, 1, (n, m))
+    ref = oracle.solve(oracle.assemble_d4(n, sigma), F)
+    with pb.Plan.factor_d4(n, sigma) as p:
+        X, (after, before) = solve_gpu(torch, p, F, 3, 0, ld=m + pad)
+    assert np.all(colerr(X, ref) <= d4_tol(sigma))
+    assert np.array_equal(after, before)
 
 
 def test_batch_zero_is_noop(torch):
