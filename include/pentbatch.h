@@ -94,6 +94,45 @@ int pent_solve(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream
  * problems). */
 int pent_solve_strided(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream);
 
+/* ------------------------------------------------- precision extension --
+ * Element types of the right-hand sides. */
+#define PENT_DTYPE_FP64 0
+#define PENT_DTYPE_FP32 1
+
+/* Solve A x = f with f streamed in FP32 or FP64 and x written in FP64.  The
+ * factors and every operation stay FP64 (the paper computes in FP64, Sec. 3);
+ * only the stored precision of the right-hand-side stream changes, so an
+ * FP32 f costs 4 instead of 8 bytes per unknown and the result is the FP64
+ * solution of the system with the FP32 values as right-hand side.
+ *   f, ld_f : DEVICE, batch-fastest, element (i, j) at f[i*ld_f + j], of
+ *             type f_dtype (PENT_DTYPE_FP32 or PENT_DTYPE_FP64).
+ *   x, ld_x : DEVICE FP64 output, same layout.  x may be f itself only for
+ *             FP64 f with ld_x == ld_f and refine_steps == 0.
+ *   refine_steps (0..16): iterative-refinement corrections after the solve;
+ *             each evaluates r = f - A x in compensated FP64 (every product
+ *             and sum carried with its rounding error), solves A d = r and
+ *             sets x += d.
+ *   eta_out : optional DEVICE array of batch doubles; receives each system's
+ *             backward error ||f - A x||_inf / (||A||_inf ||x||_inf +
+ *             ||f||_inf) with the residual evaluated compensated.
+ *   work    : DEVICE scratch of at least
+ *             pent_mixed_workspace_size(h, batch, refine_steps, eta_out != NULL)
+ *             bytes, caller-owned (NULL allowed when that size is 0).
+ * Asynchronous on `stream`; allocates nothing.  Returns PENT_INVALID_VALUE
+ * for bad arguments, PENT_SIZE_MISMATCH for a workspace that is too small,
+ * PENT_NOT_SUPPORTED for n > 2097120. */
+int pent_solve_mixed(pent_handle h, const void *f, int f_dtype, int64_t ld_f, double *x,
+                     int64_t ld_x, int64_t batch, int refine_steps, double *eta_out, void *work,
+                     size_t work_bytes, void *stream);
+size_t pent_mixed_workspace_size(pent_handle h, int64_t batch, int refine_steps, int want_eta);
+
+/* Per-system backward error of a computed solution x (same definition and
+ * layouts as eta_out above).  work: DEVICE scratch of at least
+ * 24*batch bytes.  Asynchronous on `stream`. */
+int pent_backward_error(pent_handle h, const void *f, int f_dtype, int64_t ld_f, const double *x,
+                        int64_t ld_x, int64_t batch, double *eta_out, void *work,
+                        size_t work_bytes, void *stream);
+
 /* ----------------------------------------------------------- inspection --
  * Copy the handle's data to HOST arrays of n doubles each (blocking).
  * pent_get_factors: alpha, beta, gamma, delta of Sec. 2.4 (epsilon = a).

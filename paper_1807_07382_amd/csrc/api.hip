@@ -33,6 +33,7 @@ void free_plan(pent_plan *p)
     if (!p) return;
     if (p->d_diag) (void)hipFree(p->d_diag);
     if (p->d_fac) (void)hipFree(p->d_fac);
+    if (p->d_anorm) (void)hipFree(p->d_anorm);
     if (p->d_fwd) (void)hipFree(p->d_fwd);
     if (p->d_bwd) (void)hipFree(p->d_bwd);
     for (auto &c : p->seg)
@@ -56,6 +57,7 @@ pent_plan *new_plan(int64_t n, int *st)
     p->npad = (n + kRecPad - 1) / kRecPad * kRecPad;
     p->d_diag = nullptr;
     p->d_fac = nullptr;
+    p->d_anorm = nullptr;
     p->d_fwd = nullptr;
     p->d_bwd = nullptr;
     p->sched_kind = 0;
@@ -66,6 +68,7 @@ pent_plan *new_plan(int64_t n, int *st)
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipMalloc(&p->d_diag, sizeof(double) * 5 * n);
     if (e == hipSuccess) e = hipMalloc(&p->d_fac, sizeof(double) * 4 * n);
+    if (e == hipSuccess) e = hipMalloc(&p->d_anorm, sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&p->d_fwd, sizeof(FwdRec) * p->npad);
     if (e == hipSuccess) e = hipMalloc(&p->d_bwd, sizeof(BwdRec) * p->npad);
     if (e != hipSuccess) {
@@ -84,6 +87,7 @@ pent_handle finish_factor(pent_plan *p)
     int64_t bad = -1;
     hipError_t e = hipMalloc(&d_bad, sizeof(int64_t));
     if (e == hipSuccess) e = launch_factor(p->d_diag, p->n, p->npad, p->d_fac, p->d_fwd, p->d_bwd, d_bad, 0);
+    if (e == hipSuccess) e = launch_anorm(p->d_diag, p->n, p->d_anorm, 0);
     if (e == hipSuccess) e = hipMemcpy(&bad, d_bad, sizeof(int64_t), hipMemcpyDeviceToHost);
     if (d_bad) (void)hipFree(d_bad);
     if (e != hipSuccess) {
@@ -192,6 +196,54 @@ void choose_schedule(const pent_plan *p, int64_t batch, int *kind, int *seg_rows
     }
 }
 
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Scratch of the partitioned schedule for `batch` systems (0 for the others).
+size_t summ_bytes(const pent_plan *p, int kind, int seg_rows, int64_t batch)
+{
+    if (kind != 2) return 0;
+    const int64_t nseg = (p->n + seg_rows - 1) / seg_rows;
+    const int64_t summ_ld = (batch + 63) / 64 * 64;
+    return align256(sizeof(double) * 4 * nseg * summ_ld);
+}
+
+// Effective schedule of an out-of-place / FP32-input solve (the one-lane
+// schedule only works in place on FP64, so it maps to the partitioned one).
+void io_schedule(const pent_plan *p, int64_t batch, bool inplace64, int *kind, int *seg_rows)
+{
+    choose_schedule(p, batch, kind, seg_rows);
+    if (*kind == 2 && (p->n + *seg_rows - 1) / *seg_rows > 65535) *kind = 1;
+    if (*kind == 1 && !inplace64) {
+        *kind = 2;
+        *seg_rows = 64;
+    }
+}
+
+// x = A^{-1} f with FP64 arithmetic; f FP32 or FP64; summ: scratch of
+// summ_bytes() for the chosen schedule.
+int solve_io(pent_plan *h, const void *f, bool f32, int64_t ldf, double *x, int64_t ldx,
+             int64_t batch, void *summ, hipStream_t s)
+{
+    const bool inplace64 = !f32 && (const void *)x == f && ldx == ldf;
+    int kind, seg_rows, st;
+    io_schedule(h, batch, inplace64, &kind, &seg_rows);
+    if (kind == 1) return hip_status(launch_lane_sweep(h->d_fwd, h->d_bwd, h->n, x, batch, ldx, s));
+    if (kind == 3) {
+        const int rows = tile_rows_for(h->n);
+        const ScanRec *scan;
+        const double *trec;
+        if (!tile_cache(h, rows, &scan, &trec, &st)) return st;
+        return hip_status(launch_tile_sweep_io(trec, scan, h->n, rows, f, f32, ldf, x, ldx, batch, s));
+    }
+    const SegRec *seg = seg_cache(h, seg_rows, &st);
+    if (!seg) return st;
+    const int64_t summ_ld = (batch + 63) / 64 * 64;
+    return hip_status(launch_part_sweep_io(h->d_fwd, h->d_bwd, seg, h->n, h->npad, seg_rows, f,
+                                           f32, ldf, x, ldx, batch, (double *)summ, summ_ld, s));
+}
+
+constexpr int kMaxRefine = 16;
+
 }  // namespace
 
 extern "C" {
@@ -289,10 +341,86 @@ int pent_solve(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream
     double *summ = nullptr;
     hipError_t e = hipMallocAsync((void **)&summ, sizeof(double) * 4 * nseg * summ_ld, s);
     if (e != hipSuccess) return ret(hip_status(e));
-    e = launch_part_sweep(h->d_fwd, h->d_bwd, seg, h->n, seg_rows, F, batch, ld, summ, summ_ld, s);
+    e = launch_part_sweep(h->d_fwd, h->d_bwd, seg, h->n, h->npad, seg_rows, F, batch, ld, summ,
+                          summ_ld, s);
     hipError_t e2 = hipFreeAsync(summ, s);
     if (e == hipSuccess) e = e2;
     return ret(hip_status(e));
+}
+
+size_t pent_mixed_workspace_size(pent_handle h, int64_t batch, int refine_steps, int want_eta)
+{
+    if (!valid(h) || batch < 0 || refine_steps < 0 || refine_steps > kMaxRefine) {
+        ret(PENT_INVALID_VALUE);
+        return 0;
+    }
+    int kind, seg_rows;
+    io_schedule(h, batch, false, &kind, &seg_rows);
+    size_t b = summ_bytes(h, kind, seg_rows, batch);
+    if (refine_steps > 0) b += align256(sizeof(double) * (size_t)h->n * batch);
+    if (want_eta) b += align256(sizeof(unsigned long long) * 3 * (size_t)batch);
+    ret(PENT_OK);
+    return b;
+}
+
+int pent_solve_mixed(pent_handle h, const void *f, int f_dtype, int64_t ld_f, double *x,
+                     int64_t ld_x, int64_t batch, int refine_steps, double *eta_out, void *work,
+                     size_t work_bytes, void *stream)
+{
+    if (!valid(h) || batch < 0 || (f_dtype != PENT_DTYPE_FP64 && f_dtype != PENT_DTYPE_FP32) ||
+        ld_f < batch || ld_x < batch || refine_steps < 0 || refine_steps > kMaxRefine)
+        return ret(PENT_INVALID_VALUE);
+    if (batch == 0) return ret(PENT_OK);
+    if (!f || !x) return ret(PENT_INVALID_VALUE);
+    const bool f32 = f_dtype == PENT_DTYPE_FP32;
+    const bool alias = (const void *)x == f;
+    if (alias && (f32 || ld_x != ld_f || refine_steps > 0)) return ret(PENT_INVALID_VALUE);
+    if (h->n > (int64_t)65535 * 32) return ret(PENT_NOT_SUPPORTED);
+    int kind, seg_rows;
+    io_schedule(h, batch, alias, &kind, &seg_rows);
+    const size_t b_summ = summ_bytes(h, kind, seg_rows, batch);
+    const size_t b_r = refine_steps > 0 ? align256(sizeof(double) * (size_t)h->n * batch) : 0;
+    const size_t b_acc = eta_out ? align256(sizeof(unsigned long long) * 3 * (size_t)batch) : 0;
+    const size_t need = b_summ + b_r + b_acc;
+    if (need > 0 && (!work || work_bytes < need)) return ret(need > 0 && work ? PENT_SIZE_MISMATCH : PENT_INVALID_VALUE);
+    char *w = (char *)work;
+    void *summ = w;
+    double *r = (double *)(w + b_summ);
+    unsigned long long *acc = (unsigned long long *)(w + b_summ + b_r);
+    hipStream_t s = (hipStream_t)stream;
+
+    int st = solve_io(h, f, f32, ld_f, x, ld_x, batch, summ, s);
+    if (st != PENT_OK) return ret(st);
+    for (int it = 0; it < refine_steps; it++) {
+        hipError_t e = launch_residual(h->d_diag, h->n, f, f32, ld_f, x, ld_x, r, batch, batch, s);
+        if (e != hipSuccess) return ret(hip_status(e));
+        st = solve_io(h, r, false, batch, r, batch, batch, summ, s);
+        if (st != PENT_OK) return ret(st);
+        e = launch_axpy(x, ld_x, r, batch, h->n, batch, s);
+        if (e != hipSuccess) return ret(hip_status(e));
+    }
+    if (eta_out) {
+        hipError_t e = launch_eta(h->d_diag, h->d_anorm, h->n, f, f32, ld_f, x, ld_x, batch, acc,
+                                  eta_out, s);
+        if (e != hipSuccess) return ret(hip_status(e));
+    }
+    return ret(PENT_OK);
+}
+
+int pent_backward_error(pent_handle h, const void *f, int f_dtype, int64_t ld_f, const double *x,
+                        int64_t ld_x, int64_t batch, double *eta_out, void *work,
+                        size_t work_bytes, void *stream)
+{
+    if (!valid(h) || batch < 0 || (f_dtype != PENT_DTYPE_FP64 && f_dtype != PENT_DTYPE_FP32) ||
+        ld_f < batch || ld_x < batch)
+        return ret(PENT_INVALID_VALUE);
+    if (batch == 0) return ret(PENT_OK);
+    if (!f || !x || !eta_out || !work) return ret(PENT_INVALID_VALUE);
+    if (work_bytes < sizeof(unsigned long long) * 3 * (size_t)batch) return ret(PENT_SIZE_MISMATCH);
+    if (h->n > (int64_t)65535 * 32) return ret(PENT_NOT_SUPPORTED);
+    return ret(hip_status(launch_eta(h->d_diag, h->d_anorm, h->n, f, f_dtype == PENT_DTYPE_FP32,
+                                     ld_f, x, ld_x, batch, (unsigned long long *)work, eta_out,
+                                     (hipStream_t)stream)));
 }
 
 int pent_solve_strided(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream)

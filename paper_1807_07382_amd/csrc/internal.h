@@ -74,6 +74,7 @@ struct pent_plan {
     int device;
     double *d_diag;          // 5n: a, b, c, d, e (zero-padded outside the matrix)
     double *d_fac;           // 4n: alpha, beta, gamma, delta
+    double *d_anorm;         // 1: ||A||_inf
     int64_t npad;            // record rows: n rounded up to kRecPad, rows >= n all zero
     pent::FwdRec *d_fwd;     // npad
     pent::BwdRec *d_bwd;     // npad
@@ -100,8 +101,12 @@ hipError_t launch_seg_prep(const FwdRec *d_fwd, const BwdRec *d_bwd, int64_t n, 
 hipError_t launch_lane_sweep(const FwdRec *fwd, const BwdRec *bwd, int64_t n, double *F,
                              int64_t batch, int64_t ld, hipStream_t s);
 hipError_t launch_part_sweep(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg,
-                             int64_t n, int seg_rows, double *F, int64_t batch, int64_t ld,
-                             double *summ, int64_t summ_ld, hipStream_t s);
+                             int64_t n, int64_t npad, int seg_rows, double *F, int64_t batch,
+                             int64_t ld, double *summ, int64_t summ_ld, hipStream_t s);
+hipError_t launch_part_sweep_io(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg,
+                                int64_t n, int64_t npad, int seg_rows, const void *Fin, bool f32,
+                                int64_t ldf, double *X, int64_t ldx, int64_t batch, double *summ,
+                                int64_t summ_ld, hipStream_t s);
 int tile_rows_for(int64_t n);  // rows per lane of the resident tile, 0 if n is too large
 hipError_t launch_scan_prep(const SegRec *seg, int64_t nseg, ScanRec *out, hipStream_t s);
 size_t tile_recs_doubles(int rows);
@@ -109,6 +114,24 @@ hipError_t launch_tile_recs(const FwdRec *fwd, const BwdRec *bwd, int rows, doub
                             hipStream_t s);
 hipError_t launch_tile_sweep(const double *trec, const ScanRec *scan, int64_t n, int rows,
                              double *F, int64_t batch, int64_t ld, hipStream_t s);
+hipError_t launch_tile_sweep_io(const double *trec, const ScanRec *scan, int64_t n, int rows,
+                                const void *Fin, bool f32, int64_t ldf, double *X, int64_t ldx,
+                                int64_t batch, hipStream_t s);
+
+// ---- precision extension (mixed.hip) ----
+// r = f - A x in compensated FP64 (f of type float or double); r may not alias f or x.
+hipError_t launch_residual(const double *d_diag, int64_t n, const void *f, bool f32, int64_t ldf,
+                           const double *x, int64_t ldx, double *r, int64_t ldr, int64_t batch,
+                           hipStream_t s);
+// x += d
+hipError_t launch_axpy(double *x, int64_t ldx, const double *d, int64_t ldd, int64_t n,
+                       int64_t batch, hipStream_t s);
+// eta[j] = ||f - A x||_inf / (||A||_inf ||x||_inf + ||f||_inf), compensated; acc is
+// 3*batch uint64 of scratch.
+hipError_t launch_eta(const double *d_diag, const double *d_anorm, int64_t n, const void *f,
+                      bool f32, int64_t ldf, const double *x, int64_t ldx, int64_t batch,
+                      unsigned long long *acc, double *eta, hipStream_t s);
+hipError_t launch_anorm(const double *d_diag, int64_t n, double *d_anorm, hipStream_t s);
 hipError_t launch_strided_sweep(const FwdRec *fwd, const BwdRec *bwd, int64_t n, double *F,
                                 int64_t batch, int64_t ld, hipStream_t s);
 

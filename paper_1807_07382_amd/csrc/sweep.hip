@@ -132,69 +132,125 @@ __global__ __launch_bounds__(256) void k_lane(const FwdRec *__restrict__ fwd,
 // backward state.  Pass 1 writes the zero-incoming outgoing states; the chain
 // overwrites them with the true incoming states of the segment.
 
-template <int K>
-__device__ __forceinline__ void seg_load(double (&v)[K], const double *col, int64_t ld, int64_t r0,
+template <int K, typename TI>
+__device__ __forceinline__ void seg_load(double (&v)[K], const TI *col, int64_t ld, int64_t r0,
                                          int L)
 {
+    const TI *base = col + r0 * ld;
     if (L == K) {
 #pragma unroll
-        for (int k = 0; k < K; k++) v[k] = __builtin_nontemporal_load(col + (r0 + k) * ld);
+        for (int k = 0; k < K; k++) v[k] = (double)__builtin_nontemporal_load(base + k * ld);
     } else {
 #pragma unroll
-        for (int k = 0; k < K; k++) v[k] = (k < L) ? col[(r0 + k) * ld] : 0.0;
+        for (int k = 0; k < K; k++) v[k] = (k < L) ? (double)base[k * ld] : 0.0;
     }
 }
 
+// Row records of a segment: lane k of the wave loads the records of row
+// r0 + k (one coalesced load per wave), and step k of a sweep takes them from
+// lane k with v_readlane into scalar registers.  Rows past n have all-zero
+// records, so the sweeps need no per-row guards.
+__device__ __forceinline__ double lane_bcast(double v, int k)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+    return __hiloint2double(hi, lo);
+}
+
+struct LaneRecs {
+    double ra, ap, bp, gm, dl;
+};
+
+__device__ __forceinline__ LaneRecs load_lane_recs(const FwdRec *__restrict__ fwd,
+                                                   const BwdRec *__restrict__ bwd, int64_t r0,
+                                                   int K, int64_t npad)
+{
+    const int lane = threadIdx.x & 63;
+    int64_t row = r0 + (lane < K ? lane : 0);
+    row = row < npad ? row : npad - 1;
+    const FwdRec f = fwd[row];
+    const BwdRec b = bwd[row];
+    return LaneRecs{f.ra, f.ap, f.bp, b.gm, b.dl};
+}
+
+// Same sweeps with the records taken from scalar loads (wave-uniform rows);
+// fewer vector registers than the broadcast form.
 template <int K>
-__device__ __forceinline__ void seg_forward(double (&v)[K], const FwdRec *__restrict__ fwd,
-                                            int64_t r0, int L, double &p2, double &p1)
+__device__ __forceinline__ void seg_forward_s(double (&v)[K], const FwdRec *__restrict__ fwd,
+                                              int64_t r0, double &p2, double &p1)
 {
 #pragma unroll
     for (int k = 0; k < K; k++) {
-        if (k < L) {
-            const FwdRec r = fwd[r0 + k];
-            const double g = fma(-r.bp, p1, fma(-r.ap, p2, r.ra * v[k]));
-            v[k] = g;
-            p2 = p1;
-            p1 = g;
-        }
+        const FwdRec r = fwd[r0 + k];
+        const double g = fma(-r.bp, p1, fma(-r.ap, p2, r.ra * v[k]));
+        v[k] = g;
+        p2 = p1;
+        p1 = g;
     }
 }
 
 template <int K>
-__device__ __forceinline__ void seg_backward(double (&v)[K], const BwdRec *__restrict__ bwd,
-                                             int64_t r0, int L, double &q1, double &q2)
+__device__ __forceinline__ void seg_backward_s(double (&v)[K], const BwdRec *__restrict__ bwd,
+                                               int64_t r0, double &q1, double &q2)
 {
 #pragma unroll
     for (int k = K - 1; k >= 0; k--) {
-        if (k < L) {
-            const BwdRec r = bwd[r0 + k];
-            const double x = fma(-r.gm, q1, fma(-r.dl, q2, v[k]));
-            v[k] = x;
-            q2 = q1;
-            q1 = x;
-        }
+        const BwdRec r = bwd[r0 + k];
+        const double x = fma(-r.gm, q1, fma(-r.dl, q2, v[k]));
+        v[k] = x;
+        q2 = q1;
+        q1 = x;
     }
 }
 
 template <int K>
-__global__ __launch_bounds__(64) void k_part_summary(const FwdRec *__restrict__ fwd,
+__device__ __forceinline__ void seg_forward(double (&v)[K], const LaneRecs &rc, double &p2,
+                                            double &p1)
+{
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const double ra = lane_bcast(rc.ra, k), ap = lane_bcast(rc.ap, k), bp = lane_bcast(rc.bp, k);
+        const double g = fma(-bp, p1, fma(-ap, p2, ra * v[k]));
+        v[k] = g;
+        p2 = p1;
+        p1 = g;
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void seg_backward(double (&v)[K], const LaneRecs &rc, double &q1,
+                                             double &q2)
+{
+#pragma unroll
+    for (int k = K - 1; k >= 0; k--) {
+        const double gm = lane_bcast(rc.gm, k), dl = lane_bcast(rc.dl, k);
+        const double x = fma(-gm, q1, fma(-dl, q2, v[k]));
+        v[k] = x;
+        q2 = q1;
+        q1 = x;
+    }
+}
+
+template <int K, typename TI>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_part_summary(const FwdRec *__restrict__ fwd,
                                                      const BwdRec *__restrict__ bwd, int64_t n,
-                                                     const double *__restrict__ F, int64_t batch,
-                                                     int64_t ld, double *__restrict__ summ,
-                                                     int64_t summ_ld)
+                                                     int64_t npad, const TI *__restrict__ F,
+                                                     int64_t batch, int64_t ld,
+                                                     double *__restrict__ summ, int64_t summ_ld)
 {
     const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const int64_t s = blockIdx.y;
-    if (j >= batch) return;
+    const bool act = j < batch;  // every lane stays: records are read across lanes
     const int64_t r0 = s * K;
     const int L = (int)((n - r0) < K ? (n - r0) : K);
     double v[K];
-    seg_load<K>(v, F + j, ld, r0, L);
+    seg_load<K, TI>(v, F + (act ? j : 0), ld, r0, act ? L : 0);
+    const LaneRecs rc = load_lane_recs(fwd, bwd, r0, K, npad);
     double p2 = 0.0, p1 = 0.0;
-    seg_forward<K>(v, fwd, r0, L, p2, p1);
+    seg_forward<K>(v, rc, p2, p1);
     double q1 = 0.0, q2 = 0.0;
-    seg_backward<K>(v, bwd, r0, L, q1, q2);
+    seg_backward<K>(v, rc, q1, q2);
+    if (!act) return;
     double *o = summ + s * 4 * summ_ld + j;
     o[0] = p2;
     o[summ_ld] = p1;
@@ -239,33 +295,40 @@ __global__ __launch_bounds__(256) void k_part_chain(const SegRec *__restrict__ s
     }
 }
 
-template <int K>
-__global__ __launch_bounds__(64) void k_part_final(const FwdRec *__restrict__ fwd,
+// Pass 2 reads f (type TI, leading dimension ldf) and writes x (FP64,
+// leading dimension ldx); x may be f itself when TI is double and ldx == ldf.
+template <int K, typename TI>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_part_final(const FwdRec *__restrict__ fwd,
                                                    const BwdRec *__restrict__ bwd, int64_t n,
-                                                   double *__restrict__ F, int64_t batch,
-                                                   int64_t ld, const double *__restrict__ summ,
+                                                   int64_t npad, const TI *Fin, int64_t ldf,
+                                                   double *X, int64_t ldx, int64_t batch,
+                                                   const double *__restrict__ summ,
                                                    int64_t summ_ld)
 {
     const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
     const int64_t s = blockIdx.y;
-    if (j >= batch) return;
+    const bool act = j < batch;  // every lane stays: records are read across lanes
+    const int64_t jj = act ? j : 0;
     const int64_t r0 = s * K;
     const int L = (int)((n - r0) < K ? (n - r0) : K);
-    double *col = F + j;
     double v[K];
-    seg_load<K>(v, col, ld, r0, L);
-    const double *o = summ + s * 4 * summ_ld + j;
+    seg_load<K, TI>(v, Fin + jj, ldf, r0, act ? L : 0);
+    double *col = X + jj;
+    const int64_t ld = ldx;
+    const double *o = summ + s * 4 * summ_ld + jj;
     double p2 = o[0], p1 = o[summ_ld];
     double q1 = o[2 * summ_ld], q2 = o[3 * summ_ld];
-    seg_forward<K>(v, fwd, r0, L, p2, p1);
-    seg_backward<K>(v, bwd, r0, L, q1, q2);
+    seg_forward_s<K>(v, fwd, r0, p2, p1);
+    seg_backward_s<K>(v, bwd, r0, q1, q2);
+    if (!act) return;
+    double *base = col + r0 * ld;
     if (L == K) {
 #pragma unroll
-        for (int k = 0; k < K; k++) __builtin_nontemporal_store(v[k], col + (r0 + k) * ld);
+        for (int k = 0; k < K; k++) __builtin_nontemporal_store(v[k], base + k * ld);
     } else {
 #pragma unroll
         for (int k = 0; k < K; k++)
-            if (k < L) col[(r0 + k) * ld] = v[k];
+            if (k < L) base[k * ld] = v[k];
     }
 }
 
@@ -341,43 +404,51 @@ hipError_t launch_lane_sweep(const FwdRec *fwd, const BwdRec *bwd, int64_t n, do
     return hipGetLastError();
 }
 
-hipError_t launch_part_sweep(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg,
-                             int64_t n, int seg_rows, double *F, int64_t batch, int64_t ld,
-                             double *summ, int64_t summ_ld, hipStream_t s)
+template <int K, typename TI>
+static hipError_t part_sweep_k(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg, int64_t n,
+                               int64_t npad, const TI *Fin, int64_t ldf, double *X, int64_t ldx,
+                               int64_t batch, double *summ, int64_t summ_ld, hipStream_t s)
 {
-    const int64_t nseg = (n + seg_rows - 1) / seg_rows;
+    const int64_t nseg = (n + K - 1) / K;
     const dim3 grid((unsigned)((batch + 63) / 64), (unsigned)nseg);
     const dim3 gridc((unsigned)((batch + 255) / 256));
-    switch (seg_rows) {
-    case 16:
-        hipLaunchKernelGGL(k_part_summary<16>, grid, dim3(64), 0, s, fwd, bwd, n, F, batch, ld, summ, summ_ld);
-        break;
-    case 32:
-        hipLaunchKernelGGL(k_part_summary<32>, grid, dim3(64), 0, s, fwd, bwd, n, F, batch, ld, summ, summ_ld);
-        break;
-    case 64:
-        hipLaunchKernelGGL(k_part_summary<64>, grid, dim3(64), 0, s, fwd, bwd, n, F, batch, ld, summ, summ_ld);
-        break;
-    default:
-        return hipErrorInvalidValue;
-    }
+    hipLaunchKernelGGL((k_part_summary<K, TI>), grid, dim3(64), 0, s, fwd, bwd, n, npad, Fin, batch,
+                       ldf, summ, summ_ld);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     hipLaunchKernelGGL(k_part_chain, gridc, dim3(256), 0, s, seg, nseg, summ, summ_ld, batch);
     err = hipGetLastError();
     if (err != hipSuccess) return err;
-    switch (seg_rows) {
-    case 16:
-        hipLaunchKernelGGL(k_part_final<16>, grid, dim3(64), 0, s, fwd, bwd, n, F, batch, ld, summ, summ_ld);
-        break;
-    case 32:
-        hipLaunchKernelGGL(k_part_final<32>, grid, dim3(64), 0, s, fwd, bwd, n, F, batch, ld, summ, summ_ld);
-        break;
-    default:
-        hipLaunchKernelGGL(k_part_final<64>, grid, dim3(64), 0, s, fwd, bwd, n, F, batch, ld, summ, summ_ld);
-        break;
-    }
+    hipLaunchKernelGGL((k_part_final<K, TI>), grid, dim3(64), 0, s, fwd, bwd, n, npad, Fin, ldf, X,
+                       ldx, batch, summ, summ_ld);
     return hipGetLastError();
+}
+
+hipError_t launch_part_sweep_io(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg,
+                                int64_t n, int64_t npad, int seg_rows, const void *Fin, bool f32,
+                                int64_t ldf, double *X, int64_t ldx, int64_t batch, double *summ,
+                                int64_t summ_ld, hipStream_t s)
+{
+#define PENT_PART(KK)                                                                              \
+    return f32 ? part_sweep_k<KK, float>(fwd, bwd, seg, n, npad, (const float *)Fin, ldf, X, ldx, \
+                                         batch, summ, summ_ld, s)                                  \
+               : part_sweep_k<KK, double>(fwd, bwd, seg, n, npad, (const double *)Fin, ldf, X,    \
+                                          ldx, batch, summ, summ_ld, s)
+    switch (seg_rows) {
+    case 16: PENT_PART(16);
+    case 32: PENT_PART(32);
+    case 64: PENT_PART(64);
+    default: return hipErrorInvalidValue;
+    }
+#undef PENT_PART
+}
+
+hipError_t launch_part_sweep(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg,
+                             int64_t n, int64_t npad, int seg_rows, double *F, int64_t batch,
+                             int64_t ld, double *summ, int64_t summ_ld, hipStream_t s)
+{
+    return launch_part_sweep_io(fwd, bwd, seg, n, npad, seg_rows, F, false, ld, F, ld, batch,
+                                summ, summ_ld, s);
 }
 
 hipError_t launch_strided_sweep(const FwdRec *fwd, const BwdRec *bwd, int64_t n, double *F,

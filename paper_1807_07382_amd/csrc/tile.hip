@@ -59,11 +59,13 @@ constexpr int tile_lds_bytes()
     return K == 64 ? 5 * kTileSeg * K * 8 : 5 * kTileSeg * K * 8 + 4 * kTileW * kTileSeg * 8;
 }
 
-template <int K>
+// f is read with type TI (leading dimension ldf), x written as FP64 (ldx);
+// x may be f itself when TI is double and ldx == ldf.
+template <int K, typename TI>
 __global__ __launch_bounds__(kTileThreads) void k_tile(const double *__restrict__ trec,
                                                       const ScanRec *__restrict__ scan, int n,
-                                                      double *__restrict__ F, int64_t batch,
-                                                      int64_t ld, int64_t ntiles)
+                                                      const TI *Fin, int64_t ldf, double *X,
+                                                      int64_t ldx, int64_t batch, int64_t ntiles)
 {
     extern __shared__ double lds[];
     constexpr int C = kTileSeg * K;  // doubles per record component
@@ -84,17 +86,18 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const double *__restrict_
     const int r0 = s * K;
     const int L = max(0, min(K, n - r0));
     const bool full = act && L == K;
-    // lane base: row r0 of system j (rows past n / systems past the batch are
-    // never dereferenced)
-    double *base = F + (act ? j : 0) + (int64_t)(L > 0 ? r0 : 0) * ld;
+    // lane bases: row r0 of system j (rows past n / systems past the batch
+    // are never dereferenced)
+    const int64_t roff = (int64_t)(L > 0 ? r0 : 0);
+    const TI *fbase = Fin + (act ? j : 0) + roff * ldf;
 
     double v[K];
     if (full) {
 #pragma unroll
-        for (int k = 0; k < K; k++) v[k] = __builtin_nontemporal_load(base + k * ld);
+        for (int k = 0; k < K; k++) v[k] = (double)__builtin_nontemporal_load(fbase + k * ldf);
     } else {
 #pragma unroll
-        for (int k = 0; k < K; k++) v[k] = (act && k < L) ? base[k * ld] : 0.0;
+        for (int k = 0; k < K; k++) v[k] = (act && k < L) ? (double)fbase[k * ldf] : 0.0;
     }
     // stage the records into LDS: 1 KB per wave per instruction, straight
     // from global memory (no VGPRs)
@@ -209,13 +212,14 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(const double *__restrict_
         q1 = x;
         if (k % kFence == 0) __builtin_amdgcn_sched_barrier(0);
     }
+    double *base = X + (act ? j : 0) + roff * ldx;
     if (full) {
 #pragma unroll
-        for (int k = 0; k < K; k++) __builtin_nontemporal_store(v[k], base + k * ld);
+        for (int k = 0; k < K; k++) __builtin_nontemporal_store(v[k], base + k * ldx);
     } else if (act) {
 #pragma unroll
         for (int k = 0; k < K; k++)
-            if (k < L) base[k * ld] = v[k];
+            if (k < L) base[k * ldx] = v[k];
     }
 }
 
@@ -314,35 +318,46 @@ hipError_t launch_tile_recs(const FwdRec *fwd, const BwdRec *bwd, int rows, doub
 }
 
 namespace {
-template <int K>
-hipError_t launch_tile_k(const double *trec, const ScanRec *scan, int64_t n, double *F,
-                         int64_t batch, int64_t ld, hipStream_t s)
+template <int K, typename TI>
+hipError_t launch_tile_k(const double *trec, const ScanRec *scan, int64_t n, const TI *Fin,
+                         int64_t ldf, double *X, int64_t ldx, int64_t batch, hipStream_t s)
 {
     static bool attr_set = false;  // benign race: the attribute value is the same
     constexpr int lds = tile_lds_bytes<K>();
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_tile<K>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_tile<K, TI>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     const int64_t ntiles = (batch + kTileW - 1) / kTileW;
     const int64_t nblocks = (ntiles + 15) / 16 * 16;
-    hipLaunchKernelGGL(k_tile<K>, dim3((unsigned)nblocks), dim3(kTileThreads), lds, s, trec, scan,
-                       (int)n, F, batch, ld, ntiles);
+    hipLaunchKernelGGL((k_tile<K, TI>), dim3((unsigned)nblocks), dim3(kTileThreads), lds, s, trec,
+                       scan, (int)n, Fin, ldf, X, ldx, batch, ntiles);
     return hipGetLastError();
 }
 }  // namespace
 
+hipError_t launch_tile_sweep_io(const double *trec, const ScanRec *scan, int64_t n, int rows,
+                                const void *Fin, bool f32, int64_t ldf, double *X, int64_t ldx,
+                                int64_t batch, hipStream_t s)
+{
+#define PENT_TILE(KK)                                                                              \
+    return f32 ? launch_tile_k<KK, float>(trec, scan, n, (const float *)Fin, ldf, X, ldx, batch, s) \
+               : launch_tile_k<KK, double>(trec, scan, n, (const double *)Fin, ldf, X, ldx, batch, s)
+    switch (rows) {
+    case 16: PENT_TILE(16);
+    case 32: PENT_TILE(32);
+    case 64: PENT_TILE(64);
+    default: return hipErrorInvalidValue;
+    }
+#undef PENT_TILE
+}
+
 hipError_t launch_tile_sweep(const double *trec, const ScanRec *scan, int64_t n, int rows,
                              double *F, int64_t batch, int64_t ld, hipStream_t s)
 {
-    switch (rows) {
-    case 16: return launch_tile_k<16>(trec, scan, n, F, batch, ld, s);
-    case 32: return launch_tile_k<32>(trec, scan, n, F, batch, ld, s);
-    case 64: return launch_tile_k<64>(trec, scan, n, F, batch, ld, s);
-    default: return hipErrorInvalidValue;
-    }
+    return launch_tile_sweep_io(trec, scan, n, rows, F, false, ld, F, ld, batch, s);
 }
 
 }  // namespace pent

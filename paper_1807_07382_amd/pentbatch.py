@@ -36,6 +36,9 @@ SIGNATURES = {
     "pent_destroy": (_I, [_P]),
     "pent_solve": (_I, [_P, _P, _I64, _I64, _P]),
     "pent_solve_strided": (_I, [_P, _P, _I64, _I64, _P]),
+    "pent_solve_mixed": (_I, [_P, _P, _I, _I64, _P, _I64, _I64, _I, _P, _P, ctypes.c_size_t, _P]),
+    "pent_mixed_workspace_size": (ctypes.c_size_t, [_P, _I64, _I, _I]),
+    "pent_backward_error": (_I, [_P, _P, _I, _I64, _P, _I64, _I64, _P, _P, ctypes.c_size_t, _P]),
     "pent_get_factors": (_I, [_P, _P, _P, _P, _P]),
     "pent_get_diagonals": (_I, [_P, _P, _P, _P, _P, _P]),
     "pent_size": (_I64, [_P]),
@@ -177,6 +180,49 @@ class Plan:
                                         max(F.stride(0), self.n), _stream_ptr(stream)),
                "solve_strided")
         return F
+
+    def solve_mixed(self, F, X, refine_steps: int = 0, eta=None, work=None, stream=None):
+        """X (cuda float64, shape (n, batch)) = A^{-1} F with F cuda float32 or
+        float64 of the same shape; FP64 arithmetic, ``refine_steps``
+        compensated-residual corrections, optional per-system backward error
+        into ``eta`` (cuda float64, shape (batch,)).  ``work`` is allocated
+        with torch when not given."""
+        import torch
+        if F.dim() != 2 or F.shape[0] != self.n or X.shape != F.shape:
+            raise ValueError(f"F and X must have shape ({self.n}, batch)")
+        m = F.shape[1]
+        for t in (F, X):
+            if m > 1 and t.stride(1) != 1:
+                raise ValueError("unit batch stride required")
+        fdt = {torch.float32: 1, torch.float64: 0}.get(F.dtype)
+        if fdt is None:
+            raise ValueError("F must be float32 or float64")
+        nbytes = lib().pent_mixed_workspace_size(self._h, m, int(refine_steps), int(eta is not None))
+        if work is None and nbytes:
+            work = torch.empty(nbytes, dtype=torch.uint8, device=F.device)
+        wptr = work.data_ptr() if work is not None else None
+        wlen = work.numel() * work.element_size() if work is not None else 0
+        if eta is not None and (eta.dtype != torch.float64 or eta.numel() < m):
+            raise ValueError("eta must be float64 with batch elements")
+        _check(lib().pent_solve_mixed(self._h, F.data_ptr(), fdt, max(F.stride(0), m),
+                                      _dptr(X, "float64"), max(X.stride(0), m), m,
+                                      int(refine_steps), eta.data_ptr() if eta is not None else None,
+                                      wptr, wlen, _stream_ptr(stream)), "solve_mixed")
+        return X
+
+    def backward_error(self, F, X, eta, work=None, stream=None):
+        """eta[j] = ||F_j - A X_j||_inf / (||A||_inf ||X_j||_inf + ||F_j||_inf),
+        residual evaluated compensated on the device."""
+        import torch
+        m = F.shape[1]
+        fdt = {torch.float32: 1, torch.float64: 0}[F.dtype]
+        if work is None:
+            work = torch.empty(24 * max(m, 1), dtype=torch.uint8, device=F.device)
+        _check(lib().pent_backward_error(self._h, F.data_ptr(), fdt, max(F.stride(0), m),
+                                         _dptr(X, "float64"), max(X.stride(0), m), m,
+                                         eta.data_ptr(), work.data_ptr(), work.numel(),
+                                         _stream_ptr(stream)), "backward_error")
+        return eta
 
     # -- inspection ----------------------------------------------------------
     def factors(self):

@@ -1,0 +1,144 @@
+"""GPU tests of the precision extension (pent_solve_mixed, pent_backward_error)
+against the FP64 path and the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1807_07382_amd import inputs
+from paper_1807_07382_amd import pentbatch as pb
+from tests._gpu import colerr, d4_tol, print_case, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+SCHEDULES = [(0, 0), (1, 0), (2, 16), (2, 32), (2, 64), (3, 0)]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return torch_dev()
+
+
+def f32_rhs(n, m, seed):
+    return np.random.Generator(np.random.PCG64(seed)).uniform(-1, 1, (n, m)).astype(np.float32)
+
+
+@pytest.mark.parametrize("kind,seg", SCHEDULES)
+@pytest.mark.parametrize("n,m", [(300, 130), (1000, 64), (4096, 77), (37, 5)])
+def test_fp32_stream_equals_fp64_path_bitwise(torch, kind, seg, n, m):
+    """FP32 f with FP64 arithmetic is the FP64 solve of the widened values,
+    bit for bit (same kernels, same operations)."""
+    print_case(test="mixed_bitwise", kind=kind, seg=seg, n=n, m=m)
+    f32 = f32_rhs(n, m, n + m)
+    with pb.Plan.factor_d4(n, 200.0) as p:
+        p.set_schedule(kind, seg)
+        F = torch.from_numpy(f32).cuda()
+        X = torch.empty((n, m), dtype=torch.float64, device="cuda")
+        p.solve_mixed(F, X)
+        Y = F.double()
+        if kind == 1:
+            p.set_schedule(2, 64)   # the lane schedule maps to partitioned out of place
+        p.solve_(Y)
+        torch.cuda.synchronize()
+        assert torch.equal(X, Y)
+
+
+@pytest.mark.parametrize("sigma", [1.0, 1e2, 1e4])
+@pytest.mark.parametrize("refine", [0, 1, 2])
+def test_mixed_against_oracle(torch, sigma, refine):
+    n, m = 2000, 300
+    print_case(test="mixed_oracle", sigma=sigma, refine=refine)
+    f32 = f32_rhs(n, m, 4)
+    dg = oracle.assemble_d4(n, sigma)
+    ref = oracle.solve(dg, f32.astype(np.float64))
+    with pb.Plan.factor_d4(n, sigma) as p:
+        F = torch.from_numpy(f32).cuda()
+        X = torch.empty((n, m), dtype=torch.float64, device="cuda")
+        eta = torch.empty(m, dtype=torch.float64, device="cuda")
+        p.solve_mixed(F, X, refine_steps=refine, eta=eta)
+        torch.cuda.synchronize()
+    Xh = X.cpu().numpy()
+    assert np.all(colerr(Xh, ref) <= d4_tol(sigma))
+    eta_ref, _ = oracle.residual(dg, Xh, f32.astype(np.float64))
+    eta_dev = eta.cpu().numpy()
+    assert np.all(eta_dev <= 1e-12) and np.all(eta_ref <= 1e-12)
+    assert np.allclose(eta_dev, eta_ref, rtol=1e-6, atol=1e-30)
+
+
+def test_backward_error_of_perturbed_solution(torch):
+    """pent_backward_error sees a planted perturbation of x (the oracle's
+    evaluator gives the same number)."""
+    n, m = 500, 70
+    dg = oracle.assemble_d4(n, 50.0)
+    f = np.random.Generator(np.random.PCG64(8)).uniform(-1, 1, (n, m))
+    x = oracle.solve(dg, f)
+    x[17, 5] += 1e-6
+    eta_ref, _ = oracle.residual(dg, x, f)
+    with pb.Plan.factor_d4(n, 50.0) as p:
+        eta = torch.empty(m, dtype=torch.float64, device="cuda")
+        p.backward_error(torch.from_numpy(f).cuda(), torch.from_numpy(x).cuda(), eta)
+        torch.cuda.synchronize()
+    e = eta.cpu().numpy()
+    assert e[5] > 1e-9
+    assert np.allclose(e, eta_ref, rtol=1e-6, atol=1e-30)
+
+
+def test_mixed_in_place_fp64(torch):
+    n, m = 700, 90
+    f = np.random.Generator(np.random.PCG64(9)).uniform(-1, 1, (n, m))
+    with pb.Plan.factor_d4(n, 3.0) as p:
+        T = torch.from_numpy(f).cuda()
+        ref = T.clone()
+        p.solve_(ref)
+        p.solve_mixed(T, T)
+        torch.cuda.synchronize()
+        assert torch.equal(T, ref)
+
+
+def test_mixed_argument_errors(torch):
+    n, m = 64, 16
+    with pb.Plan.factor_d4(n, 1.0) as p:
+        L = pb.lib()
+        F = torch.zeros((n, m), dtype=torch.float32, device="cuda")
+        F64 = torch.zeros((n, m), dtype=torch.float64, device="cuda")
+        X = torch.zeros((n, m), dtype=torch.float64, device="cuda")
+        h = p.handle
+        # aliasing with FP32 input or with refinement is refused
+        assert L.pent_solve_mixed(h, X.data_ptr(), 1, m, X.data_ptr(), m, m, 0, None, None, 0,
+                                  None) == pb.INVALID_VALUE
+        need = L.pent_mixed_workspace_size(h, m, 1, 0)
+        assert need > 0
+        assert L.pent_solve_mixed(h, F64.data_ptr(), 0, m, F64.data_ptr(), m, m, 1, None, None, 0,
+                                  None) == pb.INVALID_VALUE
+        W = torch.zeros(need - 8, dtype=torch.uint8, device="cuda")
+        assert L.pent_solve_mixed(h, F.data_ptr(), 1, m, X.data_ptr(), m, m, 1, None,
+                                  W.data_ptr(), need - 8, None) == pb.SIZE_MISMATCH
+        assert L.pent_solve_mixed(h, F.data_ptr(), 7, m, X.data_ptr(), m, m, 0, None, None, 0,
+                                  None) == pb.INVALID_VALUE
+        assert L.pent_solve_mixed(h, F.data_ptr(), 1, m - 1, X.data_ptr(), m, m, 0, None, None, 0,
+                                  None) == pb.INVALID_VALUE
+        assert L.pent_solve_mixed(h, F.data_ptr(), 1, m, X.data_ptr(), m, m, 17, None, None, 0,
+                                  None) == pb.INVALID_VALUE
+        assert L.pent_solve_mixed(h, None, 1, m, None, m, 0, 0, None, None, 0, None) == pb.OK
+
+
+def test_precision_workload_full_size_sampled(torch):
+    """N=8192, 131072 FP32 right-hand sides (the full precision workload), at
+    sigma in {1, 1e2, 1e4}: 64 sampled systems against the oracle, and the
+    device backward error of every system below 1e-12."""
+    w = inputs.precision()
+    f32 = w["F32"]
+    n, m = f32.shape
+    cols = np.concatenate([np.random.Generator(np.random.PCG64(5)).choice(m, 60, replace=False),
+                           [0, 63, 64, m - 1]])
+    F = torch.from_numpy(f32).cuda()
+    X = torch.empty((n, m), dtype=torch.float64, device="cuda")
+    eta = torch.empty(m, dtype=torch.float64, device="cuda")
+    for sigma in inputs.PRECISION["sigmas"]:
+        print_case(test="precision_full", sigma=sigma)
+        with pb.Plan.factor_d4(n, sigma) as p:
+            p.solve_mixed(F, X, eta=eta)
+            torch.cuda.synchronize()
+        assert float(eta.max()) <= 1e-12
+        Xs = X[:, torch.from_numpy(cols).cuda()].cpu().numpy()
+        ref = oracle.solve(oracle.assemble_d4(n, sigma), f32[:, cols].astype(np.float64))
+        assert np.all(colerr(Xs, ref) <= d4_tol(sigma))
