@@ -8,7 +8,12 @@ seed 2), factor once, every step solves A C^{k+1} = C^k in place.  A step is
 one full solve of all 65536 systems; inputs are resident in HBM before the
 timed region.  Prints one JSON line.
 
-Other workloads (for tuning runs): ``plain`` (N=256, 256 RHS).
+The same line carries a ``precision`` object: FP64 sweeps against FP32
+right-hand-side streams (FP64 arithmetic, with 0 and 1 refinement steps) on
+N=8192 with 131072 right-hand sides, sigma=1e2.
+
+Other workloads (for tuning runs): ``plain`` (N=256, 256 RHS), ``precision``
+(all three sigma), ``shape`` (any n / batch), ``copy`` (device copy).
 """
 from __future__ import annotations
 
@@ -29,26 +34,31 @@ PEAK_HBM_GBS = 8000.0
 BYTES_PER_UNKNOWN_FP64 = 16  # read f once, write x once
 
 
-def kernel_source_hash() -> str:
-    h = hashlib.sha256()
-    for name in sorted(os.listdir(os.path.join(ROOT, "paper_1807_07382_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_1807_07382_amd", "csrc", name), "rb") as fh:
-            h.update(name.encode())
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+SCHEDULE_NAMES = {1: "lane", 2: "partitioned", 3: "tile"}
+
+
+# kernel source file of each schedule (the counters go stale when it changes)
+SCHEDULE_SOURCES = {"lane": "sweep.hip", "partitioned": "sweep.hip", "tile": "tile.hip"}
+
+
+def kernel_source_hash(name: str) -> str:
+    with open(os.path.join(ROOT, "paper_1807_07382_amd", "csrc", name), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
 def traffic_for(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel sources; else None."""
+    """HBM bytes moved by one step (all kernels of one solve) from the
+    committed rocprofv3 counter summary, if it was taken on the current kernel
+    sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh).get(f"{kernel}@{workload}")
-    if not rec or rec.get("source_hash") != kernel_source_hash():
+    base = "".join(c for c in kernel if not c.isdigit())
+    if not rec or rec.get("source_hash") != kernel_source_hash(SCHEDULE_SOURCES[base]):
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("bytes_per_step")
 
 
 def cpu_baseline_hyperdiff(n, sigma, C0, budget_s=12.0):
@@ -95,6 +105,7 @@ def run_hyperdiff(args, torch):
     if args.schedule:
         kind, seg = (int(x) for x in args.schedule.split(","))
         plan.set_schedule(kind, seg)
+    sched = plan.schedule_for(batch)
     for _ in range(args.warmup):
         plan.solve_(T, stream)
     torch.cuda.synchronize()
@@ -115,15 +126,15 @@ def run_hyperdiff(args, torch):
     solves_s = batch * args.steps / (ms / 1e3)
     alg_bytes = BYTES_PER_UNKNOWN_FP64 * n * batch
     achieved = alg_bytes / (ms_step / 1e3) / 1e9
-    kname = "k_lane" if (not args.schedule or args.schedule.startswith("1")) else "k_part"
-    tr = traffic_for(kname, "hyperdiff")
+    sched_name = SCHEDULE_NAMES[sched[0]] + (f"{sched[1]}" if sched[0] == 2 else "")
+    tr = traffic_for(sched_name, "hyperdiff")
     out = dict(
         metric=METRIC, value=solves_s, unit="RHS-solves/s", n_gpus=1, steps=args.steps,
         warmup=args.warmup, ms_per_step=ms_step, higher_is_better=True, scaling="weak",
         vs_baseline=None, dtype="f64", data="synthetic",
         config=dict(workload="hyperdiff", n=n, systems=batch, sigma=sigma,
                     implicit_steps=args.steps, layout="interleaved (batch-fastest)",
-                    parallelism="single GPU"),
+                    parallelism="single GPU", schedule=sched_name),
         roofline=dict(bound="hbm", achieved=achieved, peak=PEAK_HBM_GBS, unit="GB/s",
                       frac=achieved / PEAK_HBM_GBS,
                       traffic=tr),
@@ -131,9 +142,90 @@ def run_hyperdiff(args, torch):
         factor_ms=fac_s * 1e3,
         parity=dict(probe_systems=len(probe), max_rel_err_vs_oracle=err),
     )
+    if not args.no_precision:
+        del T
+        torch.cuda.empty_cache()
+        out["precision"] = precision_compare(torch, 1e2)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_hyperdiff(n, sigma, C0)
     return out
+
+
+def _timed(torch, stream, fn, reps):
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(reps):
+        fn()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps
+
+
+def precision_compare(torch, sigma, reps=10, seed=4):
+    """FP64 sweeps against FP32 right-hand-side streams (FP64 arithmetic,
+    0 and 1 refinement steps) on the precision workload: N=8192, 131072
+    right-hand sides uniform[-1, 1) rounded to FP32 (drawn on the device from
+    a seeded generator).  Reports solves/s, bytes per unknown moved by the
+    partitioned schedule, the largest device backward error and the largest
+    error against the oracle on sampled systems."""
+    from paper_1807_07382_amd import inputs
+    from paper_1807_07382_amd import pentbatch as pb
+    import oracle
+    n, m = inputs.PRECISION["n"], inputs.PRECISION["batch"]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    F64src = torch.empty((n, m), dtype=torch.float64, device="cuda").uniform_(-1, 1, generator=g)
+    F32 = F64src.float()
+    del F64src
+    F64 = F32.double()
+    X = torch.empty((n, m), dtype=torch.float64, device="cuda")
+    eta = torch.empty(m, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    cols = torch.arange(0, m, m // 16, device="cuda")
+    f_sample = F32[:, cols].double().cpu().numpy()
+    ref = oracle.solve(oracle.assemble_d4(n, sigma), f_sample)
+    out = dict(workload="precision", n=n, systems=m, sigma=sigma)
+    with pb.Plan.factor_d4(n, sigma) as plan:
+        nbytes = pb.lib().pent_mixed_workspace_size(plan.handle, m, 1, 1)
+        work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+
+        def rel_err(T):
+            Xs = T[:, cols].cpu().numpy()
+            return float(np.max(np.max(np.abs(Xs - ref), axis=0) / np.max(np.abs(ref), axis=0)))
+
+        # FP64: out-of-place solve X = A^{-1} F64 (copy + in-place solve would add a pass)
+        ms64 = _timed(torch, stream, lambda: plan.solve_mixed(F64, X, work=work, stream=stream), reps)
+        plan.solve_mixed(F64, X, eta=eta, work=work, stream=stream)
+        torch.cuda.synchronize()
+        out["fp64"] = dict(ms=ms64, solves_per_s=m / (ms64 / 1e3), bytes_per_unknown=24,
+                           max_eta=float(eta.max()), max_rel_err_vs_oracle=rel_err(X))
+        for k in (0, 1):
+            ms = _timed(torch, stream,
+                        lambda: plan.solve_mixed(F32, X, refine_steps=k, work=work, stream=stream),
+                        reps)
+            plan.solve_mixed(F32, X, refine_steps=k, eta=eta, work=work, stream=stream)
+            torch.cuda.synchronize()
+            out[f"fp32_stream_refine{k}"] = dict(
+                ms=ms, solves_per_s=m / (ms / 1e3), bytes_per_unknown=16 if k == 0 else 84,
+                max_eta=float(eta.max()), max_rel_err_vs_oracle=rel_err(X),
+                speedup_vs_fp64=ms64 / ms)
+    del F32, F64, X, work
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_precision(args, torch):
+    from paper_1807_07382_amd import inputs
+    res = [precision_compare(torch, s) for s in inputs.PRECISION["sigmas"]]
+    best = res[1]["fp32_stream_refine0"]
+    return dict(metric=METRIC, value=best["solves_per_s"], unit="RHS-solves/s", n_gpus=1,
+                steps=10, warmup=0, ms_per_step=best["ms"], higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype="f32-stream/f64", data="synthetic",
+                config=dict(workload="precision", n=inputs.PRECISION["n"],
+                            systems=inputs.PRECISION["batch"]),
+                per_sigma=res)
 
 
 def run_plain(args, torch):
@@ -229,7 +321,7 @@ def run_shape(args, torch):
 
 
 WORKLOADS = {"hyperdiff": run_hyperdiff, "plain": run_plain, "copy": run_copy,
-             "shape": run_shape}
+             "shape": run_shape, "precision": run_precision}
 
 
 def main(argv=None):
@@ -240,6 +332,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="hyperdiff", choices=sorted(WORKLOADS))
     ap.add_argument("--schedule", default="", help="force kind,seg_rows (tuning)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the FP32-stream vs FP64 comparison object")
     ap.add_argument("--n", type=int, default=1024, help="shape workload: rows")
     ap.add_argument("--batch", type=int, default=32768, help="shape workload: systems")
     ap.add_argument("--sigma", type=float, default=200.0, help="shape workload: sigma")

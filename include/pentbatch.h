@@ -154,6 +154,10 @@ int64_t pent_size(pent_handle h); /* n, or -1 for a bad handle */
  * Returns PENT_INVALID_VALUE for an unknown kind or seg_rows. */
 int pent_set_schedule(pent_handle h, int kind, int seg_rows);
 
+/* The schedule pent_solve would use for `batch` systems on this handle
+ * (kind as above, seg_rows 0 unless kind is 2).  Host-only, no HIP call. */
+int pent_query_schedule(pent_handle h, int64_t batch, int *kind, int *seg_rows);
+
 /* --------------------------------------------------------------- status -- */
 int pent_last_status(void);
 int64_t pent_last_pivot_row(void); /* row of the last PENT_ZERO_PIVOT, else -1 */

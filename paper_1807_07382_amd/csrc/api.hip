@@ -482,6 +482,15 @@ int pent_set_schedule(pent_handle h, int kind, int seg_rows)
     return ret(PENT_INVALID_VALUE);
 }
 
+int pent_query_schedule(pent_handle h, int64_t batch, int *kind, int *seg_rows)
+{
+    if (!valid(h) || batch < 0 || !kind || !seg_rows) return ret(PENT_INVALID_VALUE);
+    choose_schedule(h, batch, kind, seg_rows);
+    if (*kind == 2 && (h->n + *seg_rows - 1) / *seg_rows > 65535) *kind = 1;
+    if (*kind != 2) *seg_rows = 0;
+    return ret(PENT_OK);
+}
+
 int pent_last_status(void) { return g_status; }
 
 int64_t pent_last_pivot_row(void) { return g_pivot_row; }

@@ -43,6 +43,7 @@ SIGNATURES = {
     "pent_get_diagonals": (_I, [_P, _P, _P, _P, _P, _P]),
     "pent_size": (_I64, [_P]),
     "pent_set_schedule": (_I, [_P, _I, _I]),
+    "pent_query_schedule": (_I, [_P, _I64, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "pent_last_status": (_I, []),
     "pent_last_pivot_row": (_I64, []),
     "pent_status_string": (ctypes.c_char_p, [_I]),
@@ -236,6 +237,13 @@ class Plan:
         out = [np.empty(self.n) for _ in range(5)]
         _check(lib().pent_get_diagonals(self._h, *[x.ctypes.data for x in out]), "get_diagonals")
         return tuple(out)
+
+    def schedule_for(self, batch: int):
+        """(kind, seg_rows) pent_solve uses for ``batch`` systems."""
+        k, sr = _I(0), _I(0)
+        _check(lib().pent_query_schedule(self._h, int(batch), ctypes.byref(k), ctypes.byref(sr)),
+               "query_schedule")
+        return int(k.value), int(sr.value)
 
     def set_schedule(self, kind: int, seg_rows: int = 0):
         _check(lib().pent_set_schedule(self._h, int(kind), int(seg_rows)), "set_schedule")
