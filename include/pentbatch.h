@@ -133,6 +133,48 @@ int pent_backward_error(pent_handle h, const void *f, int f_dtype, int64_t ld_f,
                         int64_t ld_x, int64_t batch, double *eta_out, void *work,
                         size_t work_bytes, void *stream);
 
+/* -------------------------------------------------- batching extension --
+ * Many matrices of uneven size, each with its own block of right-hand sides,
+ * solved in ONE persistent kernel launch (the paper's batch is one matrix,
+ * Sec. 2.6; a group extends it to a parameter study with several operators). */
+typedef struct pent_group_s *pent_group;
+
+/* Make a group of `count` factored handles (HOST array; the handles must stay
+ * alive while the group exists).  Blocking.  NULL on error (pent_last_status). */
+pent_group pent_group_create(const pent_handle *hs, int64_t count);
+
+/* Scratch the group solves need for these right-hand-side counts (HOST array
+ * batch[count]); 0 on error. */
+size_t pent_group_workspace_size(pent_group g, const int64_t *batch);
+
+/* Solve every matrix k on its own block: F[k] (DEVICE pointer, FP64,
+ * batch-fastest, element (i, j) at F[k][i*ld[k] + j]) is overwritten with
+ * A_k^{-1} F[k].  F, batch and ld are HOST arrays of `count` entries.
+ * mode 0: one persistent launch for all matrices, work items of (matrix,
+ *         64 consecutive systems) taken longest first from a device counter;
+ * mode 1: one solve per matrix (the library's single-matrix schedules, one
+ *         after the other on `stream`), the baseline the persistent launch
+ *         is compared with.
+ * work: DEVICE scratch of at least pent_group_workspace_size() bytes.
+ * The buffer table is uploaded (blocking) only when F/batch/ld differ from
+ * the previous call, so repeated calls with the same buffers only enqueue
+ * kernels and may be captured into a graph.  Calls on one group must not
+ * overlap in time (they share the group's work counter). */
+int pent_group_solve(pent_group g, double *const *F, const int64_t *batch, const int64_t *ld,
+                     int mode, void *work, size_t work_bytes, void *stream);
+int pent_group_destroy(pent_group g); /* NULL is a no-op */
+
+/* Capture `steps` consecutive group solves (mode as above) on `stream` into
+ * an executable HIP graph (one graph launch = `steps` implicit time steps).
+ * `stream` must be a created stream (not the null stream).  The buffers are
+ * bound first, outside the capture.  NULL on error. */
+typedef struct pent_graph_s *pent_graph;
+pent_graph pent_group_capture(pent_group g, double *const *F, const int64_t *batch,
+                              const int64_t *ld, int mode, int steps, void *work,
+                              size_t work_bytes, void *stream);
+int pent_graph_launch(pent_graph gr, void *stream);
+int pent_graph_destroy(pent_graph gr); /* NULL is a no-op */
+
 /* ----------------------------------------------------------- inspection --
  * Copy the handle's data to HOST arrays of n doubles each (blocking).
  * pent_get_factors: alpha, beta, gamma, delta of Sec. 2.4 (epsilon = a).

@@ -136,7 +136,9 @@ def factor(diags: Diagonals) -> Factors:
 def _check_F(F: np.ndarray, n: int):
     if F.dtype != np.float64 or F.ndim != 2 or F.shape[0] != n:
         raise ValueError(f"F must be float64 of shape ({n}, batch), got {F.dtype} {F.shape}")
-    if F.strides[1] != 8 or F.strides[0] % 8:
+    if F.shape[1] == 0:
+        return 0
+    if (F.shape[1] > 1 and F.strides[1] != 8) or F.strides[0] % 8:
         raise ValueError("F must have unit stride along the batch axis")
     return F.strides[0] // 8
 

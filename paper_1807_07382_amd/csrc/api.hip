@@ -1,5 +1,6 @@
 // api.hip -- the C ABI of libpentbatch (declared in include/pentbatch.h):
 // argument checks, handle lifetime, schedule choice and kernel launches.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -246,6 +247,164 @@ constexpr int kMaxRefine = 16;
 
 }  // namespace
 
+struct pent_group_s {
+    uint64_t magic = 0;
+    int device = 0;
+    std::vector<pent_plan *> plans;
+    // bound buffers (host copies, to detect changes)
+    bool bound = false;
+    std::vector<double *> F;
+    std::vector<int64_t> batch, ld;
+    GroupMat *d_mats = nullptr;
+    GroupItem *d_items = nullptr;
+    int nitems = 0;
+    int64_t summ_doubles = 0;
+    unsigned int *d_ctr = nullptr;  // [next item, workgroups done]
+    int nblocks = 0;
+};
+
+struct pent_graph_s {
+    uint64_t magic = 0;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+constexpr uint64_t kGroupMagic = 0x70656e7467727075ull;
+constexpr uint64_t kGraphMagic = 0x70656e7467726166ull;
+
+bool gvalid(pent_group g) { return g && g->magic == kGroupMagic; }
+
+void free_group(pent_group g)
+{
+    if (!g) return;
+    if (g->d_mats) (void)hipFree(g->d_mats);
+    if (g->d_items) (void)hipFree(g->d_items);
+    if (g->d_ctr) (void)hipFree(g->d_ctr);
+    g->magic = 0;
+    delete g;
+}
+
+// Workspace of the persistent solve for these counts (doubles of summaries).
+int64_t group_summ_doubles(const pent_group g, const int64_t *batch)
+{
+    int64_t tot = 0;
+    const int K = group_seg_rows();
+    for (size_t k = 0; k < g->plans.size(); k++) {
+        const int64_t nseg = (g->plans[k]->n + K - 1) / K;
+        tot += (batch[k] + 63) / 64 * nseg * 256;
+    }
+    return tot;
+}
+
+size_t group_ws_bytes(const pent_group g, const int64_t *batch)
+{
+    size_t b = align256(sizeof(double) * (size_t)group_summ_doubles(g, batch));
+    for (size_t k = 0; k < g->plans.size(); k++) {
+        int kind, seg_rows;
+        io_schedule(g->plans[k], batch[k], true, &kind, &seg_rows);
+        b = std::max(b, summ_bytes(g->plans[k], kind, seg_rows, batch[k]));
+    }
+    return b;
+}
+
+// Upload the buffer table and the sorted work list if anything changed.
+// Blocking; also builds every per-matrix cache a later solve could need, so
+// the solves themselves never synchronise (graph capture).
+int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64_t *ld)
+{
+    const size_t cnt = g->plans.size();
+    bool same = g->bound;
+    for (size_t k = 0; same && k < cnt; k++)
+        same = g->F[k] == F[k] && g->batch[k] == batch[k] && g->ld[k] == ld[k];
+    if (same) return PENT_OK;
+    std::vector<GroupMat> mats(cnt);
+    std::vector<GroupItem> items;
+    int st;
+    const int K = group_seg_rows();
+    for (size_t k = 0; k < cnt; k++) {
+        pent_plan *p = g->plans[k];
+        const SegRec *seg = seg_cache(p, K, &st);
+        if (!seg) return st;
+        int kind, seg_rows;
+        io_schedule(p, batch[k], true, &kind, &seg_rows);
+        if (kind == 2 && !seg_cache(p, seg_rows, &st)) return st;
+        if (kind == 3) {
+            const ScanRec *sc;
+            const double *tr;
+            if (!tile_cache(p, tile_rows_for(p->n), &sc, &tr, &st)) return st;
+        }
+        mats[k] = GroupMat{p->d_fwd, p->d_bwd, seg, F[k], p->n, p->npad, ld[k], batch[k]};
+    }
+    for (size_t k = 0; k < cnt; k++)
+        for (int64_t c0 = 0; c0 < batch[k]; c0 += 64)
+            items.push_back(GroupItem{(int)k, (int)std::min<int64_t>(64, batch[k] - c0), c0, 0});
+    // longest first: rows x systems of the item
+    std::stable_sort(items.begin(), items.end(), [&](const GroupItem &a, const GroupItem &b) {
+        return mats[a.mat].n * a.ncols > mats[b.mat].n * b.ncols;
+    });
+    int64_t off = 0;
+    for (auto &it : items) {
+        it.summ_off = off;
+        off += (mats[it.mat].n + K - 1) / K * 256;
+    }
+    if (items.size() > (size_t)INT32_MAX) return PENT_NOT_SUPPORTED;
+    GroupMat *dm = nullptr;
+    GroupItem *di = nullptr;
+    hipError_t e = hipMalloc(&dm, sizeof(GroupMat) * std::max<size_t>(cnt, 1));
+    if (e == hipSuccess) e = hipMalloc(&di, sizeof(GroupItem) * std::max<size_t>(items.size(), 1));
+    if (e == hipSuccess && cnt) e = hipMemcpy(dm, mats.data(), sizeof(GroupMat) * cnt, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !items.empty())
+        e = hipMemcpy(di, items.data(), sizeof(GroupItem) * items.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (dm) (void)hipFree(dm);
+        if (di) (void)hipFree(di);
+        return hip_status(e);
+    }
+    if (g->d_mats) (void)hipFree(g->d_mats);
+    if (g->d_items) (void)hipFree(g->d_items);
+    g->d_mats = dm;
+    g->d_items = di;
+    g->nitems = (int)items.size();
+    g->summ_doubles = off;
+    g->nblocks = std::max(1, std::min(g->nitems, group_max_blocks()));
+    g->F.assign(F, F + cnt);
+    g->batch.assign(batch, batch + cnt);
+    g->ld.assign(ld, ld + cnt);
+    g->bound = true;
+    return PENT_OK;
+}
+
+// Enqueue one group solve of the bound buffers (no synchronisation).
+int group_enqueue(pent_group g, int mode, void *work, hipStream_t s)
+{
+    if (mode == 0) {
+        if (g->nitems == 0) return PENT_OK;
+        return hip_status(launch_group(g->d_mats, g->d_items, g->nitems, (double *)work, g->d_ctr,
+                                       g->nblocks, s));
+    }
+    for (size_t k = 0; k < g->plans.size(); k++) {
+        if (g->batch[k] == 0) continue;
+        const int st = solve_io(g->plans[k], g->F[k], false, g->ld[k], g->F[k], g->ld[k],
+                                g->batch[k], work, s);
+        if (st != PENT_OK) return st;
+    }
+    return PENT_OK;
+}
+
+int group_check_args(pent_group g, double *const *F, const int64_t *batch, const int64_t *ld,
+                     int mode)
+{
+    if (!gvalid(g) || !batch || !ld || (mode != 0 && mode != 1)) return PENT_INVALID_VALUE;
+    for (size_t k = 0; k < g->plans.size(); k++) {
+        if (!valid(g->plans[k]) || batch[k] < 0 || ld[k] < batch[k]) return PENT_INVALID_VALUE;
+        if (batch[k] > 0 && (!F || !F[k])) return PENT_INVALID_VALUE;
+    }
+    return PENT_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 pent_handle pent_factor(int64_t n, const double *a, const double *b, const double *c,
@@ -421,6 +580,142 @@ int pent_backward_error(pent_handle h, const void *f, int f_dtype, int64_t ld_f,
     return ret(hip_status(launch_eta(h->d_diag, h->d_anorm, h->n, f, f_dtype == PENT_DTYPE_FP32,
                                      ld_f, x, ld_x, batch, (unsigned long long *)work, eta_out,
                                      (hipStream_t)stream)));
+}
+
+pent_group pent_group_create(const pent_handle *hs, int64_t count)
+{
+    if (!hs || count < 1 || count > (1 << 20)) {
+        ret(PENT_INVALID_VALUE);
+        return nullptr;
+    }
+    for (int64_t k = 0; k < count; k++)
+        if (!valid(hs[k])) {
+            ret(PENT_INVALID_VALUE);
+            return nullptr;
+        }
+    pent_group g = new (std::nothrow) pent_group_s();
+    if (!g) {
+        ret(PENT_OUT_OF_MEMORY);
+        return nullptr;
+    }
+    g->plans.assign(hs, hs + count);
+    hipError_t e = hipGetDevice(&g->device);
+    if (e == hipSuccess) e = hipMalloc(&g->d_ctr, 2 * sizeof(unsigned int));
+    if (e == hipSuccess) e = launch_group_init(g->d_ctr, 0);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        free_group(g);
+        ret(hip_status(e));
+        return nullptr;
+    }
+    g->magic = kGroupMagic;
+    ret(PENT_OK);
+    return g;
+}
+
+size_t pent_group_workspace_size(pent_group g, const int64_t *batch)
+{
+    if (!gvalid(g) || !batch) {
+        ret(PENT_INVALID_VALUE);
+        return 0;
+    }
+    for (size_t k = 0; k < g->plans.size(); k++)
+        if (batch[k] < 0) {
+            ret(PENT_INVALID_VALUE);
+            return 0;
+        }
+    ret(PENT_OK);
+    return group_ws_bytes(g, batch);
+}
+
+int pent_group_solve(pent_group g, double *const *F, const int64_t *batch, const int64_t *ld,
+                     int mode, void *work, size_t work_bytes, void *stream)
+{
+    int st = group_check_args(g, F, batch, ld, mode);
+    if (st != PENT_OK) return ret(st);
+    const size_t need = group_ws_bytes(g, batch);
+    if (need > 0 && !work) return ret(PENT_INVALID_VALUE);
+    if (work_bytes < need) return ret(PENT_SIZE_MISMATCH);
+    st = group_bind(g, F, batch, ld);
+    if (st != PENT_OK) return ret(st);
+    return ret(group_enqueue(g, mode, work, (hipStream_t)stream));
+}
+
+int pent_group_destroy(pent_group g)
+{
+    if (!g) return ret(PENT_OK);
+    if (!gvalid(g)) return ret(PENT_INVALID_VALUE);
+    free_group(g);
+    return ret(PENT_OK);
+}
+
+pent_graph pent_group_capture(pent_group g, double *const *F, const int64_t *batch,
+                              const int64_t *ld, int mode, int steps, void *work,
+                              size_t work_bytes, void *stream)
+{
+    int st = group_check_args(g, F, batch, ld, mode);
+    if (st == PENT_OK && (steps < 1 || !stream)) st = PENT_INVALID_VALUE;
+    if (st != PENT_OK) {
+        ret(st);
+        return nullptr;
+    }
+    const size_t need = group_ws_bytes(g, batch);
+    if ((need > 0 && !work) || work_bytes < need) {
+        ret(work ? PENT_SIZE_MISMATCH : PENT_INVALID_VALUE);
+        return nullptr;
+    }
+    st = group_bind(g, F, batch, ld);
+    if (st != PENT_OK) {
+        ret(st);
+        return nullptr;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        ret(hip_status(e));
+        return nullptr;
+    }
+    for (int i = 0; i < steps && st == PENT_OK; i++) st = group_enqueue(g, mode, work, s);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s, &graph);
+    if (st == PENT_OK && e != hipSuccess) st = hip_status(e);
+    hipGraphExec_t exec = nullptr;
+    if (st == PENT_OK) {
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) st = hip_status(e);
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+    if (st != PENT_OK) {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        ret(st);
+        return nullptr;
+    }
+    pent_graph gr = new (std::nothrow) pent_graph_s();
+    if (!gr) {
+        (void)hipGraphExecDestroy(exec);
+        ret(PENT_OUT_OF_MEMORY);
+        return nullptr;
+    }
+    gr->exec = exec;
+    gr->magic = kGraphMagic;
+    ret(PENT_OK);
+    return gr;
+}
+
+int pent_graph_launch(pent_graph gr, void *stream)
+{
+    if (!gr || gr->magic != kGraphMagic) return ret(PENT_INVALID_VALUE);
+    return ret(hip_status(hipGraphLaunch(gr->exec, (hipStream_t)stream)));
+}
+
+int pent_graph_destroy(pent_graph gr)
+{
+    if (!gr) return ret(PENT_OK);
+    if (gr->magic != kGraphMagic) return ret(PENT_INVALID_VALUE);
+    (void)hipGraphExecDestroy(gr->exec);
+    gr->magic = 0;
+    delete gr;
+    return ret(PENT_OK);
 }
 
 int pent_solve_strided(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream)

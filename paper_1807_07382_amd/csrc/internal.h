@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <mutex>
+#include <vector>
 
 #include "../../include/pentbatch.h"
 
@@ -57,6 +58,23 @@ struct alignas(64) ScanRec {
 // past n are all-zero records, which map a zero right-hand side to zero and
 // let fixed-height kernels run without per-row guards.
 constexpr int64_t kRecPad = 4096;
+
+// One matrix of a group solve, as the persistent kernel sees it.
+struct GroupMat {
+    const FwdRec *fwd;
+    const BwdRec *bwd;
+    const SegRec *seg;  // transfer matrices for 64-row segments
+    double *F;          // right-hand sides, batch-fastest, overwritten in place
+    int64_t n, npad, ld, batch;
+};
+
+// One work item: up to 64 consecutive systems of one matrix.
+struct GroupItem {
+    int mat;
+    int ncols;
+    int64_t col0;
+    int64_t summ_off;  // offset (doubles) of the item's segment summaries in the workspace
+};
 
 constexpr int kMaxSegCaches = 3;  // seg_rows 16, 32, 64
 
@@ -132,6 +150,14 @@ hipError_t launch_eta(const double *d_diag, const double *d_anorm, int64_t n, co
                       bool f32, int64_t ldf, const double *x, int64_t ldx, int64_t batch,
                       unsigned long long *acc, double *eta, hipStream_t s);
 hipError_t launch_anorm(const double *d_diag, int64_t n, double *d_anorm, hipStream_t s);
+
+// ---- group solve (group.hip) ----
+int group_seg_rows();
+int group_max_blocks();  // co-resident workgroups of the group kernel on the current device
+int group_threads();
+hipError_t launch_group_init(unsigned int *ctr, hipStream_t s);
+hipError_t launch_group(const GroupMat *mats, const GroupItem *items, int nitems, double *summ,
+                        unsigned int *ctr, int nblocks, hipStream_t s);
 hipError_t launch_strided_sweep(const FwdRec *fwd, const BwdRec *bwd, int64_t n, double *F,
                                 int64_t batch, int64_t ld, hipStream_t s);
 

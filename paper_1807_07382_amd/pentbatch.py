@@ -39,6 +39,15 @@ SIGNATURES = {
     "pent_solve_mixed": (_I, [_P, _P, _I, _I64, _P, _I64, _I64, _I, _P, _P, ctypes.c_size_t, _P]),
     "pent_mixed_workspace_size": (ctypes.c_size_t, [_P, _I64, _I, _I]),
     "pent_backward_error": (_I, [_P, _P, _I, _I64, _P, _I64, _I64, _P, _P, ctypes.c_size_t, _P]),
+    "pent_group_create": (_P, [ctypes.POINTER(_P), _I64]),
+    "pent_group_workspace_size": (ctypes.c_size_t, [_P, ctypes.POINTER(_I64)]),
+    "pent_group_solve": (_I, [_P, ctypes.POINTER(_P), ctypes.POINTER(_I64), ctypes.POINTER(_I64),
+                              _I, _P, ctypes.c_size_t, _P]),
+    "pent_group_destroy": (_I, [_P]),
+    "pent_group_capture": (_P, [_P, ctypes.POINTER(_P), ctypes.POINTER(_I64),
+                                ctypes.POINTER(_I64), _I, _I, _P, ctypes.c_size_t, _P]),
+    "pent_graph_launch": (_I, [_P, _P]),
+    "pent_graph_destroy": (_I, [_P]),
     "pent_get_factors": (_I, [_P, _P, _P, _P, _P]),
     "pent_get_diagonals": (_I, [_P, _P, _P, _P, _P, _P]),
     "pent_size": (_I64, [_P]),
@@ -247,3 +256,87 @@ class Plan:
 
     def set_schedule(self, kind: int, seg_rows: int = 0):
         _check(lib().pent_set_schedule(self._h, int(kind), int(seg_rows)), "set_schedule")
+
+
+class Group:
+    """Several factored plans solved together (pent_group).  ``solve`` runs
+    one persistent launch (mode 0) or one solve per matrix (mode 1)."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        arr = (_P * len(self.plans))(*[p.handle for p in self.plans])
+        self._g = lib().pent_group_create(arr, len(self.plans))
+        if not self._g:
+            raise PentError(lib().pent_last_status(), "group_create")
+        self._work = None
+
+    def _args(self, Fs):
+        import torch
+        if len(Fs) != len(self.plans):
+            raise ValueError("one right-hand-side block per plan")
+        for p, F in zip(self.plans, Fs):
+            if F.dim() != 2 or F.shape[0] != p.n or F.dtype != torch.float64 or not F.is_cuda:
+                raise ValueError("each block must be cuda float64 of shape (n_k, r_k)")
+            if F.shape[1] > 1 and F.stride(1) != 1:
+                raise ValueError("unit batch stride required")
+        cnt = len(Fs)
+        ptrs = (_P * cnt)(*[F.data_ptr() for F in Fs])
+        batch = (_I64 * cnt)(*[F.shape[1] for F in Fs])
+        ld = (_I64 * cnt)(*[max(F.stride(0), F.shape[1]) for F in Fs])
+        return ptrs, batch, ld
+
+    def workspace(self, Fs):
+        import torch
+        _, batch, _ = self._args(Fs)
+        nbytes = lib().pent_group_workspace_size(self._g, batch)
+        if self._work is None or self._work.numel() < nbytes:
+            self._work = torch.empty(max(nbytes, 256), dtype=torch.uint8, device="cuda")
+        return self._work
+
+    def solve_(self, Fs, mode: int = 0, stream=None):
+        ptrs, batch, ld = self._args(Fs)
+        w = self.workspace(Fs)
+        _check(lib().pent_group_solve(self._g, ptrs, batch, ld, int(mode), w.data_ptr(), w.numel(),
+                                      _stream_ptr(stream)), "group_solve")
+        return Fs
+
+    def capture(self, Fs, steps: int, mode: int = 0, stream=None):
+        """Executable graph of ``steps`` group solves on ``stream`` (a
+        torch.cuda.Stream, not the null stream)."""
+        ptrs, batch, ld = self._args(Fs)
+        w = self.workspace(Fs)
+        gr = lib().pent_group_capture(self._g, ptrs, batch, ld, int(mode), int(steps),
+                                      w.data_ptr(), w.numel(), _stream_ptr(stream))
+        if not gr:
+            raise PentError(lib().pent_last_status(), "group_capture")
+        return Graph(gr)
+
+    def close(self):
+        if self._g:
+            _check(lib().pent_group_destroy(self._g), "group_destroy")
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    def __init__(self, handle):
+        self._h = handle
+
+    def launch(self, stream=None):
+        _check(lib().pent_graph_launch(self._h, _stream_ptr(stream)), "graph_launch")
+
+    def close(self):
+        if self._h:
+            _check(lib().pent_graph_destroy(self._h), "graph_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,159 @@
+"""GPU tests of the batching extension: many matrices in one persistent
+launch (mode 0), the one-solve-per-matrix baseline (mode 1), and captured
+HIP graphs of several time steps, all against the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import workloads
+from paper_1807_07382_amd import inputs
+from paper_1807_07382_amd import pentbatch as pb
+from tests._gpu import colerr, d4_tol, print_case, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return torch_dev()
+
+
+SMALL = [(0.01, 64, 8), (3.0, 65, 1), (1e4, 1000, 130), (50.0, 4096, 64), (200.0, 129, 200),
+         (0.5, 8192, 5), (7.0, 1, 3), (1e2, 300, 0)]
+
+
+def make(torch, shapes, seed=0):
+    mats = [(s, np.random.Generator(np.random.PCG64(seed + k)).uniform(-1, 1, (n, r)))
+            for k, (s, n, r) in enumerate(shapes)]
+    plans = [pb.Plan.factor_d4(F.shape[0], s) for s, F in mats]
+    Ts = [torch.from_numpy(F.copy()).cuda() for _, F in mats]
+    return mats, plans, Ts
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("steps", [1, 3])
+def test_group_small_against_oracle(torch, mode, steps):
+    print_case(test="group_small", mode=mode, steps=steps)
+    mats, plans, Ts = make(torch, SMALL)
+    g = pb.Group(plans)
+    for _ in range(steps):
+        g.solve_(Ts, mode=mode)
+    torch.cuda.synchronize()
+    refs = workloads.group_run(mats, steps)
+    for (sigma, F), T, ref in zip(mats, Ts, refs):
+        X = T.cpu().numpy()
+        if F.shape[1]:
+            assert np.all(colerr(X, ref) <= steps * d4_tol(sigma)), (sigma, F.shape)
+    g.close()
+    for p in plans:
+        p.close()
+
+
+def test_group_deterministic_and_ld(torch):
+    """Same bits on every launch, and blocks with ld > batch."""
+    print_case(test="group_ld")
+    shapes = [(2.0, 500, 70), (1e3, 2000, 64)]
+    mats = [(s, np.random.Generator(np.random.PCG64(k)).uniform(-1, 1, (n, r)))
+            for k, (s, n, r) in enumerate(shapes)]
+    plans = [pb.Plan.factor_d4(F.shape[0], s) for s, F in mats]
+    bufs = [torch.full((F.shape[0], F.shape[1] + 9), 7.0, dtype=torch.float64, device="cuda")
+            for _, F in mats]
+    for b, (_, F) in zip(bufs, mats):
+        b[:, :F.shape[1]] = torch.from_numpy(F).cuda()
+    views = [b[:, :F.shape[1]] for b, (_, F) in zip(bufs, mats)]
+    g = pb.Group(plans)
+    g.solve_(views)
+    first = [v.clone() for v in views]
+    for v, (_, F) in zip(views, mats):
+        v.copy_(torch.from_numpy(F).cuda())
+    g.solve_(views)
+    torch.cuda.synchronize()
+    for a, b in zip(first, views):
+        assert torch.equal(a, b)
+    for b, (_, F) in zip(bufs, mats):
+        assert bool(torch.all(b[:, F.shape[1]:] == 7.0))
+    refs = workloads.group_run(mats, 1)
+    for (sigma, _), v, ref in zip(mats, views, refs):
+        assert np.all(colerr(v.cpu().numpy(), ref) <= d4_tol(sigma))
+    g.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_graph_replays_match_eager(torch, mode):
+    """A captured graph of 3 steps, replayed 3 times with eager work and
+    synchronisations in between: every replay equals the eager result."""
+    print_case(test="graph", mode=mode)
+    shapes = [(0.3, 200, 33), (5e3, 3000, 100), (1.0, 64, 8)]
+    mats, plans, Ts = make(torch, shapes, seed=11)
+    g = pb.Group(plans)
+    init = [T.clone() for T in Ts]
+    # eager reference: 3 steps
+    for _ in range(3):
+        g.solve_(Ts, mode=mode)
+    torch.cuda.synchronize()
+    eager = [T.clone() for T in Ts]
+    s = torch.cuda.Stream()
+    for T, I in zip(Ts, init):
+        T.copy_(I)
+    torch.cuda.synchronize()
+    graph = g.capture(Ts, steps=3, mode=mode, stream=s)
+    for rep in range(3):
+        for T, I in zip(Ts, init):
+            T.copy_(I)
+        junk = torch.randn(1000, device="cuda").sum()   # unrelated eager work
+        torch.cuda.synchronize()
+        graph.launch(stream=s)
+        s.synchronize()
+        for T, E in zip(Ts, eager):
+            assert torch.equal(T, E), f"replay {rep}"
+        del junk
+    graph.close()
+    refs = workloads.group_run(mats, 3)
+    for (sigma, _), E, ref in zip(mats, eager, refs):
+        assert np.all(colerr(E.cpu().numpy(), ref) <= 3 * d4_tol(sigma))
+    g.close()
+
+
+def test_group_workload_full_shapes(torch):
+    """The 48-matrix workload at its full sizes (sigma_k, N_k, R_k of seed 5),
+    5 steps in one persistent launch each; 4 sampled systems per matrix
+    against the oracle."""
+    print_case(test="group_full")
+    mats = inputs.group()
+    plans = [pb.Plan.factor_d4(F.shape[0], s) for s, F in mats]
+    Ts = [torch.from_numpy(F).cuda() for _, F in mats]
+    g = pb.Group(plans)
+    steps = 5
+    for _ in range(steps):
+        g.solve_(Ts)
+    torch.cuda.synchronize()
+    for k, ((sigma, F), T) in enumerate(zip(mats, Ts)):
+        r = F.shape[1]
+        cols = np.unique(np.array([0, r // 3, (2 * r) // 3, r - 1]))
+        ref = workloads.group_run([(sigma, np.ascontiguousarray(F[:, cols]))], steps)[0]
+        X = T[:, torch.from_numpy(cols).cuda()].cpu().numpy()
+        assert np.all(colerr(X, ref) <= steps * d4_tol(sigma)), (k, sigma, F.shape)
+    g.close()
+
+
+def test_group_argument_errors(torch):
+    L = pb.lib()
+    with pb.Plan.factor_d4(10, 1.0) as p:
+        arr = (pb._P * 1)(p.handle)
+        g = L.pent_group_create(arr, 1)
+        assert g
+        T = torch.zeros((10, 4), dtype=torch.float64, device="cuda")
+        ptrs = (pb._P * 1)(T.data_ptr())
+        batch = (pb._I64 * 1)(4)
+        ld = (pb._I64 * 1)(3)      # ld < batch
+        assert L.pent_group_solve(g, ptrs, batch, ld, 0, None, 0, None) == pb.INVALID_VALUE
+        ld = (pb._I64 * 1)(4)
+        need = L.pent_group_workspace_size(g, batch)
+        assert need > 0
+        W = torch.zeros(need, dtype=torch.uint8, device="cuda")
+        assert L.pent_group_solve(g, ptrs, batch, ld, 5, W.data_ptr(), need, None) == pb.INVALID_VALUE
+        assert L.pent_group_solve(g, ptrs, batch, ld, 0, W.data_ptr(), need - 1, None) == pb.SIZE_MISMATCH
+        assert L.pent_group_solve(g, ptrs, batch, ld, 0, W.data_ptr(), need, None) == pb.OK
+        assert L.pent_group_destroy(g) == pb.OK
+    assert not L.pent_group_create(None, 1)
+    assert L.pent_group_destroy(None) == pb.OK
