@@ -13,7 +13,9 @@ right-hand-side streams (FP64 arithmetic, with 0 and 1 refinement steps) on
 N=8192 with 131072 right-hand sides, sigma=1e2.
 
 Other workloads (for tuning runs): ``plain`` (N=256, 256 RHS), ``precision``
-(all three sigma), ``shape`` (any n / batch), ``copy`` (device copy).
+(all three sigma), ``shape`` (any n / batch), ``copy`` (device copy),
+``group`` (48 matrices, 200 graph-captured steps, persistent launch vs one
+solve per matrix).
 """
 from __future__ import annotations
 
@@ -228,6 +230,64 @@ def run_precision(args, torch):
                 per_sigma=res)
 
 
+def run_group(args, torch):
+    """48 matrices I + sigma_k*D4 (sigma_k, N_k, R_k log-uniform, seed 5),
+    every step solves all of them in place (backward Euler); 200 steps are
+    captured into one HIP graph.  Persistent single launch per step (kernel
+    variant autotuned) against one solve per matrix (schedules autotuned)."""
+    from paper_1807_07382_amd import inputs
+    from paper_1807_07382_amd import pentbatch as pb
+    from oracle import workloads
+    steps = args.steps if args.steps != 100 else inputs.GROUP["steps"]
+    mats = inputs.group()
+    plans = [pb.Plan.factor_d4(F.shape[0], sg) for sg, F in mats]
+    Ts = [torch.from_numpy(F).cuda() for _, F in mats]
+    probe = [(k, np.unique([0, F.shape[1] - 1])) for k, (_, F) in enumerate(mats)]
+    init = [T.clone() for T in Ts]
+    unknowns = sum(F.shape[0] * F.shape[1] for _, F in mats)
+    systems = sum(F.shape[1] for _, F in mats)
+    g = pb.Group(plans)
+    variant, tune_ms = g.autotune(Ts)
+    for p, (_, F) in zip(plans, mats):
+        p.autotune(F.shape[1])
+    s = torch.cuda.Stream()
+    res = {}
+    for mode in (0, 1):
+        for T, I in zip(Ts, init):
+            T.copy_(I)
+        torch.cuda.synchronize()
+        graph = g.capture(Ts, steps=steps, mode=mode, stream=s)
+        graph.launch(stream=s)                     # warm-up replay
+        s.synchronize()
+        for T, I in zip(Ts, init):
+            T.copy_(I)
+        torch.cuda.synchronize()
+        ms = _timed(torch, s, lambda: graph.launch(stream=s), 1)
+        # parity: the state after one replay (= steps implicit steps)
+        errs = []
+        for k, cols in probe:
+            sigma, F = mats[k]
+            ref = workloads.group_run([(sigma, np.ascontiguousarray(F[:, cols]))], steps)[0]
+            X = Ts[k][:, torch.from_numpy(cols).cuda()].cpu().numpy()
+            den = np.maximum(np.max(np.abs(ref), axis=0), 1e-300)
+            errs.append(float(np.max(np.max(np.abs(X - ref), axis=0) / den)))
+        graph.close()
+        res[mode] = dict(ms=ms, max_rel_err_vs_oracle=max(errs))
+    g.close()
+    ms_step = res[0]["ms"] / steps
+    gbs = BYTES_PER_UNKNOWN_FP64 * unknowns / (ms_step / 1e3) / 1e9
+    return dict(metric=METRIC, value=systems * steps / (res[0]["ms"] / 1e3), unit="RHS-solves/s",
+                n_gpus=1, steps=steps, warmup=1, ms_per_step=ms_step, higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+                config=dict(workload="group", matrices=len(mats), unknowns_per_step=unknowns,
+                            systems=systems, graph_steps=steps, kernel_variant=variant),
+                roofline=dict(bound="hbm", achieved=gbs, peak=PEAK_HBM_GBS, unit="GB/s",
+                              frac=gbs / PEAK_HBM_GBS, traffic=None),
+                persistent=res[0],
+                per_matrix=dict(res[1], ms_per_step=res[1]["ms"] / steps,
+                                speedup_of_persistent=res[1]["ms"] / res[0]["ms"]))
+
+
 def run_plain(args, torch):
     from paper_1807_07382_amd import inputs
     from paper_1807_07382_amd import pentbatch as pb
@@ -321,7 +381,7 @@ def run_shape(args, torch):
 
 
 WORKLOADS = {"hyperdiff": run_hyperdiff, "plain": run_plain, "copy": run_copy,
-             "shape": run_shape, "precision": run_precision}
+             "shape": run_shape, "precision": run_precision, "group": run_group}
 
 
 def main(argv=None):

@@ -164,6 +164,20 @@ int pent_group_solve(pent_group g, double *const *F, const int64_t *batch, const
                      int mode, void *work, size_t work_bytes, void *stream);
 int pent_group_destroy(pent_group g); /* NULL is a no-op */
 
+/* Autotune the persistent group kernel for these right-hand-side counts
+ * (HOST array batch[count]): every kernel variant (64 or 32 rows per segment,
+ * 8 or 4 waves per workgroup) is timed on scratch blocks of the same shapes
+ * (the caller's data is not touched) and the fastest is kept for later mode-0
+ * solves.  Blocking; allocates scratch for the duration of the call.
+ * variant_out / ms_out (HOST, optional) receive the choice and its time. */
+int pent_group_autotune(pent_group g, const int64_t *batch, int *variant_out, double *ms_out,
+                        void *stream);
+
+/* Force the persistent kernel variant (0..3: 64/32/64/32 rows per segment
+ * with 8/8/4/4 waves per workgroup) for later mode-0 solves (tests and
+ * manual tuning).  PENT_INVALID_VALUE for an unknown variant. */
+int pent_group_set_variant(pent_group g, int variant);
+
 /* Capture `steps` consecutive group solves (mode as above) on `stream` into
  * an executable HIP graph (one graph launch = `steps` implicit time steps).
  * `stream` must be a created stream (not the null stream).  The buffers are
@@ -195,6 +209,17 @@ int64_t pent_size(pent_handle h); /* n, or -1 for a bad handle */
  *           For larger n a solve falls back to kind 2.
  * Returns PENT_INVALID_VALUE for an unknown kind or seg_rows. */
 int pent_set_schedule(pent_handle h, int kind, int seg_rows);
+
+/* Autotune the schedule of this handle for `batch` systems: one lane per
+ * system, partitioned with 16/32/64 rows per lane, and (n <= 4096) the
+ * resident tile are timed on a scratch buffer of n x batch (allocated and
+ * freed here) and the fastest is set as the handle's schedule (for every
+ * later batch size).  Results are kept per process for (n, batch) and
+ * appended to the text file named by the environment variable
+ * PENT_TUNE_CACHE, which later processes read back.  Blocking.  kind_out,
+ * seg_rows_out, ms_out (HOST, optional) receive the choice and its time. */
+int pent_autotune(pent_handle h, int64_t batch, int *kind_out, int *seg_rows_out, double *ms_out,
+                  void *stream);
 
 /* The schedule pent_solve would use for `batch` systems on this handle
  * (kind as above, seg_rows 0 unless kind is 2).  Host-only, no HIP call. */

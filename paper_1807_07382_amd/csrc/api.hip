@@ -2,8 +2,12 @@
 // argument checks, handle lifetime, schedule choice and kernel launches.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
+#include <tuple>
 
 #include "internal.h"
 
@@ -260,7 +264,7 @@ struct pent_group_s {
     int nitems = 0;
     int64_t summ_doubles = 0;
     unsigned int *d_ctr = nullptr;  // [next item, workgroups done]
-    int nblocks = 0;
+    int variant = 0;                // group kernel variant (autotuned)
 };
 
 struct pent_graph_s {
@@ -285,16 +289,16 @@ void free_group(pent_group g)
     delete g;
 }
 
-// Workspace of the persistent solve for these counts (doubles of summaries).
+// Workspace of the persistent solve for these counts (doubles of segment
+// summaries, counted for 64-row segments; the 32-row variants use twice that).
 int64_t group_summ_doubles(const pent_group g, const int64_t *batch)
 {
     int64_t tot = 0;
-    const int K = group_seg_rows();
     for (size_t k = 0; k < g->plans.size(); k++) {
-        const int64_t nseg = (g->plans[k]->n + K - 1) / K;
+        const int64_t nseg = (g->plans[k]->n + 63) / 64;
         tot += (batch[k] + 63) / 64 * nseg * 256;
     }
-    return tot;
+    return 2 * tot;
 }
 
 size_t group_ws_bytes(const pent_group g, const int64_t *batch)
@@ -321,11 +325,12 @@ int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64
     std::vector<GroupMat> mats(cnt);
     std::vector<GroupItem> items;
     int st;
-    const int K = group_seg_rows();
     for (size_t k = 0; k < cnt; k++) {
         pent_plan *p = g->plans[k];
-        const SegRec *seg = seg_cache(p, K, &st);
-        if (!seg) return st;
+        const SegRec *seg64 = seg_cache(p, 64, &st);
+        if (!seg64) return st;
+        const SegRec *seg32 = seg_cache(p, 32, &st);
+        if (!seg32) return st;
         int kind, seg_rows;
         io_schedule(p, batch[k], true, &kind, &seg_rows);
         if (kind == 2 && !seg_cache(p, seg_rows, &st)) return st;
@@ -334,7 +339,7 @@ int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64
             const double *tr;
             if (!tile_cache(p, tile_rows_for(p->n), &sc, &tr, &st)) return st;
         }
-        mats[k] = GroupMat{p->d_fwd, p->d_bwd, seg, F[k], p->n, p->npad, ld[k], batch[k]};
+        mats[k] = GroupMat{p->d_fwd, p->d_bwd, seg64, seg32, F[k], p->n, p->npad, ld[k], batch[k]};
     }
     for (size_t k = 0; k < cnt; k++)
         for (int64_t c0 = 0; c0 < batch[k]; c0 += 64)
@@ -346,7 +351,7 @@ int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64
     int64_t off = 0;
     for (auto &it : items) {
         it.summ_off = off;
-        off += (mats[it.mat].n + K - 1) / K * 256;
+        off += (mats[it.mat].n + 63) / 64 * 256;
     }
     if (items.size() > (size_t)INT32_MAX) return PENT_NOT_SUPPORTED;
     GroupMat *dm = nullptr;
@@ -366,8 +371,7 @@ int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64
     g->d_mats = dm;
     g->d_items = di;
     g->nitems = (int)items.size();
-    g->summ_doubles = off;
-    g->nblocks = std::max(1, std::min(g->nitems, group_max_blocks()));
+    g->summ_doubles = 2 * off;
     g->F.assign(F, F + cnt);
     g->batch.assign(batch, batch + cnt);
     g->ld.assign(ld, ld + cnt);
@@ -380,8 +384,9 @@ int group_enqueue(pent_group g, int mode, void *work, hipStream_t s)
 {
     if (mode == 0) {
         if (g->nitems == 0) return PENT_OK;
-        return hip_status(launch_group(g->d_mats, g->d_items, g->nitems, (double *)work, g->d_ctr,
-                                       g->nblocks, s));
+        const int nblocks = std::max(1, std::min(g->nitems, group_max_blocks(g->variant)));
+        return hip_status(launch_group(g->variant, g->d_mats, g->d_items, g->nitems,
+                                       (double *)work, g->d_ctr, nblocks, s));
     }
     for (size_t k = 0; k < g->plans.size(); k++) {
         if (g->batch[k] == 0) continue;
@@ -390,6 +395,75 @@ int group_enqueue(pent_group g, int mode, void *work, hipStream_t s)
         if (st != PENT_OK) return st;
     }
     return PENT_OK;
+}
+
+// ---- autotuning ----
+// Results are kept per process, keyed by (n, batch), and optionally in a text
+// file named by PENT_TUNE_CACHE ("n batch kind seg_rows ms" per line).
+std::mutex g_tune_mu;
+std::map<std::pair<int64_t, int64_t>, std::tuple<int, int, double>> g_tune;
+bool g_tune_loaded = false;
+
+void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("PENT_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    long long n, b;
+    int kind, seg;
+    double ms;
+    while (std::fscanf(f, "%lld %lld %d %d %lf", &n, &b, &kind, &seg, &ms) == 5)
+        g_tune[{n, b}] = std::make_tuple(kind, seg, ms);
+    std::fclose(f);
+}
+
+void tune_store_locked(int64_t n, int64_t b, int kind, int seg, double ms)
+{
+    g_tune[{n, b}] = std::make_tuple(kind, seg, ms);
+    const char *path = std::getenv("PENT_TUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%lld %lld %d %d %.6f\n", (long long)n, (long long)b, kind, seg, ms);
+    std::fclose(f);
+}
+
+__global__ void k_fill_const(double *p, int64_t count, double v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+hipError_t fill_const(double *p, int64_t count, double v, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_const, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p,
+                       count, v);
+    return hipGetLastError();
+}
+
+// Average milliseconds of `reps` calls of fn after one warm-up call.
+template <typename Fn>
+int time_ms(Fn fn, hipStream_t s, int reps, double *ms)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    int st = e == hipSuccess ? fn() : hip_status(e);
+    if (st == PENT_OK) e = hipEventRecord(e0, s);
+    for (int r = 0; st == PENT_OK && e == hipSuccess && r < reps; r++) st = fn();
+    if (st == PENT_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+    if (st == PENT_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (st == PENT_OK && e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st == PENT_OK && e != hipSuccess) st = hip_status(e);
+    *ms = t / reps;
+    return st;
 }
 
 int group_check_args(pent_group g, double *const *F, const int64_t *batch, const int64_t *ld,
@@ -639,6 +713,128 @@ int pent_group_solve(pent_group g, double *const *F, const int64_t *batch, const
     st = group_bind(g, F, batch, ld);
     if (st != PENT_OK) return ret(st);
     return ret(group_enqueue(g, mode, work, (hipStream_t)stream));
+}
+
+int pent_autotune(pent_handle h, int64_t batch, int *kind_out, int *seg_rows_out, double *ms_out,
+                  void *stream)
+{
+    if (!valid(h) || batch < 1) return ret(PENT_INVALID_VALUE);
+    hipStream_t s = (hipStream_t)stream;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find({h->n, batch});
+        if (it != g_tune.end()) {
+            h->sched_kind = std::get<0>(it->second);
+            h->sched_seg = std::get<1>(it->second);
+            if (kind_out) *kind_out = h->sched_kind;
+            if (seg_rows_out) *seg_rows_out = h->sched_seg;
+            if (ms_out) *ms_out = std::get<2>(it->second);
+            return ret(PENT_OK);
+        }
+    }
+    const int cands[5][2] = {{1, 0}, {2, 16}, {2, 32}, {2, 64}, {3, 0}};
+    double *F = nullptr;
+    void *work = nullptr;
+    const size_t nF = (size_t)h->n * batch;
+    size_t wbytes = 0;
+    for (const auto &c : cands) wbytes = std::max(wbytes, summ_bytes(h, c[0], c[1] ? c[1] : 64, batch));
+    hipError_t e = hipMalloc(&F, sizeof(double) * nF);
+    if (e == hipSuccess && wbytes) e = hipMalloc(&work, wbytes);
+    if (e == hipSuccess) e = fill_const(F, (int64_t)nF, 1.0, s);
+    int st = hip_status(e);
+    const int saved_kind = h->sched_kind, saved_seg = h->sched_seg;
+    int best_kind = 0, best_seg = 0;
+    double best = 1e300;
+    for (const auto &c : cands) {
+        if (st != PENT_OK) break;
+        if (c[0] == 3 && tile_rows_for(h->n) == 0) continue;
+        if (c[0] == 2 && (h->n + c[1] - 1) / c[1] > 65535) continue;
+        h->sched_kind = c[0];
+        h->sched_seg = c[1];
+        double ms = 0.0;
+        st = time_ms([&] { return solve_io(h, F, false, batch, F, batch, batch, work, s); }, s, 3, &ms);
+        if (st == PENT_OK && ms < best) {
+            best = ms;
+            best_kind = c[0];
+            best_seg = c[1];
+        }
+    }
+    if (F) (void)hipFree(F);
+    if (work) (void)hipFree(work);
+    if (st != PENT_OK) {
+        h->sched_kind = saved_kind;
+        h->sched_seg = saved_seg;
+        return ret(st);
+    }
+    h->sched_kind = best_kind;
+    h->sched_seg = best_seg;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_store_locked(h->n, batch, best_kind, best_seg, best);
+    }
+    if (kind_out) *kind_out = best_kind;
+    if (seg_rows_out) *seg_rows_out = best_seg;
+    if (ms_out) *ms_out = best;
+    return ret(PENT_OK);
+}
+
+int pent_group_autotune(pent_group g, const int64_t *batch, int *variant_out, double *ms_out,
+                        void *stream)
+{
+    if (!gvalid(g) || !batch) return ret(PENT_INVALID_VALUE);
+    const size_t cnt = g->plans.size();
+    for (size_t k = 0; k < cnt; k++)
+        if (batch[k] < 0) return ret(PENT_INVALID_VALUE);
+    hipStream_t s = (hipStream_t)stream;
+    // scratch blocks of the same shapes (the caller's data is never touched)
+    std::vector<double *> F(cnt, nullptr);
+    std::vector<int64_t> ld(batch, batch + cnt);
+    void *work = nullptr;
+    hipError_t e = hipSuccess;
+    for (size_t k = 0; k < cnt && e == hipSuccess; k++) {
+        const size_t m = (size_t)g->plans[k]->n * std::max<int64_t>(batch[k], 1);
+        e = hipMalloc(&F[k], sizeof(double) * m);
+        if (e == hipSuccess) e = fill_const(F[k], (int64_t)m, 1.0, s);
+    }
+    const size_t wbytes = group_ws_bytes(g, batch);
+    if (e == hipSuccess && wbytes) e = hipMalloc(&work, wbytes);
+    int st = hip_status(e);
+    // keep the caller's binding to restore afterwards
+    const bool had = g->bound;
+    std::vector<double *> oF = g->F;
+    std::vector<int64_t> ob = g->batch, ol = g->ld;
+    if (st == PENT_OK) st = group_bind(g, F.data(), batch, ld.data());
+    const int saved = g->variant;
+    int best_v = saved;
+    double best = 1e300;
+    for (int v = 0; st == PENT_OK && v < group_variants(); v++) {
+        g->variant = v;
+        double ms = 0.0;
+        st = time_ms([&] { return group_enqueue(g, 0, work, s); }, s, 3, &ms);
+        if (st == PENT_OK && ms < best) {
+            best = ms;
+            best_v = v;
+        }
+    }
+    g->variant = st == PENT_OK ? best_v : saved;
+    if (st == PENT_OK) (void)hipStreamSynchronize(s);
+    g->bound = false;  // next solve re-binds (to the caller's buffers)
+    if (had && st == PENT_OK) st = group_bind(g, oF.data(), ob.data(), ol.data());
+    for (auto p : F)
+        if (p) (void)hipFree(p);
+    if (work) (void)hipFree(work);
+    if (st != PENT_OK) return ret(st);
+    if (variant_out) *variant_out = best_v;
+    if (ms_out) *ms_out = best;
+    return ret(PENT_OK);
+}
+
+int pent_group_set_variant(pent_group g, int variant)
+{
+    if (!gvalid(g) || variant < 0 || variant >= group_variants()) return ret(PENT_INVALID_VALUE);
+    g->variant = variant;
+    return ret(PENT_OK);
 }
 
 int pent_group_destroy(pent_group g)

@@ -19,7 +19,6 @@
 namespace pent {
 namespace {
 
-constexpr int kGK = 64;       // rows per segment
 
 // Pointers read from the device table are generic; give them their address
 // spaces back so records become scalar loads and data global (not flat) loads.
@@ -27,9 +26,8 @@ typedef __attribute__((address_space(4))) const FwdRec *CFwd;
 typedef __attribute__((address_space(4))) const BwdRec *CBwd;
 typedef __attribute__((address_space(4))) const SegRec *CSeg;
 typedef __attribute__((address_space(1))) double *GDbl;
-constexpr int kGroupWaves = 8;
-constexpr int kGroupThreads = 64 * kGroupWaves;
 
+template <int kGK>
 __device__ __forceinline__ void load_seg(double (&v)[kGK], GDbl base, int64_t ld, int L)
 {
     if (L == kGK) {
@@ -44,6 +42,7 @@ __device__ __forceinline__ void load_seg(double (&v)[kGK], GDbl base, int64_t ld
 // Sweeps over one segment; the per-row records are wave-uniform (every lane
 // of the wave is on the same row), so they come through scalar loads.
 // Rows past n have all-zero records and zero data, so no per-row guards.
+template <int kGK>
 __device__ __forceinline__ void fwd_seg(double (&v)[kGK], CFwd fwd, int64_t r0, double &p2,
                                         double &p1)
 {
@@ -57,6 +56,7 @@ __device__ __forceinline__ void fwd_seg(double (&v)[kGK], CFwd fwd, int64_t r0, 
     }
 }
 
+template <int kGK>
 __device__ __forceinline__ void bwd_seg(double (&v)[kGK], CBwd bwd, int64_t r0, double &q1,
                                         double &q2)
 {
@@ -70,10 +70,12 @@ __device__ __forceinline__ void bwd_seg(double (&v)[kGK], CBwd bwd, int64_t r0, 
     }
 }
 
-__global__ __launch_bounds__(kGroupThreads) void k_group(const GroupMat *__restrict__ mats,
-                                                         const GroupItem *__restrict__ items,
-                                                         int nitems, double *__restrict__ summ,
-                                                         unsigned int *__restrict__ ctr)
+// kGK rows per segment, kGroupWaves waves per workgroup (tuned per group).
+template <int kGK, int kGroupWaves>
+__global__ __launch_bounds__(64 * kGroupWaves) void k_group(const GroupMat *__restrict__ mats,
+                                                            const GroupItem *__restrict__ items,
+                                                            int nitems, double *__restrict__ summ,
+                                                            unsigned int *__restrict__ ctr)
 {
     __shared__ int s_item;
     const int tid = threadIdx.x;
@@ -88,13 +90,13 @@ __global__ __launch_bounds__(kGroupThreads) void k_group(const GroupMat *__restr
         const GroupMat m = mats[item.mat];
         const CFwd fwd = (CFwd)m.fwd;
         const CBwd bwd = (CBwd)m.bwd;
-        const CSeg segr = (CSeg)m.seg;
+        const CSeg segr = (CSeg)(kGK == 64 ? m.seg64 : m.seg32);
         const int64_t n = m.n;
         const int nseg = (int)((n + kGK - 1) / kGK);
         const bool act = lane < item.ncols;
         const int64_t j = item.col0 + (act ? lane : 0);
         GDbl col = (GDbl)m.F + j;
-        GDbl S = (GDbl)summ + item.summ_off;  // [seg][4][64]
+        GDbl S = (GDbl)summ + item.summ_off * (64 / kGK);  // [seg][4][64]
 
         // pass 1: zero-incoming sweeps per segment, outgoing states to S
         for (int sg = w; sg < nseg; sg += kGroupWaves) {
@@ -193,19 +195,42 @@ __global__ void k_zero_u32(unsigned int *p, int count)
 
 }  // namespace
 
-int group_seg_rows() { return kGK; }
+int group_variants() { return 4; }
 
-int group_max_blocks()
+// variant -> (rows per segment, waves per workgroup)
+static void variant_shape(int v, int *K, int *W)
 {
-    int dev = 0, cus = 0, per_cu = 0;
+    *K = (v & 1) ? 32 : 64;
+    *W = (v & 2) ? 4 : 8;
+}
+
+int group_variant_seg_rows(int v)
+{
+    int K, W;
+    variant_shape(v, &K, &W);
+    return K;
+}
+
+static const void *variant_fn(int v)
+{
+    switch (v) {
+    case 0: return (const void *)k_group<64, 8>;
+    case 1: return (const void *)k_group<32, 8>;
+    case 2: return (const void *)k_group<64, 4>;
+    default: return (const void *)k_group<32, 4>;
+    }
+}
+
+int group_max_blocks(int v)
+{
+    int dev = 0, cus = 0, per_cu = 0, K, W;
+    variant_shape(v, &K, &W);
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_group, kGroupThreads, 0) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, variant_fn(v), 64 * W, 0) != hipSuccess)
         return 0;
     return cus * (per_cu > 0 ? per_cu : 1);
 }
-int group_threads() { return kGroupThreads; }
 
 hipError_t launch_group_init(unsigned int *ctr, hipStream_t s)
 {
@@ -213,11 +238,18 @@ hipError_t launch_group_init(unsigned int *ctr, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_group(const GroupMat *mats, const GroupItem *items, int nitems, double *summ,
-                        unsigned int *ctr, int nblocks, hipStream_t s)
+hipError_t launch_group(int v, const GroupMat *mats, const GroupItem *items, int nitems,
+                        double *summ, unsigned int *ctr, int nblocks, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_group, dim3((unsigned)nblocks), dim3(kGroupThreads), 0, s, mats, items,
-                       nitems, summ, ctr);
+    int K, W;
+    variant_shape(v, &K, &W);
+    const dim3 grid((unsigned)nblocks), block(64 * W);
+    switch (v) {
+    case 0: hipLaunchKernelGGL((k_group<64, 8>), grid, block, 0, s, mats, items, nitems, summ, ctr); break;
+    case 1: hipLaunchKernelGGL((k_group<32, 8>), grid, block, 0, s, mats, items, nitems, summ, ctr); break;
+    case 2: hipLaunchKernelGGL((k_group<64, 4>), grid, block, 0, s, mats, items, nitems, summ, ctr); break;
+    default: hipLaunchKernelGGL((k_group<32, 4>), grid, block, 0, s, mats, items, nitems, summ, ctr); break;
+    }
     return hipGetLastError();
 }
 

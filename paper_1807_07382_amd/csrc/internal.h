@@ -63,7 +63,8 @@ constexpr int64_t kRecPad = 4096;
 struct GroupMat {
     const FwdRec *fwd;
     const BwdRec *bwd;
-    const SegRec *seg;  // transfer matrices for 64-row segments
+    const SegRec *seg64;  // transfer matrices for 64-row segments
+    const SegRec *seg32;  // ... and for 32-row segments
     double *F;          // right-hand sides, batch-fastest, overwritten in place
     int64_t n, npad, ld, batch;
 };
@@ -152,12 +153,15 @@ hipError_t launch_eta(const double *d_diag, const double *d_anorm, int64_t n, co
 hipError_t launch_anorm(const double *d_diag, int64_t n, double *d_anorm, hipStream_t s);
 
 // ---- group solve (group.hip) ----
-int group_seg_rows();
-int group_max_blocks();  // co-resident workgroups of the group kernel on the current device
-int group_threads();
+// Kernel variants (rows per segment x waves per workgroup), chosen by the
+// group autotuner.  Summary offsets in GroupItem are in units of the 64-row
+// variant; a 32-row variant scales them by 2.
+int group_variants();
+int group_variant_seg_rows(int v);
+int group_max_blocks(int v);  // co-resident workgroups of variant v on the current device
 hipError_t launch_group_init(unsigned int *ctr, hipStream_t s);
-hipError_t launch_group(const GroupMat *mats, const GroupItem *items, int nitems, double *summ,
-                        unsigned int *ctr, int nblocks, hipStream_t s);
+hipError_t launch_group(int v, const GroupMat *mats, const GroupItem *items, int nitems,
+                        double *summ, unsigned int *ctr, int nblocks, hipStream_t s);
 hipError_t launch_strided_sweep(const FwdRec *fwd, const BwdRec *bwd, int64_t n, double *F,
                                 int64_t batch, int64_t ld, hipStream_t s);
 

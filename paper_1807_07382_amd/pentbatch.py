@@ -44,10 +44,15 @@ SIGNATURES = {
     "pent_group_solve": (_I, [_P, ctypes.POINTER(_P), ctypes.POINTER(_I64), ctypes.POINTER(_I64),
                               _I, _P, ctypes.c_size_t, _P]),
     "pent_group_destroy": (_I, [_P]),
+    "pent_group_set_variant": (_I, [_P, _I]),
     "pent_group_capture": (_P, [_P, ctypes.POINTER(_P), ctypes.POINTER(_I64),
                                 ctypes.POINTER(_I64), _I, _I, _P, ctypes.c_size_t, _P]),
     "pent_graph_launch": (_I, [_P, _P]),
     "pent_graph_destroy": (_I, [_P]),
+    "pent_autotune": (_I, [_P, _I64, ctypes.POINTER(_I), ctypes.POINTER(_I),
+                           ctypes.POINTER(_D), _P]),
+    "pent_group_autotune": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I),
+                                 ctypes.POINTER(_D), _P]),
     "pent_get_factors": (_I, [_P, _P, _P, _P, _P]),
     "pent_get_diagonals": (_I, [_P, _P, _P, _P, _P, _P]),
     "pent_size": (_I64, [_P]),
@@ -247,6 +252,14 @@ class Plan:
         _check(lib().pent_get_diagonals(self._h, *[x.ctypes.data for x in out]), "get_diagonals")
         return tuple(out)
 
+    def autotune(self, batch: int, stream=None):
+        """Time the schedules for ``batch`` systems and keep the fastest;
+        returns (kind, seg_rows, ms)."""
+        k, sr, ms = _I(0), _I(0), _D(0.0)
+        _check(lib().pent_autotune(self._h, int(batch), ctypes.byref(k), ctypes.byref(sr),
+                                   ctypes.byref(ms), _stream_ptr(stream)), "autotune")
+        return int(k.value), int(sr.value), float(ms.value)
+
     def schedule_for(self, batch: int):
         """(kind, seg_rows) pent_solve uses for ``batch`` systems."""
         k, sr = _I(0), _I(0)
@@ -299,6 +312,18 @@ class Group:
         _check(lib().pent_group_solve(self._g, ptrs, batch, ld, int(mode), w.data_ptr(), w.numel(),
                                       _stream_ptr(stream)), "group_solve")
         return Fs
+
+    def set_variant(self, variant: int):
+        _check(lib().pent_group_set_variant(self._g, int(variant)), "group_set_variant")
+
+    def autotune(self, Fs, stream=None):
+        """Time the persistent kernel variants on scratch blocks shaped like
+        ``Fs`` and keep the fastest; returns (variant, ms)."""
+        _, batch, _ = self._args(Fs)
+        v, ms = _I(0), _D(0.0)
+        _check(lib().pent_group_autotune(self._g, batch, ctypes.byref(v), ctypes.byref(ms),
+                                         _stream_ptr(stream)), "group_autotune")
+        return int(v.value), float(ms.value)
 
     def capture(self, Fs, steps: int, mode: int = 0, stream=None):
         """Executable graph of ``steps`` group solves on ``stream`` (a

@@ -157,3 +157,67 @@ def test_group_argument_errors(torch):
         assert L.pent_group_destroy(g) == pb.OK
     assert not L.pent_group_create(None, 1)
     assert L.pent_group_destroy(None) == pb.OK
+
+
+def test_autotune_single_matrix(torch, tmp_path, monkeypatch):
+    """The tuner times every schedule on scratch memory, keeps the fastest,
+    records it in the cache file, and the tuned solve still matches the
+    oracle; a second handle of the same shape reads the cached choice."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("PENT_TUNE_CACHE", str(cache))
+    n, m, sigma = 1500, 700, 20.0
+    print_case(test="autotune", n=n, m=m)
+    F = np.random.Generator(np.random.PCG64(3)).uniform(-1, 1, (n, m))
+    ref = oracle.solve(oracle.assemble_d4(n, sigma), F)
+    with pb.Plan.factor_d4(n, sigma) as p:
+        kind, seg, ms = p.autotune(m)
+        assert kind in (1, 2, 3) and ms > 0
+        assert p.schedule_for(m)[0] == kind
+        T = torch.from_numpy(F).cuda()
+        p.solve_(T)
+        torch.cuda.synchronize()
+        assert np.all(colerr(T.cpu().numpy(), ref) <= d4_tol(sigma))
+    lines = cache.read_text().split()
+    assert lines[:2] == [str(n), str(m)] and int(lines[2]) == kind
+    with pb.Plan.factor_d4(n, sigma) as q:
+        assert q.autotune(m)[:2] == (kind, seg)
+
+
+def test_autotune_group_keeps_data(torch):
+    print_case(test="group_autotune")
+    shapes = [(0.3, 700, 100), (5e3, 2000, 64), (1.0, 64, 8)]
+    mats, plans, Ts = make(torch, shapes, seed=21)
+    before = [T.clone() for T in Ts]
+    g = pb.Group(plans)
+    g.solve_(Ts)                     # bind the caller's buffers first
+    torch.cuda.synchronize()
+    after_one = [T.clone() for T in Ts]
+    v, ms = g.autotune(Ts)
+    assert 0 <= v < 4 and ms > 0
+    for a, T in zip(after_one, Ts):
+        assert torch.equal(a, T)     # tuning ran on scratch blocks
+    g.solve_(Ts)
+    torch.cuda.synchronize()
+    refs = workloads.group_run(mats, 2)
+    for (sigma, _), T, ref in zip(mats, Ts, refs):
+        assert np.all(colerr(T.cpu().numpy(), ref) <= 2 * d4_tol(sigma))
+    del before
+    g.close()
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_group_every_variant(torch, variant):
+    """Each persistent-kernel variant (64 or 32 rows per segment, 8 or 4
+    waves per workgroup) against the oracle, two steps."""
+    print_case(test="group_variant", variant=variant)
+    shapes = [(1e2, 333, 65), (2.0, 4097, 64), (1e4, 100, 7), (0.1, 8192, 3)]
+    mats, plans, Ts = make(torch, shapes, seed=31 + variant)
+    g = pb.Group(plans)
+    g.set_variant(variant)
+    g.solve_(Ts)
+    g.solve_(Ts)
+    torch.cuda.synchronize()
+    refs = workloads.group_run(mats, 2)
+    for (sigma, _), T, ref in zip(mats, Ts, refs):
+        assert np.all(colerr(T.cpu().numpy(), ref) <= 2 * d4_tol(sigma))
+    g.close()
