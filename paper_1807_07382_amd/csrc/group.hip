@@ -116,38 +116,8 @@ __global__ __launch_bounds__(64 * kGroupWaves) void k_group(const GroupMat *__re
         __threadfence_block();
         __syncthreads();
 
-        // interface recurrence (wave 0, lane = system): y forward, z backward
-        if (w == 0) {
-            double y0 = 0.0, y1 = 0.0;
-            for (int sg = 0; sg < nseg; sg++) {
-                GDbl o = S + (int64_t)sg * 256 + lane;
-                const double e0 = o[0], e1 = o[64];
-                o[0] = y0;
-                o[64] = y1;
-                const double t0 = segr[sg].tf[0], t1 = segr[sg].tf[1], t2 = segr[sg].tf[2],
-                             t3 = segr[sg].tf[3];
-                const double n0 = e0 + fma(t0, y0, t2 * y1);
-                const double n1 = e1 + fma(t1, y0, t3 * y1);
-                y0 = n0;
-                y1 = n1;
-            }
-            double z0 = 0.0, z1 = 0.0;
-            for (int sg = nseg - 1; sg >= 0; sg--) {
-                GDbl o = S + (int64_t)sg * 256 + lane;
-                const double b0 = o[128], b1 = o[192];
-                const double ys0 = o[0], ys1 = o[64];
-                o[128] = z0;
-                o[192] = z1;
-                const double c0 = segr[sg].cg[0], c1 = segr[sg].cg[1], c2 = segr[sg].cg[2],
-                             c3 = segr[sg].cg[3];
-                const double u0 = segr[sg].tb[0], u1 = segr[sg].tb[1], u2 = segr[sg].tb[2],
-                             u3 = segr[sg].tb[3];
-                const double n0 = b0 + fma(c0, ys0, c2 * ys1) + fma(u0, z0, u2 * z1);
-                const double n1 = b1 + fma(c1, ys0, c3 * ys1) + fma(u1, z0, u3 * z1);
-                z0 = n0;
-                z1 = n1;
-            }
-        }
+        // interface recurrence (wave 0, lane = system)
+        if (w == 0) interface_chain(S + lane, (int64_t)256, (int64_t)64, segr, (int64_t)nseg);
         __threadfence_block();
         __syncthreads();
 

@@ -108,6 +108,73 @@ struct pent_plan {
 
 namespace pent {
 
+// Serial interface recurrence over the segments of one system (one lane per
+// system), shared by the partitioned and group kernels:
+//   y_0 = 0,       y_{s+1} = e_s + Tf_s y_s
+//   z_{S-1} = 0,   z_{s-1} = b_s + Cg_s y_s + Tb_s z_s
+// Summary q of segment s lives at sum[s*sstride + q*qstride]; on entry it
+// holds (e_s, b_s), on exit the incoming states (y_s, z_s).  The loads of a
+// chunk of segments are issued before its arithmetic, so a chunk costs one
+// memory latency instead of one per segment.
+template <typename DP, typename SP>
+__device__ __forceinline__ void interface_chain(DP sum, int64_t sstride, int64_t qstride,
+                                                SP seg, int64_t nseg)
+{
+    constexpr int CH = 8;
+    double y0 = 0.0, y1 = 0.0;
+    for (int64_t s0 = 0; s0 < nseg; s0 += CH) {
+        double e0[CH], e1[CH];
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            if (s0 + k < nseg) {
+                e0[k] = sum[(s0 + k) * sstride];
+                e1[k] = sum[(s0 + k) * sstride + qstride];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            if (s0 + k < nseg) {
+                const int64_t s = s0 + k;
+                sum[s * sstride] = y0;
+                sum[s * sstride + qstride] = y1;
+                const double t0 = seg[s].tf[0], t1 = seg[s].tf[1], t2 = seg[s].tf[2], t3 = seg[s].tf[3];
+                const double n0 = e0[k] + fma(t0, y0, t2 * y1);
+                const double n1 = e1[k] + fma(t1, y0, t3 * y1);
+                y0 = n0;
+                y1 = n1;
+            }
+        }
+    }
+    double z0 = 0.0, z1 = 0.0;
+    for (int64_t s1 = nseg - 1; s1 >= 0; s1 -= CH) {
+        double b0[CH], b1[CH], ys0[CH], ys1[CH];
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            if (s1 - k >= 0) {
+                const int64_t s = s1 - k;
+                ys0[k] = sum[s * sstride];
+                ys1[k] = sum[s * sstride + qstride];
+                b0[k] = sum[s * sstride + 2 * qstride];
+                b1[k] = sum[s * sstride + 3 * qstride];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < CH; k++) {
+            if (s1 - k >= 0) {
+                const int64_t s = s1 - k;
+                sum[s * sstride + 2 * qstride] = z0;
+                sum[s * sstride + 3 * qstride] = z1;
+                const double c0 = seg[s].cg[0], c1 = seg[s].cg[1], c2 = seg[s].cg[2], c3 = seg[s].cg[3];
+                const double u0 = seg[s].tb[0], u1 = seg[s].tb[1], u2 = seg[s].tb[2], u3 = seg[s].tb[3];
+                const double n0 = b0[k] + fma(c0, ys0[k], c2 * ys1[k]) + fma(u0, z0, u2 * z1);
+                const double n1 = b1[k] + fma(c1, ys0[k], c3 * ys1[k]) + fma(u1, z0, u3 * z1);
+                z0 = n0;
+                z1 = n1;
+            }
+        }
+    }
+}
+
 constexpr uint64_t kMagic = 0x70656e7462617463ull;  // "pentbatc"
 
 // ---- launchers (each returns a hipError_t from the launch) ----

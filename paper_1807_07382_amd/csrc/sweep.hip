@@ -258,41 +258,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void k_
     o[3 * summ_ld] = q2;
 }
 
-// Serial interface recurrence, one lane per system:
-//   y_0 = 0,       y_{s+1} = e_s + Tf_s y_s
-//   z_{S-1} = 0,   z_{s-1} = b_s + Cg_s y_s + Tb_s z_s
+// Serial interface recurrence (interface_chain), one lane per system.
 __global__ __launch_bounds__(256) void k_part_chain(const SegRec *__restrict__ seg, int64_t nseg,
                                                     double *__restrict__ summ, int64_t summ_ld,
                                                     int64_t batch)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= batch) return;
-    double *c = summ + j;
-    double y0 = 0.0, y1 = 0.0;
-    for (int64_t s = 0; s < nseg; s++) {
-        double *o = c + s * 4 * summ_ld;
-        const double e0 = o[0], e1 = o[summ_ld];
-        o[0] = y0;
-        o[summ_ld] = y1;
-        const SegRec &t = seg[s];
-        const double n0 = e0 + fma(t.tf[0], y0, t.tf[2] * y1);
-        const double n1 = e1 + fma(t.tf[1], y0, t.tf[3] * y1);
-        y0 = n0;
-        y1 = n1;
-    }
-    double z0 = 0.0, z1 = 0.0;
-    for (int64_t s = nseg - 1; s >= 0; s--) {
-        double *o = c + s * 4 * summ_ld;
-        const double b0 = o[2 * summ_ld], b1 = o[3 * summ_ld];
-        const double ys0 = o[0], ys1 = o[summ_ld];
-        o[2 * summ_ld] = z0;
-        o[3 * summ_ld] = z1;
-        const SegRec &t = seg[s];
-        const double n0 = b0 + fma(t.cg[0], ys0, t.cg[2] * ys1) + fma(t.tb[0], z0, t.tb[2] * z1);
-        const double n1 = b1 + fma(t.cg[1], ys0, t.cg[3] * ys1) + fma(t.tb[1], z0, t.tb[3] * z1);
-        z0 = n0;
-        z1 = n1;
-    }
+    interface_chain(summ + j, 4 * summ_ld, summ_ld, seg, nseg);
 }
 
 // Pass 2 reads f (type TI, leading dimension ldf) and writes x (FP64,
