@@ -15,7 +15,7 @@ N=8192 with 131072 right-hand sides, sigma=1e2.
 Other workloads (for tuning runs): ``plain`` (N=256, 256 RHS), ``precision``
 (all three sigma), ``shape`` (any n / batch), ``copy`` (device copy),
 ``group`` (48 matrices, 200 graph-captured steps, persistent launch vs one
-solve per matrix).
+solve per matrix), ``cahn2d`` (2-D split-implicit Cahn-Hilliard, 1024^2 x 32).
 """
 from __future__ import annotations
 
@@ -288,6 +288,45 @@ def run_group(args, torch):
                                 speedup_of_persistent=res[1]["ms"] / res[0]["ms"]))
 
 
+def run_cahn2d(args, torch):
+    """2-D split-implicit Cahn-Hilliard: 1024 x 1024 grid, 32 instances,
+    sigma = 200, 50 steps; every step = explicit stencil, 32768 x sweeps
+    (system-major) and 32768 y sweeps (batch-fastest), N = 1024."""
+    from paper_1807_07382_amd import inputs
+    from paper_1807_07382_amd import pentbatch as pb
+    from oracle import workloads
+    w = inputs.cahn2d()
+    n, ninst, sigma = w["nx"], w["ninst"], w["sigma"]
+    steps = args.steps if args.steps != 100 else inputs.CAHN2D["steps"]
+    h = 1.0 / n
+    gam = w["gammas"]
+    dt = torch.from_numpy(sigma * h ** 4 / gam).cuda()
+    C0 = torch.from_numpy(w["C0"]).cuda()
+    C = C0.clone()
+    R = torch.empty_like(C)
+    stream = torch.cuda.current_stream()
+    plan = pb.Plan.factor_d4(n, sigma)
+    for _ in range(args.warmup):
+        pb.ch2d_step(plan, plan, C, R, dt, h, stream)
+    C.copy_(C0)
+    ms = _timed(torch, stream, lambda: pb.ch2d_step(plan, plan, C, R, dt, h, stream), steps)
+    # parity of one instance after `steps` steps
+    sub = np.ascontiguousarray(w["C0"][:, :1, :])
+    ref = workloads.ch_run(sub, gam[:1], sigma, steps)
+    err = float(np.max(np.abs(C[:, :1, :].cpu().numpy() - ref)) / np.max(np.abs(ref)))
+    plan.close()
+    points = n * n * ninst
+    alg = 3 * BYTES_PER_UNKNOWN_FP64 * points  # stencil pass + two solves
+    gbs = alg / (ms / 1e3) / 1e9
+    return dict(metric=METRIC, value=2 * n * ninst / (ms / 1e3), unit="RHS-solves/s", n_gpus=1,
+                steps=steps, warmup=args.warmup, ms_per_step=ms, higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+                config=dict(workload="cahn2d", grid=[n, n], instances=ninst, sigma=sigma),
+                roofline=dict(bound="hbm", achieved=gbs, peak=PEAK_HBM_GBS, unit="GB/s",
+                              frac=gbs / PEAK_HBM_GBS, traffic=None),
+                parity=dict(instance=0, max_rel_err_vs_oracle=err))
+
+
 def run_plain(args, torch):
     from paper_1807_07382_amd import inputs
     from paper_1807_07382_amd import pentbatch as pb
@@ -381,7 +420,8 @@ def run_shape(args, torch):
 
 
 WORKLOADS = {"hyperdiff": run_hyperdiff, "plain": run_plain, "copy": run_copy,
-             "shape": run_shape, "precision": run_precision, "group": run_group}
+             "shape": run_shape, "precision": run_precision, "group": run_group,
+             "cahn2d": run_cahn2d}
 
 
 def main(argv=None):

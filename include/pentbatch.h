@@ -51,7 +51,8 @@ typedef enum pent_status {
     PENT_HIP_ERROR = 4,     /* a HIP runtime call or kernel launch failed */
     PENT_NOT_CONVERGED = 5, /* refinement did not reach its tolerance */
     PENT_SIZE_MISMATCH = 6, /* buffers of one call disagree in size */
-    PENT_NOT_SUPPORTED = 7  /* a valid request this build does not handle */
+    PENT_NOT_SUPPORTED = 7, /* a valid request this build does not handle */
+    PENT_TIMEOUT = 8        /* a bounded device-side wait ran out (see pent_group_check) */
 } pent_status;
 
 /* ---------------------------------------------------------------- factor --
@@ -173,10 +174,18 @@ int pent_group_destroy(pent_group g); /* NULL is a no-op */
 int pent_group_autotune(pent_group g, const int64_t *batch, int *variant_out, double *ms_out,
                         void *stream);
 
-/* Force the persistent kernel variant (0..3: 64/32/64/32 rows per segment
- * with 8/8/4/4 waves per workgroup) for later mode-0 solves (tests and
- * manual tuning).  PENT_INVALID_VALUE for an unknown variant. */
+/* Force the persistent kernel variant for later mode-0 solves (tests and
+ * manual tuning).  0..3: one workgroup per work item, 64/32/64/32 rows per
+ * segment with 8/8/4/4 waves; 4, 5: one-wave tasks (item, segment) drawn
+ * independently, 64/32 rows per segment, pass-2 tasks waiting (bounded) on
+ * a per-item flag the last pass-1 task sets.  PENT_INVALID_VALUE for an
+ * unknown variant. */
 int pent_group_set_variant(pent_group g, int variant);
+
+/* Blocking check of the group's device status after its solves: PENT_OK, or
+ * PENT_TIMEOUT if a bounded wait of variants 4/5 ran out (then results of
+ * that launch are incomplete). */
+int pent_group_check(pent_group g);
 
 /* Capture `steps` consecutive group solves (mode as above) on `stream` into
  * an executable HIP graph (one graph launch = `steps` implicit time steps).
@@ -188,6 +197,25 @@ pent_graph pent_group_capture(pent_group g, double *const *F, const int64_t *bat
                               size_t work_bytes, void *stream);
 int pent_graph_launch(pent_graph gr, void *stream);
 int pent_graph_destroy(pent_graph gr); /* NULL is a no-op */
+
+/* ------------------------------------------ 2-D Cahn-Hilliard workload --
+ * Split-implicit step of the 2-D Cahn-Hilliard equation on ninst independent
+ * ny x nx grids (the semi-implicit scheme of Sec. 2.1 applied direction by
+ * direction; Sec. 4 names this alternating-direction route to 2-D).
+ * C, R: DEVICE FP64, layout [y][inst][x] contiguous (element (y, k, x) at
+ * (y*ninst + k)*nx + x); dt: DEVICE, ninst time steps; h: grid spacing.
+ * pent_ch2d_rhs:  R = C + dt_k * Lap_h(C^3 - C) (5-point Laplacian, zero
+ *                 values outside the grid); C and R must not overlap.
+ * pent_ch2d_step: R = the right-hand side above, then the x sweeps
+ *                 (I + sigma D4_x) R* = R in place (hx: n = nx, system-major),
+ *                 then the y sweeps (I + sigma D4_y) C = R* (hy: n = ny,
+ *                 batch-fastest over ninst*nx systems), so C holds the next
+ *                 state and R is scratch.  May allocate stream-ordered
+ *                 scratch.  Limits: ny, ninst <= 65535. */
+int pent_ch2d_rhs(const double *C, double *R, int64_t ny, int64_t ninst, int64_t nx,
+                  const double *dt, double h, void *stream);
+int pent_ch2d_step(pent_handle hx, pent_handle hy, double *C, double *R, int64_t ny,
+                   int64_t ninst, int64_t nx, const double *dt, double h, void *stream);
 
 /* ----------------------------------------------------------- inspection --
  * Copy the handle's data to HOST arrays of n doubles each (blocking).

@@ -247,6 +247,26 @@ int solve_io(pent_plan *h, const void *f, bool f32, int64_t ldf, double *x, int6
                                            f32, ldf, x, ldx, batch, (double *)summ, summ_ld, s));
 }
 
+// solve_io with its scratch taken from the stream-ordered allocator.
+int solve_io_scratch(pent_plan *h, const double *f, int64_t ldf, double *x, int64_t ldx,
+                     int64_t batch, hipStream_t s)
+{
+    int kind, seg_rows;
+    io_schedule(h, batch, (const void *)f == (const void *)x && ldf == ldx, &kind, &seg_rows);
+    const size_t bytes = summ_bytes(h, kind, seg_rows, batch);
+    void *summ = nullptr;
+    if (bytes) {
+        hipError_t e = hipMallocAsync(&summ, bytes, s);
+        if (e != hipSuccess) return hip_status(e);
+    }
+    const int st = solve_io(h, f, false, ldf, x, ldx, batch, summ, s);
+    if (summ) {
+        hipError_t e = hipFreeAsync(summ, s);
+        if (st == PENT_OK && e != hipSuccess) return hip_status(e);
+    }
+    return st;
+}
+
 constexpr int kMaxRefine = 16;
 
 }  // namespace
@@ -263,7 +283,12 @@ struct pent_group_s {
     GroupItem *d_items = nullptr;
     int nitems = 0;
     int64_t summ_doubles = 0;
-    unsigned int *d_ctr = nullptr;  // [next item, workgroups done]
+    unsigned int *d_ctr = nullptr;  // [next item/task, workgroups done, wait timed out]
+    int2 *d_tasks64 = nullptr;      // (item, segment) task lists of the decoupled variants
+    int2 *d_tasks32 = nullptr;
+    int ntasks64 = 0, ntasks32 = 0;
+    unsigned int *d_cnt = nullptr;  // per-item pass-1 completion count
+    unsigned int *d_ready = nullptr;  // per-item interface-ready flag
     int variant = 0;                // group kernel variant (autotuned)
 };
 
@@ -285,6 +310,10 @@ void free_group(pent_group g)
     if (g->d_mats) (void)hipFree(g->d_mats);
     if (g->d_items) (void)hipFree(g->d_items);
     if (g->d_ctr) (void)hipFree(g->d_ctr);
+    if (g->d_tasks64) (void)hipFree(g->d_tasks64);
+    if (g->d_tasks32) (void)hipFree(g->d_tasks32);
+    if (g->d_cnt) (void)hipFree(g->d_cnt);
+    if (g->d_ready) (void)hipFree(g->d_ready);
     g->magic = 0;
     delete g;
 }
@@ -353,23 +382,52 @@ int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64
         it.summ_off = off;
         off += (mats[it.mat].n + 63) / 64 * 256;
     }
-    if (items.size() > (size_t)INT32_MAX) return PENT_NOT_SUPPORTED;
+    if (items.size() > (size_t)INT32_MAX / 2) return PENT_NOT_SUPPORTED;
+    // task lists of the decoupled variants, items in work-list order
+    std::vector<int2> t64, t32;
+    for (size_t i = 0; i < items.size(); i++) {
+        const int64_t n = mats[items[i].mat].n;
+        for (int64_t sg = 0; sg < (n + 63) / 64; sg++) t64.push_back(make_int2((int)i, (int)sg));
+        for (int64_t sg = 0; sg < (n + 31) / 32; sg++) t32.push_back(make_int2((int)i, (int)sg));
+    }
+    if (t32.size() > (size_t)INT32_MAX / 2) return PENT_NOT_SUPPORTED;
     GroupMat *dm = nullptr;
     GroupItem *di = nullptr;
+    int2 *d64 = nullptr, *d32 = nullptr;
+    unsigned int *dc = nullptr, *dr = nullptr;
+    const size_t ni = std::max<size_t>(items.size(), 1);
     hipError_t e = hipMalloc(&dm, sizeof(GroupMat) * std::max<size_t>(cnt, 1));
-    if (e == hipSuccess) e = hipMalloc(&di, sizeof(GroupItem) * std::max<size_t>(items.size(), 1));
+    if (e == hipSuccess) e = hipMalloc(&di, sizeof(GroupItem) * ni);
+    if (e == hipSuccess) e = hipMalloc(&d64, sizeof(int2) * std::max<size_t>(t64.size(), 1));
+    if (e == hipSuccess) e = hipMalloc(&d32, sizeof(int2) * std::max<size_t>(t32.size(), 1));
+    if (e == hipSuccess) e = hipMalloc(&dc, sizeof(unsigned int) * ni);
+    if (e == hipSuccess) e = hipMalloc(&dr, sizeof(unsigned int) * ni);
     if (e == hipSuccess && cnt) e = hipMemcpy(dm, mats.data(), sizeof(GroupMat) * cnt, hipMemcpyHostToDevice);
     if (e == hipSuccess && !items.empty())
         e = hipMemcpy(di, items.data(), sizeof(GroupItem) * items.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !t64.empty())
+        e = hipMemcpy(d64, t64.data(), sizeof(int2) * t64.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && !t32.empty())
+        e = hipMemcpy(d32, t32.data(), sizeof(int2) * t32.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_zero_u32(dc, (int)ni, 0);
+    if (e == hipSuccess) e = launch_zero_u32(dr, (int)ni, 0);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
-        if (dm) (void)hipFree(dm);
-        if (di) (void)hipFree(di);
+        for (void *q : {(void *)dm, (void *)di, (void *)d64, (void *)d32, (void *)dc, (void *)dr})
+            if (q) (void)hipFree(q);
         return hip_status(e);
     }
-    if (g->d_mats) (void)hipFree(g->d_mats);
-    if (g->d_items) (void)hipFree(g->d_items);
+    for (void *q : {(void *)g->d_mats, (void *)g->d_items, (void *)g->d_tasks64,
+                    (void *)g->d_tasks32, (void *)g->d_cnt, (void *)g->d_ready})
+        if (q) (void)hipFree(q);
     g->d_mats = dm;
     g->d_items = di;
+    g->d_tasks64 = d64;
+    g->d_tasks32 = d32;
+    g->ntasks64 = (int)t64.size();
+    g->ntasks32 = (int)t32.size();
+    g->d_cnt = dc;
+    g->d_ready = dr;
     g->nitems = (int)items.size();
     g->summ_doubles = 2 * off;
     g->F.assign(F, F + cnt);
@@ -384,9 +442,15 @@ int group_enqueue(pent_group g, int mode, void *work, hipStream_t s)
 {
     if (mode == 0) {
         if (g->nitems == 0) return PENT_OK;
-        const int nblocks = std::max(1, std::min(g->nitems, group_max_blocks(g->variant)));
-        return hip_status(launch_group(g->variant, g->d_mats, g->d_items, g->nitems,
-                                       (double *)work, g->d_ctr, nblocks, s));
+        const int v = g->variant;
+        const bool tasks = group_variant_is_tasks(v);
+        const bool k64 = group_variant_seg_rows(v) == 64;
+        const int ntasks = k64 ? g->ntasks64 : g->ntasks32;
+        const int units = tasks ? 2 * ntasks : g->nitems;
+        const int nblocks = std::max(1, std::min(units, group_max_blocks(v)));
+        return hip_status(launch_group(v, g->d_mats, g->d_items, g->nitems,
+                                       k64 ? g->d_tasks64 : g->d_tasks32, ntasks, (double *)work,
+                                       g->d_ctr, g->d_cnt, g->d_ready, nblocks, s));
     }
     for (size_t k = 0; k < g->plans.size(); k++) {
         if (g->batch[k] == 0) continue;
@@ -554,31 +618,7 @@ int pent_solve(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream
     if (!valid(h) || batch < 0 || ld < batch) return ret(PENT_INVALID_VALUE);
     if (batch == 0) return ret(PENT_OK);
     if (!F) return ret(PENT_INVALID_VALUE);
-    hipStream_t s = (hipStream_t)stream;
-    int kind, seg_rows;
-    choose_schedule(h, batch, &kind, &seg_rows);
-    if (kind == 2 && (h->n + seg_rows - 1) / seg_rows > 65535) kind = 1;
-    if (kind == 1) return ret(hip_status(launch_lane_sweep(h->d_fwd, h->d_bwd, h->n, F, batch, ld, s)));
-    int st;
-    if (kind == 3) {
-        const int rows = tile_rows_for(h->n);
-        const ScanRec *scan;
-        const double *trec;
-        if (!tile_cache(h, rows, &scan, &trec, &st)) return ret(st);
-        return ret(hip_status(launch_tile_sweep(trec, scan, h->n, rows, F, batch, ld, s)));
-    }
-    const SegRec *seg = seg_cache(h, seg_rows, &st);
-    if (!seg) return ret(st);
-    const int64_t nseg = (h->n + seg_rows - 1) / seg_rows;
-    const int64_t summ_ld = (batch + 63) / 64 * 64;
-    double *summ = nullptr;
-    hipError_t e = hipMallocAsync((void **)&summ, sizeof(double) * 4 * nseg * summ_ld, s);
-    if (e != hipSuccess) return ret(hip_status(e));
-    e = launch_part_sweep(h->d_fwd, h->d_bwd, seg, h->n, h->npad, seg_rows, F, batch, ld, summ,
-                          summ_ld, s);
-    hipError_t e2 = hipFreeAsync(summ, s);
-    if (e == hipSuccess) e = e2;
-    return ret(hip_status(e));
+    return ret(solve_io_scratch(h, F, ld, F, ld, batch, (hipStream_t)stream));
 }
 
 size_t pent_mixed_workspace_size(pent_handle h, int64_t batch, int refine_steps, int want_eta)
@@ -674,7 +714,7 @@ pent_group pent_group_create(const pent_handle *hs, int64_t count)
     }
     g->plans.assign(hs, hs + count);
     hipError_t e = hipGetDevice(&g->device);
-    if (e == hipSuccess) e = hipMalloc(&g->d_ctr, 2 * sizeof(unsigned int));
+    if (e == hipSuccess) e = hipMalloc(&g->d_ctr, 3 * sizeof(unsigned int));
     if (e == hipSuccess) e = launch_group_init(g->d_ctr, 0);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -837,6 +877,15 @@ int pent_group_set_variant(pent_group g, int variant)
     return ret(PENT_OK);
 }
 
+int pent_group_check(pent_group g)
+{
+    if (!gvalid(g)) return ret(PENT_INVALID_VALUE);
+    unsigned int flags[3] = {0, 0, 0};
+    hipError_t e = hipMemcpy(flags, g->d_ctr, sizeof(flags), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return ret(hip_status(e));
+    return ret(flags[2] ? PENT_TIMEOUT : PENT_OK);
+}
+
 int pent_group_destroy(pent_group g)
 {
     if (!g) return ret(PENT_OK);
@@ -912,6 +961,28 @@ int pent_graph_destroy(pent_graph gr)
     gr->magic = 0;
     delete gr;
     return ret(PENT_OK);
+}
+
+int pent_ch2d_rhs(const double *C, double *R, int64_t ny, int64_t ninst, int64_t nx,
+                  const double *dt, double h, void *stream)
+{
+    if (!C || !R || !dt || ny < 1 || ninst < 1 || nx < 1 || !(h > 0.0) || ny > 65535 ||
+        ninst > 65535 || C == R)
+        return ret(PENT_INVALID_VALUE);
+    return ret(hip_status(launch_ch2d_rhs(C, R, ny, ninst, nx, dt, h, (hipStream_t)stream)));
+}
+
+int pent_ch2d_step(pent_handle hx, pent_handle hy, double *C, double *R, int64_t ny,
+                   int64_t ninst, int64_t nx, const double *dt, double h, void *stream)
+{
+    if (!valid(hx) || !valid(hy) || hx->n != nx || hy->n != ny) return ret(PENT_INVALID_VALUE);
+    int st = pent_ch2d_rhs(C, R, ny, ninst, nx, dt, h, stream);
+    if (st != PENT_OK) return st;
+    // x sweeps: system (y, k) is nx contiguous values
+    st = pent_solve_strided(hx, R, ny * ninst, nx, stream);
+    if (st != PENT_OK) return st;
+    // y sweeps: batch-fastest over (k, x), read from R, written into C
+    return ret(solve_io_scratch(hy, R, ninst * nx, C, ninst * nx, ninst * nx, (hipStream_t)stream));
 }
 
 int pent_solve_strided(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream)
@@ -997,6 +1068,7 @@ const char *pent_status_string(int status)
     case PENT_NOT_CONVERGED: return "iterative refinement did not converge";
     case PENT_SIZE_MISMATCH: return "buffer sizes disagree";
     case PENT_NOT_SUPPORTED: return "not supported";
+    case PENT_TIMEOUT: return "a device-side wait ran out (work list not drained)";
     default: return "unknown status";
     }
 }

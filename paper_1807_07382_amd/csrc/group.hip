@@ -157,6 +157,121 @@ __global__ __launch_bounds__(64 * kGroupWaves) void k_group(const GroupMat *__re
     }
 }
 
+// Decoupled variant: one-wave workgroups, each pulling (item, segment)
+// tasks from one counter.  Tasks [0, T) are pass 1 of every segment of every
+// item (items longest first), tasks [T, 2T) pass 2 in the same order.  The
+// wave that completes the last pass-1 task of an item runs the item's
+// interface recurrence and then publishes ready[item]; a pass-2 task waits
+// for that flag.  Every pass-2 task is handed out only after all pass-1
+// tasks have been handed to running waves, and those never wait on
+// anything, so every flag is eventually published; the wait is bounded
+// anyway and a timeout is reported through ctr[2] instead of hanging.
+constexpr int kSpinLimit = 1 << 24;
+
+template <int kGK>
+__global__ __launch_bounds__(64) void k_group_tasks(const GroupMat *__restrict__ mats,
+                                                    const GroupItem *__restrict__ items,
+                                                    const int2 *__restrict__ tasks, int ntasks,
+                                                    int nitems, double *__restrict__ summ,
+                                                    unsigned int *__restrict__ ctr,
+                                                    unsigned int *__restrict__ cnt,
+                                                    unsigned int *__restrict__ ready)
+{
+    const int lane = threadIdx.x;
+    for (;;) {
+        unsigned int t0 = 0;
+        if (lane == 0) t0 = atomicAdd(&ctr[0], 1u);
+        const int t = __builtin_amdgcn_readfirstlane((int)t0);
+        if (t >= 2 * ntasks) break;
+        const bool pass1 = t < ntasks;
+        const int2 task = tasks[pass1 ? t : t - ntasks];
+        const int ii = __builtin_amdgcn_readfirstlane(task.x);
+        const int sg = __builtin_amdgcn_readfirstlane(task.y);
+        const GroupItem item = items[ii];
+        const GroupMat m = mats[item.mat];
+        const CFwd fwd = (CFwd)m.fwd;
+        const CBwd bwd = (CBwd)m.bwd;
+        const CSeg segr = (CSeg)(kGK == 64 ? m.seg64 : m.seg32);
+        const int64_t n = m.n;
+        const int nseg = (int)((n + kGK - 1) / kGK);
+        const bool act = lane < item.ncols;
+        const int64_t j = item.col0 + (act ? lane : 0);
+        GDbl col = (GDbl)m.F + j;
+        GDbl S = (GDbl)summ + item.summ_off * (64 / kGK);
+        const int64_t r0 = (int64_t)sg * kGK;
+        const int L = (int)((n - r0) < kGK ? (n - r0) : kGK);
+        GDbl base = col + r0 * m.ld;
+        GDbl o = S + (int64_t)sg * 256 + lane;
+        double v[kGK];
+        if (pass1) {
+            load_seg(v, base, m.ld, act ? L : 0);
+            double p2 = 0.0, p1 = 0.0, q1 = 0.0, q2 = 0.0;
+            fwd_seg(v, fwd, r0, p2, p1);
+            bwd_seg(v, bwd, r0, q1, q2);
+            o[0] = p2;
+            o[64] = p1;
+            o[128] = q1;
+            o[192] = q2;
+            __threadfence();  // summaries visible before the count
+            unsigned int c0 = 0;
+            if (lane == 0) c0 = atomicAdd(&cnt[ii], 1u);
+            const int c = __builtin_amdgcn_readfirstlane((int)c0);
+            if (c == nseg - 1) {  // last segment of this item: resolve its interfaces
+                __threadfence();
+                interface_chain(S + lane, (int64_t)256, (int64_t)64, segr, (int64_t)nseg);
+                __threadfence();
+                if (lane == 0) __hip_atomic_store(&ready[ii], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        } else {
+            int spins = 0;
+            unsigned int rdy = 0;
+            for (;;) {
+                if (lane == 0) rdy = __hip_atomic_load(&ready[ii], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                if (__builtin_amdgcn_readfirstlane((int)rdy) != 0) break;
+                if (++spins >= kSpinLimit) break;
+                __builtin_amdgcn_s_sleep(2);
+            }
+            if (spins >= kSpinLimit) {
+                if (lane == 0) atomicExch(&ctr[2], 1u);
+                continue;
+            }
+            __threadfence();
+            load_seg(v, base, m.ld, act ? L : 0);
+            double p2 = o[0], p1 = o[64], q1 = o[128], q2 = o[192];
+            fwd_seg(v, fwd, r0, p2, p1);
+            bwd_seg(v, bwd, r0, q1, q2);
+            if (act) {
+                if (L == kGK) {
+#pragma unroll
+                    for (int k = 0; k < kGK; k++) __builtin_nontemporal_store(v[k], base + k * m.ld);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < kGK; k++)
+                        if (k < L) base[k * m.ld] = v[k];
+                }
+            }
+        }
+    }
+    // last wave out resets the counters and flags for the next launch
+    if (lane == 0) __threadfence();
+    unsigned int d0 = 0;
+    if (lane == 0) d0 = atomicAdd(&ctr[1], 1u);
+    const unsigned int d = (unsigned int)__builtin_amdgcn_readfirstlane((int)d0);
+    if (d == gridDim.x - 1) {
+        __threadfence();
+        for (int i = lane; i < nitems; i += 64) {
+            cnt[i] = 0u;
+            ready[i] = 0u;
+        }
+        __threadfence();
+        if (lane == 0) {
+            atomicExch(&ctr[0], 0u);
+            atomicExch(&ctr[1], 0u);
+        }
+        __threadfence();
+    }
+}
+
 __global__ void k_zero_u32(unsigned int *p, int count)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -165,14 +280,22 @@ __global__ void k_zero_u32(unsigned int *p, int count)
 
 }  // namespace
 
-int group_variants() { return 4; }
+// variants 0..3: one workgroup per item (64/32 rows, 8/4 waves);
+// variants 4, 5: decoupled one-wave tasks (64/32 rows).
+int group_variants() { return 6; }
 
-// variant -> (rows per segment, waves per workgroup)
 static void variant_shape(int v, int *K, int *W)
 {
+    if (v >= 4) {
+        *K = v == 4 ? 64 : 32;
+        *W = 1;
+        return;
+    }
     *K = (v & 1) ? 32 : 64;
     *W = (v & 2) ? 4 : 8;
 }
+
+bool group_variant_is_tasks(int v) { return v >= 4; }
 
 int group_variant_seg_rows(int v)
 {
@@ -187,7 +310,9 @@ static const void *variant_fn(int v)
     case 0: return (const void *)k_group<64, 8>;
     case 1: return (const void *)k_group<32, 8>;
     case 2: return (const void *)k_group<64, 4>;
-    default: return (const void *)k_group<32, 4>;
+    case 3: return (const void *)k_group<32, 4>;
+    case 4: return (const void *)k_group_tasks<64>;
+    default: return (const void *)k_group_tasks<32>;
     }
 }
 
@@ -204,12 +329,20 @@ int group_max_blocks(int v)
 
 hipError_t launch_group_init(unsigned int *ctr, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ctr, 2);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ctr, 3);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(unsigned int *p, int count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u32, dim3((count + 255) / 256), dim3(256), 0, s, p, count);
     return hipGetLastError();
 }
 
 hipError_t launch_group(int v, const GroupMat *mats, const GroupItem *items, int nitems,
-                        double *summ, unsigned int *ctr, int nblocks, hipStream_t s)
+                        const int2 *tasks, int ntasks, double *summ, unsigned int *ctr,
+                        unsigned int *cnt, unsigned int *ready, int nblocks, hipStream_t s)
 {
     int K, W;
     variant_shape(v, &K, &W);
@@ -218,7 +351,15 @@ hipError_t launch_group(int v, const GroupMat *mats, const GroupItem *items, int
     case 0: hipLaunchKernelGGL((k_group<64, 8>), grid, block, 0, s, mats, items, nitems, summ, ctr); break;
     case 1: hipLaunchKernelGGL((k_group<32, 8>), grid, block, 0, s, mats, items, nitems, summ, ctr); break;
     case 2: hipLaunchKernelGGL((k_group<64, 4>), grid, block, 0, s, mats, items, nitems, summ, ctr); break;
-    default: hipLaunchKernelGGL((k_group<32, 4>), grid, block, 0, s, mats, items, nitems, summ, ctr); break;
+    case 3: hipLaunchKernelGGL((k_group<32, 4>), grid, block, 0, s, mats, items, nitems, summ, ctr); break;
+    case 4:
+        hipLaunchKernelGGL((k_group_tasks<64>), grid, block, 0, s, mats, items, tasks, ntasks, nitems,
+                           summ, ctr, cnt, ready);
+        break;
+    default:
+        hipLaunchKernelGGL((k_group_tasks<32>), grid, block, 0, s, mats, items, tasks, ntasks, nitems,
+                           summ, ctr, cnt, ready);
+        break;
     }
     return hipGetLastError();
 }

@@ -219,16 +219,26 @@ hipError_t launch_eta(const double *d_diag, const double *d_anorm, int64_t n, co
                       unsigned long long *acc, double *eta, hipStream_t s);
 hipError_t launch_anorm(const double *d_diag, int64_t n, double *d_anorm, hipStream_t s);
 
+// ---- 2-D Cahn-Hilliard explicit term (ch2d.hip) ----
+hipError_t launch_ch2d_rhs(const double *C, double *R, int64_t ny, int64_t ninst, int64_t nx,
+                           const double *dt, double h, hipStream_t s);
+
 // ---- group solve (group.hip) ----
 // Kernel variants (rows per segment x waves per workgroup), chosen by the
 // group autotuner.  Summary offsets in GroupItem are in units of the 64-row
 // variant; a 32-row variant scales them by 2.
 int group_variants();
+bool group_variant_is_tasks(int v);
 int group_variant_seg_rows(int v);
 int group_max_blocks(int v);  // co-resident workgroups of variant v on the current device
-hipError_t launch_group_init(unsigned int *ctr, hipStream_t s);
+hipError_t launch_group_init(unsigned int *ctr, hipStream_t s);  // ctr[0..2] = 0
+hipError_t launch_zero_u32(unsigned int *p, int count, hipStream_t s);
+// tasks: (item, segment) pairs of the variant's segment length, items in
+// work-list order; cnt / ready: one counter and one flag per item, zero on
+// entry and left zero on exit; ctr[2] becomes 1 if a wait timed out.
 hipError_t launch_group(int v, const GroupMat *mats, const GroupItem *items, int nitems,
-                        double *summ, unsigned int *ctr, int nblocks, hipStream_t s);
+                        const int2 *tasks, int ntasks, double *summ, unsigned int *ctr,
+                        unsigned int *cnt, unsigned int *ready, int nblocks, hipStream_t s);
 hipError_t launch_strided_sweep(const FwdRec *fwd, const BwdRec *bwd, int64_t n, double *F,
                                 int64_t batch, int64_t ld, hipStream_t s);
 

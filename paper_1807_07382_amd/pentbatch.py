@@ -24,6 +24,7 @@ HIP_ERROR = 4
 NOT_CONVERGED = 5
 SIZE_MISMATCH = 6
 NOT_SUPPORTED = 7
+TIMEOUT = 8
 
 # every symbol include/pentbatch.h declares: name -> (restype, argtypes)
 _P = ctypes.c_void_p
@@ -45,6 +46,7 @@ SIGNATURES = {
                               _I, _P, ctypes.c_size_t, _P]),
     "pent_group_destroy": (_I, [_P]),
     "pent_group_set_variant": (_I, [_P, _I]),
+    "pent_group_check": (_I, [_P]),
     "pent_group_capture": (_P, [_P, ctypes.POINTER(_P), ctypes.POINTER(_I64),
                                 ctypes.POINTER(_I64), _I, _I, _P, ctypes.c_size_t, _P]),
     "pent_graph_launch": (_I, [_P, _P]),
@@ -53,6 +55,8 @@ SIGNATURES = {
                            ctypes.POINTER(_D), _P]),
     "pent_group_autotune": (_I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I),
                                  ctypes.POINTER(_D), _P]),
+    "pent_ch2d_rhs": (_I, [_P, _P, _I64, _I64, _I64, _P, _D, _P]),
+    "pent_ch2d_step": (_I, [_P, _P, _P, _P, _I64, _I64, _I64, _P, _D, _P]),
     "pent_get_factors": (_I, [_P, _P, _P, _P, _P]),
     "pent_get_diagonals": (_I, [_P, _P, _P, _P, _P, _P]),
     "pent_size": (_I64, [_P]),
@@ -316,6 +320,10 @@ class Group:
     def set_variant(self, variant: int):
         _check(lib().pent_group_set_variant(self._g, int(variant)), "group_set_variant")
 
+    def check(self):
+        """Raise if a device-side wait of the last solves timed out."""
+        _check(lib().pent_group_check(self._g), "group_check")
+
     def autotune(self, Fs, stream=None):
         """Time the persistent kernel variants on scratch blocks shaped like
         ``Fs`` and keep the fastest; returns (variant, ms)."""
@@ -365,3 +373,29 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def ch2d_rhs(C, R, dt, h: float, stream=None):
+    """R = C + dt[k] * Lap_h(C^3 - C) for C, R of shape (ny, ninst, nx)
+    (cuda float64, contiguous) and dt of shape (ninst,)."""
+    ny, ninst, nx = C.shape
+    for t in (C, R):
+        if not t.is_contiguous() or t.shape != C.shape:
+            raise ValueError("C and R must be contiguous (ny, ninst, nx)")
+    if dt.numel() != ninst:
+        raise ValueError("one dt per instance")
+    _check(lib().pent_ch2d_rhs(_dptr(C, "float64"), _dptr(R, "float64"), ny, ninst, nx,
+                               _dptr(dt, "float64"), float(h), _stream_ptr(stream)), "ch2d_rhs")
+    return R
+
+
+def ch2d_step(plan_x: "Plan", plan_y: "Plan", C, R, dt, h: float, stream=None):
+    """One split-implicit Cahn-Hilliard step: C <- next state, R scratch."""
+    ny, ninst, nx = C.shape
+    for t in (C, R):
+        if not t.is_contiguous() or t.shape != C.shape:
+            raise ValueError("C and R must be contiguous (ny, ninst, nx)")
+    _check(lib().pent_ch2d_step(plan_x.handle, plan_y.handle, _dptr(C, "float64"),
+                                _dptr(R, "float64"), ny, ninst, nx, _dptr(dt, "float64"),
+                                float(h), _stream_ptr(stream)), "ch2d_step")
+    return C

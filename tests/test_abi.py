@@ -85,12 +85,14 @@ def test_destroy_null_is_noop():
     assert pb.lib().pent_last_status() == pb.OK
 
 
-@pytest.mark.parametrize("st", range(0, 9))
+@pytest.mark.parametrize("st", range(0, 10))
 def test_status_strings(st):
     s = pb.lib().pent_status_string(st)
     assert isinstance(s, bytes) and len(s) > 0
-    if st == 8:
+    if st == 9:
         assert s == b"unknown status"
+    else:
+        assert s != b"unknown status"
 
 
 def test_python_errors_on_bad_shapes():
