@@ -217,6 +217,47 @@ int pent_ch2d_rhs(const double *C, double *R, int64_t ny, int64_t ninst, int64_t
 int pent_ch2d_step(pent_handle hx, pent_handle hy, double *C, double *R, int64_t ny,
                    int64_t ninst, int64_t nx, const double *dt, double h, void *stream);
 
+/* ------------------------------------------------ periodic matrices --
+ * Cyclic pentadiagonal matrices (Sec. 2.3): the periodic fourth-derivative
+ * matrix wraps round the corners, so row i couples columns (i-2) mod n ..
+ * (i+2) mod n.  Solved by Navon's bordering (Sec. 2.3): with E the leading
+ * (n-2) x (n-2) block, k its two border columns, h^T its two border rows
+ * and C2 the trailing 2 x 2 block, the last two unknowns are
+ * [C2 - h^T E^{-1} k]^{-1} ((f_{n-2}, f_{n-1}) - h^T E^{-1} f^) and the rest
+ * E^{-1} f^ - (E^{-1} k)(x_{n-2}, x_{n-1}) (rows 0-based).  E is factored as
+ * in Sec. 2.4; E^{-1} k and the 2 x 2 inverse are computed once, at factor
+ * time.  Each solve runs one batched E-solve in place plus two light
+ * kernels; it needs no workspace beyond the E-solve's stream-ordered
+ * scratch.
+ *
+ * pent_cyclic_factor: a..e HOST FP64 arrays of length n, row-indexed and
+ *   wrapped: row i holds a[i] at column (i-2) mod n, b[i] at (i-1) mod n,
+ *   c[i] at i, d[i] at (i+1) mod n, e[i] at (i+2) mod n; every entry is
+ *   used.  n >= 5.  Copied; blocking.  NULL on failure: PENT_INVALID_VALUE,
+ *   PENT_ZERO_PIVOT (pent_last_pivot_row: the failing row of E, or n-2 when
+ *   the 2 x 2 bordered block is singular), PENT_OUT_OF_MEMORY,
+ *   PENT_HIP_ERROR.  No pivoting, so the matrix should be SPD or diagonally
+ *   dominant (the periodic I + sigma D4 is SPD for sigma >= 0).
+ * pent_cyclic_factor_d4: the Crank-Nicolson matrix of Sec. 2.3,
+ *   a = e = sigma, b = d = -4 sigma, c = 1 + 6 sigma in every row.
+ * pent_cyclic_solve: overwrite F (DEVICE FP64, element (i, j) at F[i*ld+j],
+ *   ld >= batch) with A^{-1} F, asynchronously on `stream`.
+ * pent_cyclic_cn_rhs: R = 2 C - A C, the explicit half of the
+ *   Crank-Nicolson step (Sec. 2.3: for A = I + sigma D4 this is
+ *   (I - sigma D4) C), same layout; C and R DEVICE, must not overlap.
+ * pent_cyclic_bordering: copy Z = E^{-1} k ((n-2) x 2, row-major) and
+ *   [C2 - h^T Z]^{-1} (2 x 2, row-major) to HOST arrays (blocking).
+ * pent_cyclic_destroy: NULL is a no-op; no queued work may still use c. */
+typedef struct pent_cyclic_s *pent_cyclic;
+pent_cyclic pent_cyclic_factor(int64_t n, const double *a, const double *b, const double *c,
+                               const double *d, const double *e);
+pent_cyclic pent_cyclic_factor_d4(int64_t n, double sigma);
+int pent_cyclic_solve(pent_cyclic c, double *F, int64_t batch, int64_t ld, void *stream);
+int pent_cyclic_cn_rhs(pent_cyclic c, const double *C, int64_t ldc, double *R, int64_t ldr,
+                       int64_t batch, void *stream);
+int pent_cyclic_bordering(pent_cyclic c, double *Z, double *minv);
+int pent_cyclic_destroy(pent_cyclic c);
+
 /* ----------------------------------------------------------- inspection --
  * Copy the handle's data to HOST arrays of n doubles each (blocking).
  * pent_get_factors: alpha, beta, gamma, delta of Sec. 2.4 (epsilon = a).

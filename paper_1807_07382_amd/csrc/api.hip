@@ -297,12 +297,102 @@ struct pent_graph_s {
     hipGraphExec_t exec = nullptr;
 };
 
+struct pent_cyclic_s {
+    uint64_t magic = 0;
+    int64_t n = 0;
+    pent_plan *E = nullptr;     // factors of the leading (n-2) x (n-2) block
+    double *d_cd = nullptr;     // 5n cyclic diagonals
+    double *d_Z = nullptr;      // (n-2) x 2, ld 2: E^{-1} k
+    CycAux *d_aux = nullptr;    // sparse h^T and [C2 - h^T Z]^{-1}
+};
+
 namespace {
 
 constexpr uint64_t kGroupMagic = 0x70656e7467727075ull;
 constexpr uint64_t kGraphMagic = 0x70656e7467726166ull;
 
 bool gvalid(pent_group g) { return g && g->magic == kGroupMagic; }
+
+constexpr uint64_t kCyclicMagic = 0x70656e7463796369ull;
+
+bool cvalid(pent_cyclic c) { return c && c->magic == kCyclicMagic; }
+
+void free_cyclic(pent_cyclic c)
+{
+    if (!c) return;
+    if (c->E) free_plan(c->E);
+    if (c->d_cd) (void)hipFree(c->d_cd);
+    if (c->d_Z) (void)hipFree(c->d_Z);
+    if (c->d_aux) (void)hipFree(c->d_aux);
+    c->magic = 0;
+    delete c;
+}
+
+// Allocate a periodic handle whose cyclic diagonals (c->d_cd) the caller fills.
+pent_cyclic new_cyclic(int64_t n, int *st)
+{
+    pent_cyclic c = new (std::nothrow) pent_cyclic_s();
+    if (!c) {
+        *st = PENT_OUT_OF_MEMORY;
+        return nullptr;
+    }
+    c->n = n;
+    c->E = new_plan(n - 2, st);
+    if (!c->E) {
+        free_cyclic(c);
+        return nullptr;
+    }
+    hipError_t e = hipMalloc(&c->d_cd, sizeof(double) * 5 * n);
+    if (e == hipSuccess) e = hipMalloc(&c->d_Z, sizeof(double) * 2 * (n - 2));
+    if (e == hipSuccess) e = hipMalloc(&c->d_aux, sizeof(CycAux));
+    if (e != hipSuccess) {
+        free_cyclic(c);
+        *st = hip_status(e);
+        return nullptr;
+    }
+    *st = PENT_OK;
+    return c;
+}
+
+// Bordering precomputation on the diagonals in c->d_cd: factor E, solve
+// Z = E^{-1} k (two right-hand sides), then h^T and [C2 - h^T Z]^{-1}.
+// Blocks; consumes c on error.
+pent_cyclic finish_cyclic(pent_cyclic c)
+{
+    const int64_t n = c->n;
+    hipError_t e = launch_cyc_build(c->d_cd, n, c->E->d_diag, c->d_Z, 0);
+    if (e != hipSuccess) {
+        free_cyclic(c);
+        ret(hip_status(e));
+        return nullptr;
+    }
+    pent_plan *E = c->E;
+    c->E = nullptr;           // finish_factor frees the plan itself on error
+    c->E = finish_factor(E);
+    if (!c->E) {
+        free_cyclic(c);
+        return nullptr;       // status (and pivot row) set by finish_factor
+    }
+    int st = solve_io_scratch(c->E, c->d_Z, 2, c->d_Z, 2, 2, 0);
+    if (st == PENT_OK) st = hip_status(launch_cyc_finish(c->d_cd, n, c->d_Z, c->d_aux, 0));
+    CycAux aux;
+    if (st == PENT_OK)
+        st = hip_status(hipMemcpy(&aux, c->d_aux, sizeof(CycAux), hipMemcpyDeviceToHost));
+    if (st != PENT_OK) {
+        free_cyclic(c);
+        ret(st);
+        return nullptr;
+    }
+    if (aux.bad) {
+        free_cyclic(c);
+        g_pivot_row = n - 2;
+        ret(PENT_ZERO_PIVOT);
+        return nullptr;
+    }
+    c->magic = kCyclicMagic;
+    ret(PENT_OK);
+    return c;
+}
 
 void free_group(pent_group g)
 {
@@ -983,6 +1073,93 @@ int pent_ch2d_step(pent_handle hx, pent_handle hy, double *C, double *R, int64_t
     if (st != PENT_OK) return st;
     // y sweeps: batch-fastest over (k, x), read from R, written into C
     return ret(solve_io_scratch(hy, R, ninst * nx, C, ninst * nx, ninst * nx, (hipStream_t)stream));
+}
+
+pent_cyclic pent_cyclic_factor(int64_t n, const double *a, const double *b, const double *c,
+                               const double *d, const double *e)
+{
+    g_pivot_row = -1;
+    if (n < 5 || n > INT32_MAX || !a || !b || !c || !d || !e) {
+        ret(PENT_INVALID_VALUE);
+        return nullptr;
+    }
+    int st;
+    pent_cyclic cy = new_cyclic(n, &st);
+    if (!cy) {
+        ret(st);
+        return nullptr;
+    }
+    const double *src[5] = {a, b, c, d, e};
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < 5 && err == hipSuccess; k++)
+        err = hipMemcpy(cy->d_cd + k * n, src[k], sizeof(double) * n, hipMemcpyHostToDevice);
+    if (err != hipSuccess) {
+        free_cyclic(cy);
+        ret(hip_status(err));
+        return nullptr;
+    }
+    return finish_cyclic(cy);
+}
+
+pent_cyclic pent_cyclic_factor_d4(int64_t n, double sigma)
+{
+    g_pivot_row = -1;
+    if (n < 5 || n > INT32_MAX || !std::isfinite(sigma)) {
+        ret(PENT_INVALID_VALUE);
+        return nullptr;
+    }
+    int st;
+    pent_cyclic cy = new_cyclic(n, &st);
+    if (!cy) {
+        ret(st);
+        return nullptr;
+    }
+    hipError_t err = launch_cyc_assemble_d4(cy->d_cd, n, sigma, 0);
+    if (err != hipSuccess) {
+        free_cyclic(cy);
+        ret(hip_status(err));
+        return nullptr;
+    }
+    return finish_cyclic(cy);
+}
+
+int pent_cyclic_solve(pent_cyclic c, double *F, int64_t batch, int64_t ld, void *stream)
+{
+    if (!cvalid(c) || batch < 0 || ld < batch) return ret(PENT_INVALID_VALUE);
+    if (batch == 0) return ret(PENT_OK);
+    if (!F) return ret(PENT_INVALID_VALUE);
+    const hipStream_t s = (hipStream_t)stream;
+    int st = solve_io_scratch(c->E, F, ld, F, ld, batch, s);
+    if (st != PENT_OK) return ret(st);
+    return ret(hip_status(launch_cyc_correct(c->d_aux, c->d_Z, F, c->n, batch, ld, s)));
+}
+
+int pent_cyclic_cn_rhs(pent_cyclic c, const double *C, int64_t ldc, double *R, int64_t ldr,
+                       int64_t batch, void *stream)
+{
+    if (!cvalid(c) || batch < 0 || ldc < batch || ldr < batch) return ret(PENT_INVALID_VALUE);
+    if (batch == 0) return ret(PENT_OK);
+    if (!C || !R || (const void *)C == (const void *)R) return ret(PENT_INVALID_VALUE);
+    return ret(hip_status(launch_cn_rhs(c->d_cd, c->n, C, ldc, R, ldr, batch, (hipStream_t)stream)));
+}
+
+int pent_cyclic_bordering(pent_cyclic c, double *Z, double *minv)
+{
+    if (!cvalid(c) || !Z || !minv) return ret(PENT_INVALID_VALUE);
+    CycAux aux;
+    hipError_t e = hipMemcpy(Z, c->d_Z, sizeof(double) * 2 * (c->n - 2), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&aux, c->d_aux, sizeof(CycAux), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return ret(hip_status(e));
+    std::memcpy(minv, aux.minv, sizeof(aux.minv));
+    return ret(PENT_OK);
+}
+
+int pent_cyclic_destroy(pent_cyclic c)
+{
+    if (c == nullptr) return ret(PENT_OK);
+    if (!cvalid(c)) return ret(PENT_INVALID_VALUE);
+    free_cyclic(c);
+    return ret(PENT_OK);
 }
 
 int pent_solve_strided(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream)

@@ -77,6 +77,18 @@ struct GroupItem {
     int64_t summ_off;  // offset (doubles) of the item's segment summaries in the workspace
 };
 
+// Bordering data of a periodic matrix: the at most ten non-zeros of h^T
+// (row q of the trailing pair, column hcol, value hv) and [C2 - h^T Z]^{-1}
+// row-major.  bad != 0 when that 2 x 2 matrix is singular or not finite.
+struct CycAux {
+    int nh;
+    int bad;
+    int hq[10];
+    int64_t hcol[10];
+    double hv[10];
+    double minv[4];
+};
+
 constexpr int kMaxSegCaches = 3;  // seg_rows 16, 32, 64
 
 struct SegCache {
@@ -222,6 +234,20 @@ hipError_t launch_anorm(const double *d_diag, int64_t n, double *d_anorm, hipStr
 // ---- 2-D Cahn-Hilliard explicit term (ch2d.hip) ----
 hipError_t launch_ch2d_rhs(const double *C, double *R, int64_t ny, int64_t ninst, int64_t nx,
                            const double *dt, double h, hipStream_t s);
+
+// ---- periodic matrices by bordering (cyclic.hip) ----
+// cd: 5n cyclic row-indexed diagonals on the device (a, b, c, d, e blocks).
+hipError_t launch_cyc_assemble_d4(double *cd, int64_t n, double sigma, hipStream_t s);
+// ed: 5(n-2) diagonals of the leading block E; K: (n-2) x 2, ld 2.
+hipError_t launch_cyc_build(const double *cd, int64_t n, double *ed, double *K, hipStream_t s);
+hipError_t launch_cyc_finish(const double *cd, int64_t n, const double *Z, CycAux *aux,
+                             hipStream_t s);
+// F rows 0..n-3 hold y = E^{-1} f^ on entry; rows n-2, n-1 hold f's tail.
+// On exit F holds x.  No scratch.
+hipError_t launch_cyc_correct(const CycAux *aux, const double *Z, double *F, int64_t n,
+                              int64_t batch, int64_t ld, hipStream_t s);
+hipError_t launch_cn_rhs(const double *cd, int64_t n, const double *C, int64_t ldc, double *R,
+                         int64_t ldr, int64_t batch, hipStream_t s);
 
 // ---- group solve (group.hip) ----
 // Kernel variants (rows per segment x waves per workgroup), chosen by the

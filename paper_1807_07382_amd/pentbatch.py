@@ -57,6 +57,12 @@ SIGNATURES = {
                                  ctypes.POINTER(_D), _P]),
     "pent_ch2d_rhs": (_I, [_P, _P, _I64, _I64, _I64, _P, _D, _P]),
     "pent_ch2d_step": (_I, [_P, _P, _P, _P, _I64, _I64, _I64, _P, _D, _P]),
+    "pent_cyclic_factor": (_P, [_I64, _P, _P, _P, _P, _P]),
+    "pent_cyclic_factor_d4": (_P, [_I64, _D]),
+    "pent_cyclic_solve": (_I, [_P, _P, _I64, _I64, _P]),
+    "pent_cyclic_cn_rhs": (_I, [_P, _P, _I64, _P, _I64, _I64, _P]),
+    "pent_cyclic_bordering": (_I, [_P, _P, _P]),
+    "pent_cyclic_destroy": (_I, [_P]),
     "pent_get_factors": (_I, [_P, _P, _P, _P, _P]),
     "pent_get_diagonals": (_I, [_P, _P, _P, _P, _P, _P]),
     "pent_size": (_I64, [_P]),
@@ -373,6 +379,105 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+class Cyclic:
+    """A factored periodic pentadiagonal matrix (pent_cyclic), solved by
+    bordering.  Free with close() or a with-block."""
+
+    def __init__(self, handle: int, n: int):
+        self._h = handle
+        self.n = n
+
+    @classmethod
+    def factor(cls, a, b, c, d, e) -> "Cyclic":
+        """HOST diagonals a..e of length n, row-indexed with wrap-around."""
+        import numpy as np
+        arrs = [np.ascontiguousarray(np.asarray(x, dtype=np.float64)) for x in (a, b, c, d, e)]
+        n = arrs[2].shape[0]
+        if any(x.shape != (n,) for x in arrs):
+            raise ValueError("diagonals must all have shape (n,)")
+        return cls._made(lib().pent_cyclic_factor(n, *[x.ctypes.data for x in arrs]), n)
+
+    @classmethod
+    def factor_d4(cls, n: int, sigma: float) -> "Cyclic":
+        """The periodic Crank-Nicolson matrix I + sigma*D4 (wrapped corners)."""
+        return cls._made(lib().pent_cyclic_factor_d4(int(n), float(sigma)), n)
+
+    @classmethod
+    def _made(cls, h, n):
+        if not h:
+            st = lib().pent_last_status()
+            if st == ZERO_PIVOT:
+                raise ZeroPivotError(int(lib().pent_last_pivot_row()))
+            raise PentError(st, "cyclic factor")
+        return cls(h, int(n))
+
+    def close(self):
+        if self._h:
+            _check(lib().pent_cyclic_destroy(self._h), "cyclic destroy")
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _shape_ok(self, F, name):
+        if F.dim() != 2 or F.shape[0] != self.n or (F.shape[1] > 1 and F.stride(1) != 1):
+            raise ValueError(f"{name} must have shape ({self.n}, batch) with unit batch stride")
+
+    def solve_(self, F, stream=None):
+        """Overwrite F (cuda float64, shape (n, batch)) with A^{-1} F."""
+        self._shape_ok(F, "F")
+        m = F.shape[1]
+        _check(lib().pent_cyclic_solve(self._h, _dptr(F, "float64"), m, max(F.stride(0), m),
+                                       _stream_ptr(stream)), "cyclic solve")
+        return F
+
+    def cn_rhs(self, C, R, stream=None):
+        """R = 2C - AC (the explicit Crank-Nicolson half step), C and R cuda
+        float64 of shape (n, batch), not overlapping."""
+        self._shape_ok(C, "C")
+        self._shape_ok(R, "R")
+        if R.shape != C.shape:
+            raise ValueError("C and R must have the same shape")
+        m = C.shape[1]
+        _check(lib().pent_cyclic_cn_rhs(self._h, _dptr(C, "float64"), max(C.stride(0), m),
+                                        _dptr(R, "float64"), max(R.stride(0), m), m,
+                                        _stream_ptr(stream)), "cyclic cn_rhs")
+        return R
+
+    def cn_steps_(self, C, steps: int, R=None, stream=None):
+        """Advance C by ``steps`` Crank-Nicolson steps: R = 2C - AC, then
+        C = A^{-1} R.  R is scratch of C's shape (allocated when absent)."""
+        import torch
+        if R is None:
+            R = torch.empty_like(C)
+        for _ in range(int(steps)):
+            self.cn_rhs(C, R, stream)
+            self.solve_(R, stream)
+            C, R = R, C
+        return C, R
+
+    def bordering(self):
+        """(Z = E^{-1} k of shape (n-2, 2), [C2 - h^T Z]^{-1} of shape (2, 2))."""
+        import numpy as np
+        Z = np.empty((self.n - 2, 2))
+        Minv = np.empty((2, 2))
+        _check(lib().pent_cyclic_bordering(self._h, Z.ctypes.data, Minv.ctypes.data), "bordering")
+        return Z, Minv
 
 
 def ch2d_rhs(C, R, dt, h: float, stream=None):

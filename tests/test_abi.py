@@ -98,3 +98,26 @@ def test_status_strings(st):
 def test_python_errors_on_bad_shapes():
     with pytest.raises(ValueError):
         pb.Plan.factor(np.zeros(3), np.zeros(3), np.zeros(4), np.zeros(3), np.zeros(3))
+
+
+def test_cyclic_rejects_bad_arguments_without_hip():
+    L = pb.lib()
+    a = np.zeros(8)
+    p = a.ctypes.data
+    assert not L.pent_cyclic_factor(4, p, p, p, p, p)
+    assert L.pent_last_status() == pb.INVALID_VALUE
+    assert not L.pent_cyclic_factor(8, p, None, p, p, p)
+    assert L.pent_last_status() == pb.INVALID_VALUE
+    assert not L.pent_cyclic_factor_d4(4, 1.0)
+    assert L.pent_last_status() == pb.INVALID_VALUE
+    assert not L.pent_cyclic_factor_d4(8, float("nan"))
+    assert L.pent_last_status() == pb.INVALID_VALUE
+    buf = (ctypes.c_double * 8)()
+    assert L.pent_cyclic_solve(None, buf, 1, 1, None) == pb.INVALID_VALUE
+    assert L.pent_cyclic_cn_rhs(None, buf, 1, buf, 1, 1, None) == pb.INVALID_VALUE
+    assert L.pent_cyclic_bordering(None, buf, buf) == pb.INVALID_VALUE
+    assert L.pent_cyclic_destroy(None) == pb.OK
+    junk = (ctypes.c_uint64 * 64)()
+    h = ctypes.cast(junk, ctypes.c_void_p)
+    assert L.pent_cyclic_solve(h, buf, 1, 1, None) == pb.INVALID_VALUE
+    assert L.pent_cyclic_destroy(h) == pb.INVALID_VALUE

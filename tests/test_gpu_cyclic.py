@@ -1,0 +1,197 @@
+"""GPU tests of the periodic (cyclic) path: Navon's bordering around a
+batched pentadiagonal E-solve (Sec. 2.3), the explicit Crank-Nicolson
+half-step, and the hyperdiffusion validation of Sec. 2.5, all against the
+CPU oracle (oracle/cyclic.py) on the same seeded inputs."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cyclic
+from paper_1807_07382_amd import pentbatch as pb
+from tests._gpu import U, colerr, d4_tol, print_case, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return torch_dev()
+
+
+def random_dominant(n, seed):
+    """Cyclic diagonals with |c_i| - sum of |off-diagonals| >= 2 (strict
+    dominance), non-symmetric."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    a, b, d, e = (g.uniform(-1, 1, n) for _ in range(4))
+    c = 6.0 + g.uniform(0, 1, n)
+    return oracle.Diagonals(a, b, c, d, e)
+
+
+def varah_kappa(dg):
+    """kappa_inf <= ||A||_inf / min_i (|c_i| - sum |off_i|) (Varah's bound)."""
+    off = np.abs(dg.a) + np.abs(dg.b) + np.abs(dg.d) + np.abs(dg.e)
+    return float(np.max(off + np.abs(dg.c)) / np.min(np.abs(dg.c) - off))
+
+
+def rhs(n, batch, seed):
+    return np.random.Generator(np.random.PCG64(seed)).uniform(-1, 1, (n, batch))
+
+
+GENERAL = [(5, 1), (6, 3), (7, 64), (9, 65), (64, 200), (1000, 130), (4097, 33)]
+
+
+@pytest.mark.parametrize("n,batch", GENERAL)
+def test_cyclic_general_against_oracle(torch, n, batch):
+    print_case(test="cyclic_general", n=n, batch=batch)
+    dg = random_dominant(n, seed=n)
+    F = rhs(n, batch, seed=n + 1)
+    ref = cyclic.solve_cyclic(cyclic.bordering(dg), F)
+    with pb.Cyclic.factor(*dg) as cy:
+        T = torch.from_numpy(F.copy()).cuda()
+        cy.solve_(T)
+        torch.cuda.synchronize()
+        X = T.cpu().numpy()
+    assert np.all(colerr(X, ref) <= 64 * U * varah_kappa(dg))
+
+
+@pytest.mark.parametrize("sigma", [0.01, 50.0, 1e4])
+@pytest.mark.parametrize("n,batch", [(5, 7), (256, 256), (4096, 65), (5000, 3)])
+def test_cyclic_d4_against_oracle(torch, n, batch, sigma):
+    """Periodic I + sigma D4: eigenvalues in [1, 1 + 16 sigma], so the
+    non-periodic parity tolerance applies unchanged."""
+    print_case(test="cyclic_d4", n=n, batch=batch, sigma=sigma)
+    F = rhs(n, batch, seed=7)
+    ref = cyclic.solve_cyclic(cyclic.bordering(cyclic.cyclic_d4(n, sigma)), F)
+    with pb.Cyclic.factor_d4(n, sigma) as cy:
+        T = torch.from_numpy(F.copy()).cuda()
+        cy.solve_(T)
+        torch.cuda.synchronize()
+        assert np.all(colerr(T.cpu().numpy(), ref) <= d4_tol(sigma))
+
+
+def test_cyclic_leading_dimension(torch):
+    """ld > batch: the padding columns are left untouched."""
+    n, batch, pad = 300, 70, 9
+    print_case(test="cyclic_ld", n=n, batch=batch)
+    dg = random_dominant(n, seed=3)
+    F = rhs(n, batch, seed=4)
+    buf = torch.full((n, batch + pad), 7.0, dtype=torch.float64, device="cuda")
+    buf[:, :batch] = torch.from_numpy(F).cuda()
+    with pb.Cyclic.factor(*dg) as cy:
+        cy.solve_(buf[:, :batch])
+        torch.cuda.synchronize()
+    ref = cyclic.solve_cyclic(cyclic.bordering(dg), F)
+    assert np.all(colerr(buf[:, :batch].cpu().numpy(), ref) <= 64 * U * varah_kappa(dg))
+    assert bool(torch.all(buf[:, batch:] == 7.0))
+
+
+@pytest.mark.parametrize("n", [5, 33, 2000])
+def test_bordering_quantities(n):
+    """Z = E^{-1} k and [C2 - h^T E^{-1} k]^{-1} against the oracle's
+    precomputation (dense solves of the same blocks)."""
+    torch_dev()
+    print_case(test="bordering", n=n)
+    dg = random_dominant(n, seed=100 + n)
+    bd = cyclic.bordering(dg)
+    Zref = oracle.solve(bd.E, bd.k)
+    with pb.Cyclic.factor(*dg) as cy:
+        Z, Minv = cy.bordering()
+    tol = 64 * U * varah_kappa(dg)
+    assert np.max(np.abs(Z - Zref)) <= tol * max(np.max(np.abs(Zref)), 1.0)
+    assert np.max(np.abs(Minv - bd.Minv)) <= tol * np.max(np.abs(bd.Minv)) * 4
+
+
+@pytest.mark.parametrize("sigma", [0.1, 21.5, 1e3])
+def test_cn_rhs_against_oracle(torch, sigma):
+    n, batch = 257, 130
+    print_case(test="cn_rhs", n=n, sigma=sigma)
+    C = rhs(n, batch, seed=11)
+    ref = cyclic.cn_rhs(C, sigma)
+    with pb.Cyclic.factor_d4(n, sigma) as cy:
+        Ct = torch.from_numpy(C).cuda()
+        R = torch.empty_like(Ct)
+        cy.cn_rhs(Ct, R)
+        torch.cuda.synchronize()
+        got = R.cpu().numpy()
+    # six products and six sums of terms bounded by (2 + 16 sigma) max|C|
+    assert np.max(np.abs(got - ref)) <= 16 * U * (2 + 16 * sigma) * np.max(np.abs(C))
+
+
+def test_cn_steps_fourier_modes(torch):
+    """A batch of Fourier modes cos(2 pi m x), m = 0..7, through 500
+    Crank-Nicolson steps: each mode is an eigenvector, amplified per step by
+    G = (1 - sigma mu^2) / (1 + sigma mu^2), mu^2 = (2 - 2 cos(2 pi m / n))^2
+    (Sec. 2.3 scheme)."""
+    n, dt, steps = 64, 1e-8, 500
+    dx = 1.0 / n
+    sigma = dt / (2 * dx ** 4)
+    print_case(test="cn_modes", n=n, sigma=sigma, steps=steps)
+    x = dx * np.arange(1, n + 1)
+    modes = np.arange(8)
+    C0 = np.cos(2 * np.pi * np.outer(x, modes))
+    mu2 = (2 - 2 * np.cos(2 * np.pi * modes / n)) ** 2
+    G = (1 - sigma * mu2) / (1 + sigma * mu2)
+    expect = C0 * G ** steps
+    with pb.Cyclic.factor_d4(n, sigma) as cy:
+        C = torch.from_numpy(C0.copy()).cuda()
+        C, _ = cy.cn_steps_(C, steps)
+        torch.cuda.synchronize()
+        got = C.cpu().numpy()
+    # per-step error <= a few u (1 + 16 sigma), accumulated over the steps
+    assert np.max(np.abs(got - expect)) <= steps * d4_tol(sigma)
+
+
+def test_hyperdiffusion_convergence_slope(torch):
+    """Sec. 2.5 validation on the GPU: eps_N(T) for N = 16..256 equals the
+    oracle's run to within rounding, and the fitted slope is the paper's."""
+    import os
+    g = {}
+    path = os.path.join(os.path.dirname(__file__), "golden", "convergence.txt")
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            g[k] = v
+    T, dt, mode = float(g["T"]), float(g["dt"]), int(g["mode"])
+    steps = int(round(T / dt))
+    Ns = [16, 32, 64, 128, 256]
+    eps = []
+    for n in Ns:
+        print_case(test="convergence", n=n, steps=steps)
+        dx = 1.0 / n
+        sigma = dt / (2 * dx ** 4)
+        x = dx * np.arange(1, n + 1)
+        kw = 2 * np.pi * mode
+        with pb.Cyclic.factor_d4(n, sigma) as cy:
+            C = torch.from_numpy(np.cos(kw * x)[:, None].copy()).cuda()
+            C, _ = cy.cn_steps_(C, steps)
+            torch.cuda.synchronize()
+            got = C.cpu().numpy()[:, 0]
+        exact = np.exp(-kw ** 4 * steps * dt) * np.cos(kw * x)
+        e = float(np.sqrt(np.mean((got - exact) ** 2)))
+        C_ref, _, e_ref = cyclic.hyperdiffusion_cn(n, dt, T, mode)
+        # each step is a contraction (|G| <= 1), so per-step rounding
+        # differences add at most linearly; the RMS differs by no more
+        bound = steps * d4_tol(sigma)
+        assert np.max(np.abs(got - C_ref)) <= bound, n
+        assert abs(e - e_ref) <= bound, (n, e, e_ref)
+        eps.append(e)
+    slope = np.polyfit(np.log(Ns), np.log(eps), 1)[0]
+    assert abs(slope - float(g["theory"])) < 0.05
+    assert abs(slope - float(g["slope"])) < 0.02
+
+
+def test_cyclic_zero_pivot_and_errors(torch):
+    n = 12
+    dg = random_dominant(n, seed=5)
+    c = dg.c.copy()
+    c[0] = 0.0
+    with pytest.raises(pb.ZeroPivotError) as ei:
+        pb.Cyclic.factor(dg.a, dg.b, c, dg.d, dg.e)
+    assert ei.value.row == 0
+    L = pb.lib()
+    with pb.Cyclic.factor(*dg) as cy:
+        T = torch.zeros((n, 4), dtype=torch.float64, device="cuda")
+        assert L.pent_cyclic_solve(cy.handle, T.data_ptr(), 4, 3, None) == pb.INVALID_VALUE
+        assert L.pent_cyclic_cn_rhs(cy.handle, T.data_ptr(), 4, T.data_ptr(), 4, 4,
+                                    None) == pb.INVALID_VALUE
+        assert L.pent_cyclic_solve(cy.handle, T.data_ptr(), 0, 0, None) == pb.OK
