@@ -166,7 +166,30 @@ __global__ __launch_bounds__(64 * kGroupWaves) void k_group(const GroupMat *__re
 // tasks have been handed to running waves, and those never wait on
 // anything, so every flag is eventually published; the wait is bounded
 // anyway and a timeout is reported through ctr[2] instead of hanging.
+//
+// No branch in this kernel depends on the lane index alone: the atomics are
+// executed by every lane (lanes other than 0 add zero, stores repeat the same
+// value) and lane 0's result is read back with readlane.  With a lane-0-only
+// fetch the compiler may thread the loop's back edge round the fetch for
+// the other lanes, which then re-run the previous task.
 constexpr int kSpinLimit = 1 << 24;
+
+__device__ __forceinline__ unsigned int wave_fetch_add(unsigned int *p, unsigned int v)
+{
+    const unsigned int r = atomicAdd(p, threadIdx.x == 0 ? v : 0u);
+    return (unsigned int)__builtin_amdgcn_readlane((int)r, 0);
+}
+
+// Every lane polls the flag (one address); true once it reads non-zero.
+__device__ __forceinline__ bool wait_flag(unsigned int *flag)
+{
+    for (int spins = 0; spins < kSpinLimit; spins++) {
+        const unsigned int v = __hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if (__builtin_amdgcn_readlane((int)v, 0) != 0) return true;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    return false;
+}
 
 template <int kGK>
 __global__ __launch_bounds__(64) void k_group_tasks(const GroupMat *__restrict__ mats,
@@ -179,9 +202,7 @@ __global__ __launch_bounds__(64) void k_group_tasks(const GroupMat *__restrict__
 {
     const int lane = threadIdx.x;
     for (;;) {
-        unsigned int t0 = 0;
-        if (lane == 0) t0 = atomicAdd(&ctr[0], 1u);
-        const int t = __builtin_amdgcn_readfirstlane((int)t0);
+        const int t = (int)wave_fetch_add(&ctr[0], 1u);
         if (t >= 2 * ntasks) break;
         const bool pass1 = t < ntasks;
         const int2 task = tasks[pass1 ? t : t - ntasks];
@@ -213,28 +234,16 @@ __global__ __launch_bounds__(64) void k_group_tasks(const GroupMat *__restrict__
             o[128] = q1;
             o[192] = q2;
             __threadfence();  // summaries visible before the count
-            unsigned int c0 = 0;
-            if (lane == 0) c0 = atomicAdd(&cnt[ii], 1u);
-            const int c = __builtin_amdgcn_readfirstlane((int)c0);
+            const int c = (int)wave_fetch_add(&cnt[ii], 1u);
             if (c == nseg - 1) {  // last segment of this item: resolve its interfaces
                 __threadfence();
                 interface_chain(S + lane, (int64_t)256, (int64_t)64, segr, (int64_t)nseg);
                 __threadfence();
-                if (lane == 0) __hip_atomic_store(&ready[ii], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&ready[ii], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             }
+        } else if (!wait_flag(&ready[ii])) {
+            atomicExch(&ctr[2], 1u);
         } else {
-            int spins = 0;
-            unsigned int rdy = 0;
-            for (;;) {
-                if (lane == 0) rdy = __hip_atomic_load(&ready[ii], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-                if (__builtin_amdgcn_readfirstlane((int)rdy) != 0) break;
-                if (++spins >= kSpinLimit) break;
-                __builtin_amdgcn_s_sleep(2);
-            }
-            if (spins >= kSpinLimit) {
-                if (lane == 0) atomicExch(&ctr[2], 1u);
-                continue;
-            }
             __threadfence();
             load_seg(v, base, m.ld, act ? L : 0);
             double p2 = o[0], p1 = o[64], q1 = o[128], q2 = o[192];
@@ -253,10 +262,8 @@ __global__ __launch_bounds__(64) void k_group_tasks(const GroupMat *__restrict__
         }
     }
     // last wave out resets the counters and flags for the next launch
-    if (lane == 0) __threadfence();
-    unsigned int d0 = 0;
-    if (lane == 0) d0 = atomicAdd(&ctr[1], 1u);
-    const unsigned int d = (unsigned int)__builtin_amdgcn_readfirstlane((int)d0);
+    __threadfence();
+    const unsigned int d = wave_fetch_add(&ctr[1], 1u);
     if (d == gridDim.x - 1) {
         __threadfence();
         for (int i = lane; i < nitems; i += 64) {
@@ -264,10 +271,8 @@ __global__ __launch_bounds__(64) void k_group_tasks(const GroupMat *__restrict__
             ready[i] = 0u;
         }
         __threadfence();
-        if (lane == 0) {
-            atomicExch(&ctr[0], 0u);
-            atomicExch(&ctr[1], 0u);
-        }
+        atomicExch(&ctr[0], 0u);
+        atomicExch(&ctr[1], 0u);
         __threadfence();
     }
 }
