@@ -15,7 +15,8 @@ N=8192 with 131072 right-hand sides, sigma=1e2.
 Other workloads (for tuning runs): ``plain`` (N=256, 256 RHS), ``precision``
 (all three sigma), ``shape`` (any n / batch), ``copy`` (device copy),
 ``group`` (48 matrices, 200 graph-captured steps, persistent launch vs one
-solve per matrix), ``cahn2d`` (2-D split-implicit Cahn-Hilliard, 1024^2 x 32).
+solve per matrix), ``cahn2d`` (2-D split-implicit Cahn-Hilliard, 1024^2 x 32),
+``periodic`` (periodic Crank-Nicolson hyperdiffusion, N=4096, 65536 systems).
 """
 from __future__ import annotations
 
@@ -36,11 +37,12 @@ PEAK_HBM_GBS = 8000.0
 BYTES_PER_UNKNOWN_FP64 = 16  # read f once, write x once
 
 
-SCHEDULE_NAMES = {1: "lane", 2: "partitioned", 3: "tile"}
+SCHEDULE_NAMES = {1: "lane", 2: "partitioned", 3: "tile", 4: "onepass"}
 
 
 # kernel source file of each schedule (the counters go stale when it changes)
-SCHEDULE_SOURCES = {"lane": "sweep.hip", "partitioned": "sweep.hip", "tile": "tile.hip"}
+SCHEDULE_SOURCES = {"lane": "sweep.hip", "partitioned": "sweep.hip", "tile": "tile.hip",
+                    "onepass": "onepass.hip"}
 
 
 def kernel_source_hash(name: str) -> str:
@@ -128,7 +130,7 @@ def run_hyperdiff(args, torch):
     solves_s = batch * args.steps / (ms / 1e3)
     alg_bytes = BYTES_PER_UNKNOWN_FP64 * n * batch
     achieved = alg_bytes / (ms_step / 1e3) / 1e9
-    sched_name = SCHEDULE_NAMES[sched[0]] + (f"{sched[1]}" if sched[0] == 2 else "")
+    sched_name = SCHEDULE_NAMES[sched[0]] + (f"{sched[1]}" if sched[0] in (2, 4) else "")
     tr = traffic_for(sched_name, "hyperdiff")
     out = dict(
         metric=METRIC, value=solves_s, unit="RHS-solves/s", n_gpus=1, steps=args.steps,
@@ -419,7 +421,47 @@ def run_shape(args, torch):
                               frac=gbs / PEAK_HBM_GBS, traffic=None))
 
 
-WORKLOADS = {"hyperdiff": run_hyperdiff, "plain": run_plain, "copy": run_copy,
+def run_periodic(args, torch):
+    """Periodic hyperdiffusion with Crank-Nicolson (the paper's benchmark
+    scheme, Sec. 2.3): N = 4096, sigma = 50, 65536 systems; a step is the
+    explicit half R = 2C - AC and the bordered periodic solve A C' = R."""
+    from paper_1807_07382_amd import inputs
+    from paper_1807_07382_amd import pentbatch as pb
+    from oracle import cyclic
+    w = inputs.periodic()
+    n, sigma, batch = w["n"], w["sigma"], w["C0"].shape[1]
+    steps = args.steps
+    probe = np.array([0, 1, 63, 64, 4095, 31337, batch - 1])
+    C = torch.from_numpy(w["C0"]).cuda()
+    R = torch.empty_like(C)
+    stream = torch.cuda.current_stream()
+    cy = pb.Cyclic.factor_d4(n, sigma)
+    state = {"C": C, "R": R}
+
+    def step():
+        state["C"], state["R"] = cy.cn_steps_(state["C"], 1, state["R"], stream)
+
+    for _ in range(args.warmup):
+        step()
+    ms = _timed(torch, stream, step, steps)
+    X = state["C"][:, torch.from_numpy(probe).cuda()].cpu().numpy()
+    ref = cyclic.cn_run(sigma, w["C0"][:, probe], args.warmup + steps)
+    err = float(np.max(np.max(np.abs(X - ref), axis=0) / np.max(np.abs(ref), axis=0)))
+    cy.close()
+    alg = BYTES_PER_UNKNOWN_FP64 * n * batch  # one CN step: read C once, write C' once
+    gbs = alg / (ms / 1e3) / 1e9
+    return dict(metric=METRIC, value=batch / (ms / 1e3), unit="RHS-solves/s", n_gpus=1,
+                steps=steps, warmup=args.warmup, ms_per_step=ms, higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+                config=dict(workload="periodic", n=n, systems=batch, sigma=sigma,
+                            scheme="Crank-Nicolson, periodic (bordering)"),
+                roofline=dict(bound="hbm", achieved=gbs, peak=PEAK_HBM_GBS, unit="GB/s",
+                              frac=gbs / PEAK_HBM_GBS, traffic=None),
+                parity=dict(probe_systems=len(probe), max_rel_err_vs_oracle=err,
+                            oracle_steps=args.warmup + steps))
+
+
+WORKLOADS = {"hyperdiff": run_hyperdiff, "periodic": run_periodic, "plain": run_plain, "copy": run_copy,
              "shape": run_shape, "precision": run_precision, "group": run_group,
              "cahn2d": run_cahn2d}
 

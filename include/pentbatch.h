@@ -276,8 +276,22 @@ int64_t pent_size(pent_handle h); /* n, or -1 for a bad handle */
  *   kind 3: resident tile: 8 systems per workgroup held whole in registers
  *           (n <= 4096), one read of f and one write of x; seg_rows ignored.
  *           For larger n a solve falls back to kind 2.
+ *   kind 4: single pass: the partitioned sweep of kind 2 in one kernel, each
+ *           (64-system, seg_rows-row) block held in registers from load to
+ *           store, the segment interface states exchanged between blocks
+ *           through device memory (decoupled look-back); f read once, x
+ *           written once (seg_rows in {32, 64}).  Falls back to kind 2 when
+ *           the blocks of one 64-system tile could not all be resident at
+ *           once.  Its waits are bounded; a wait that runs out (only possible
+ *           when other work holds most of the device) leaves wrong values in
+ *           that solve and is reported by pent_check.
  * Returns PENT_INVALID_VALUE for an unknown kind or seg_rows. */
 int pent_set_schedule(pent_handle h, int kind, int seg_rows);
+
+/* Blocking check of the handle's error word: PENT_TIMEOUT if a single-pass
+ * solve (kind 4) on this handle gave up a wait since the last check (the
+ * word is then cleared), else PENT_OK. */
+int pent_check(pent_handle h);
 
 /* Autotune the schedule of this handle for `batch` systems: one lane per
  * system, partitioned with 16/32/64 rows per lane, and (n <= 4096) the
@@ -291,7 +305,8 @@ int pent_autotune(pent_handle h, int64_t batch, int *kind_out, int *seg_rows_out
                   void *stream);
 
 /* The schedule pent_solve would use for `batch` systems on this handle
- * (kind as above, seg_rows 0 unless kind is 2).  Host-only, no HIP call. */
+ * (kind as above, seg_rows 0 unless kind is 2 or 4).  Host-only, no HIP
+ * call. */
 int pent_query_schedule(pent_handle h, int64_t batch, int *kind, int *seg_rows);
 
 /* --------------------------------------------------------------- status -- */

@@ -45,6 +45,7 @@ void free_plan(pent_plan *p)
         if (c.d_seg) (void)hipFree(c.d_seg);
     if (p->d_scan) (void)hipFree(p->d_scan);
     if (p->d_trec) (void)hipFree(p->d_trec);
+    if (p->d_err) (void)hipFree(p->d_err);
     p->magic = 0;
     delete p;
 }
@@ -70,12 +71,16 @@ pent_plan *new_plan(int64_t n, int *st)
     p->d_scan = nullptr;
     p->d_trec = nullptr;
     p->scan_rows = 0;
+    p->d_err = nullptr;
+    p->onepass_cap[0] = p->onepass_cap[1] = 0;
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipMalloc(&p->d_diag, sizeof(double) * 5 * n);
     if (e == hipSuccess) e = hipMalloc(&p->d_fac, sizeof(double) * 4 * n);
     if (e == hipSuccess) e = hipMalloc(&p->d_anorm, sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&p->d_fwd, sizeof(FwdRec) * p->npad);
     if (e == hipSuccess) e = hipMalloc(&p->d_bwd, sizeof(BwdRec) * p->npad);
+    if (e == hipSuccess) e = hipMalloc(&p->d_err, sizeof(unsigned int));
+    if (e == hipSuccess) e = hipMemset(p->d_err, 0, sizeof(unsigned int));
     if (e != hipSuccess) {
         free_plan(p);
         *st = hip_status(e);
@@ -203,9 +208,18 @@ void choose_schedule(const pent_plan *p, int64_t batch, int *kind, int *seg_rows
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-// Scratch of the partitioned schedule for `batch` systems (0 for the others).
+// Co-resident single-pass units on the current device (queried once per plan).
+void query_onepass_cap(pent_plan *p, int seg_rows)
+{
+    int &cap = p->onepass_cap[seg_rows == 32 ? 0 : 1];
+    if (cap == 0) cap = onepass_capacity(seg_rows);
+}
+
+// Scratch of the partitioned and single-pass schedules for `batch` systems
+// (0 for the others).
 size_t summ_bytes(const pent_plan *p, int kind, int seg_rows, int64_t batch)
 {
+    if (kind == 4) return onepass_scratch_bytes(p->n, seg_rows, batch);
     if (kind != 2) return 0;
     const int64_t nseg = (p->n + seg_rows - 1) / seg_rows;
     const int64_t summ_ld = (batch + 63) / 64 * 64;
@@ -217,6 +231,15 @@ size_t summ_bytes(const pent_plan *p, int kind, int seg_rows, int64_t batch)
 void io_schedule(const pent_plan *p, int64_t batch, bool inplace64, int *kind, int *seg_rows)
 {
     choose_schedule(p, batch, kind, seg_rows);
+    if (*kind == 4) {
+        // every unit of one tile must fit on the device at once (with room
+        // to spare for other work); else the three-kernel form
+        const int cap = p->onepass_cap[*seg_rows == 32 ? 0 : 1];
+        const int64_t nseg = (p->n + *seg_rows - 1) / *seg_rows;
+        if (cap <= 0 || nseg > cap / 4 ||
+            onepass_units(p->n, *seg_rows, batch) > (int64_t)UINT32_MAX / 2)
+            *kind = 2;
+    }
     if (*kind == 2 && (p->n + *seg_rows - 1) / *seg_rows > 65535) *kind = 1;
     if (*kind == 1 && !inplace64) {
         *kind = 2;
@@ -242,6 +265,9 @@ int solve_io(pent_plan *h, const void *f, bool f32, int64_t ldf, double *x, int6
     }
     const SegRec *seg = seg_cache(h, seg_rows, &st);
     if (!seg) return st;
+    if (kind == 4)
+        return hip_status(launch_onepass(h->d_fwd, h->d_bwd, seg, h->n, seg_rows, f, f32, ldf, x,
+                                         ldx, batch, summ, h->d_err, s));
     const int64_t summ_ld = (batch + 63) / 64 * 64;
     return hip_status(launch_part_sweep_io(h->d_fwd, h->d_bwd, seg, h->n, h->npad, seg_rows, f,
                                            f32, ldf, x, ldx, batch, (double *)summ, summ_ld, s));
@@ -863,7 +889,7 @@ int pent_autotune(pent_handle h, int64_t batch, int *kind_out, int *seg_rows_out
             return ret(PENT_OK);
         }
     }
-    const int cands[5][2] = {{1, 0}, {2, 16}, {2, 32}, {2, 64}, {3, 0}};
+    const int cands[7][2] = {{1, 0}, {2, 16}, {2, 32}, {2, 64}, {3, 0}, {4, 32}, {4, 64}};
     double *F = nullptr;
     void *work = nullptr;
     const size_t nF = (size_t)h->n * batch;
@@ -882,6 +908,10 @@ int pent_autotune(pent_handle h, int64_t batch, int *kind_out, int *seg_rows_out
         if (c[0] == 2 && (h->n + c[1] - 1) / c[1] > 65535) continue;
         h->sched_kind = c[0];
         h->sched_seg = c[1];
+        if (c[0] == 4) query_onepass_cap(h, c[1]);
+        int ek, es;
+        io_schedule(h, batch, true, &ek, &es);
+        if (ek != c[0]) continue;  // not runnable at this size (falls back)
         double ms = 0.0;
         st = time_ms([&] { return solve_io(h, F, false, batch, F, batch, batch, work, s); }, s, 3, &ms);
         if (st == PENT_OK && ms < best) {
@@ -1218,15 +1248,30 @@ int pent_set_schedule(pent_handle h, int kind, int seg_rows)
         h->sched_seg = seg_rows;
         return ret(PENT_OK);
     }
+    if (kind == 4 && (seg_rows == 32 || seg_rows == 64)) {
+        query_onepass_cap(h, seg_rows);
+        h->sched_kind = 4;
+        h->sched_seg = seg_rows;
+        return ret(PENT_OK);
+    }
     return ret(PENT_INVALID_VALUE);
+}
+
+int pent_check(pent_handle h)
+{
+    if (!valid(h)) return ret(PENT_INVALID_VALUE);
+    unsigned int w = 0;
+    hipError_t e = hipMemcpy(&w, h->d_err, sizeof(w), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && w) e = hipMemset(h->d_err, 0, sizeof(w));
+    if (e != hipSuccess) return ret(hip_status(e));
+    return ret(w ? PENT_TIMEOUT : PENT_OK);
 }
 
 int pent_query_schedule(pent_handle h, int64_t batch, int *kind, int *seg_rows)
 {
     if (!valid(h) || batch < 0 || !kind || !seg_rows) return ret(PENT_INVALID_VALUE);
-    choose_schedule(h, batch, kind, seg_rows);
-    if (*kind == 2 && (h->n + *seg_rows - 1) / *seg_rows > 65535) *kind = 1;
-    if (*kind != 2) *seg_rows = 0;
+    io_schedule(h, batch, true, kind, seg_rows);  // what an in-place pent_solve runs
+    if (*kind != 2 && *kind != 4) *seg_rows = 0;
     return ret(PENT_OK);
 }
 

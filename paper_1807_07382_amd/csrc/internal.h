@@ -109,8 +109,10 @@ struct pent_plan {
     int64_t npad;            // record rows: n rounded up to kRecPad, rows >= n all zero
     pent::FwdRec *d_fwd;     // npad
     pent::BwdRec *d_bwd;     // npad
-    int sched_kind;          // 0 auto, 1 lane, 2 partitioned, 3 resident tile
-    int sched_seg;           // seg_rows for kind 2
+    int sched_kind;          // 0 auto, 1 lane, 2 partitioned, 3 resident tile, 4 single pass
+    int sched_seg;           // seg_rows for kinds 2 and 4
+    unsigned int *d_err;     // 1 word: a single-pass wait ran out (cleared by pent_check)
+    int onepass_cap[2];      // co-resident single-pass units (32, 64 rows), 0 = not yet queried
     std::mutex mu;           // guards seg caches (lazy build)
     pent::SegCache seg[pent::kMaxSegCaches];
     pent::ScanRec *d_scan;   // resident-tile scan constants (64 records), lazily built
@@ -234,6 +236,16 @@ hipError_t launch_anorm(const double *d_diag, int64_t n, double *d_anorm, hipStr
 // ---- 2-D Cahn-Hilliard explicit term (ch2d.hip) ----
 hipError_t launch_ch2d_rhs(const double *C, double *R, int64_t ny, int64_t ninst, int64_t nx,
                            const double *dt, double h, hipStream_t s);
+
+// ---- single-pass partitioned sweep (onepass.hip) ----
+// Units = (64-system tile, segment); scratch = status words + exchange area.
+int64_t onepass_units(int64_t n, int seg_rows, int64_t batch);
+size_t onepass_scratch_bytes(int64_t n, int seg_rows, int64_t batch);
+int onepass_capacity(int seg_rows);  // co-resident units on the current device
+hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg, int64_t n,
+                          int seg_rows, const void *Fin, bool f32, int64_t ldf, double *X,
+                          int64_t ldx, int64_t batch, void *scratch, unsigned int *err,
+                          hipStream_t s);
 
 // ---- periodic matrices by bordering (cyclic.hip) ----
 // cd: 5n cyclic row-indexed diagonals on the device (a, b, c, d, e blocks).

@@ -31,6 +31,7 @@ HYPERDIFF = dict(n=4096, sigma=50.0, batch=65536, steps=100, seed=2)
 CAHN2D = dict(nx=1024, ninst=32, sigma=200.0, steps=50, seed=3)
 PRECISION = dict(n=8192, batch=131072, sigmas=(1.0, 1e2, 1e4), seed=4)
 GROUP = dict(count=48, steps=200, seed=5)
+PERIODIC = dict(n=4096, sigma=50.0, batch=65536, steps=250, seed=6)
 
 
 def rng(seed: int) -> np.random.Generator:
@@ -58,6 +59,13 @@ def plain(seed: int = PLAIN["seed"], n: int = PLAIN["n"], batch: int = PLAIN["ba
 def hyperdiff(seed: int = HYPERDIFF["seed"], n: int = HYPERDIFF["n"],
               batch: int = HYPERDIFF["batch"]):
     return dict(n=n, sigma=HYPERDIFF["sigma"], C0=uniform(seed, (n, batch)))
+
+
+def periodic(seed: int = PERIODIC["seed"], n: int = PERIODIC["n"],
+             batch: int = PERIODIC["batch"]):
+    """Periodic Crank-Nicolson hyperdiffusion batch: C^0 uniform[-1, 1) per
+    system (the step matrix is the same for every system)."""
+    return dict(n=n, sigma=PERIODIC["sigma"], C0=uniform(seed, (n, batch)))
 
 
 def cahn2d(seed: int = CAHN2D["seed"], nx: int = CAHN2D["nx"], ninst: int = CAHN2D["ninst"]):

@@ -67,6 +67,7 @@ SIGNATURES = {
     "pent_get_diagonals": (_I, [_P, _P, _P, _P, _P, _P]),
     "pent_size": (_I64, [_P]),
     "pent_set_schedule": (_I, [_P, _I, _I]),
+    "pent_check": (_I, [_P]),
     "pent_query_schedule": (_I, [_P, _I64, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "pent_last_status": (_I, []),
     "pent_last_pivot_row": (_I64, []),
@@ -279,6 +280,11 @@ class Plan:
 
     def set_schedule(self, kind: int, seg_rows: int = 0):
         _check(lib().pent_set_schedule(self._h, int(kind), int(seg_rows)), "set_schedule")
+
+    def check(self):
+        """Raise PentError(TIMEOUT) if a single-pass solve on this handle gave
+        up a wait since the last check (blocking)."""
+        _check(lib().pent_check(self._h), "check")
 
 
 class Group:

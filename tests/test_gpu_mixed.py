@@ -10,7 +10,7 @@ from tests._gpu import colerr, d4_tol, print_case, torch_dev
 
 pytestmark = pytest.mark.gpu
 
-SCHEDULES = [(0, 0), (1, 0), (2, 16), (2, 32), (2, 64), (3, 0)]
+SCHEDULES = [(0, 0), (1, 0), (2, 16), (2, 32), (2, 64), (3, 0), (4, 32), (4, 64)]
 
 
 @pytest.fixture(scope="module")

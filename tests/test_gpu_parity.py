@@ -14,7 +14,7 @@ from tests.test_oracle_pins import random_dd
 
 pytestmark = pytest.mark.gpu
 
-SCHEDULES = [(1, 0), (2, 16), (2, 32), (2, 64), (3, 0)]
+SCHEDULES = [(1, 0), (2, 16), (2, 32), (2, 64), (3, 0), (4, 32), (4, 64)]
 
 
 @pytest.fixture(scope="module")
@@ -172,6 +172,7 @@ def test_solve_argument_errors(torch):
         assert L.pent_solve_strided(p.handle, T.data_ptr(), 1, 15, None) == pb.INVALID_VALUE
         assert L.pent_set_schedule(p.handle, 2, 48) == pb.INVALID_VALUE
         assert L.pent_set_schedule(p.handle, 9, 0) == pb.INVALID_VALUE
+        assert L.pent_set_schedule(p.handle, 4, 16) == pb.INVALID_VALUE
 
 
 @pytest.mark.parametrize("n,m,pad", [(1, 3, 0), (5, 64, 2), (33, 65, 0), (1024, 100, 8),
@@ -209,6 +210,55 @@ def test_hyperdiff_full_size_sampled(torch):
         torch.cuda.synchronize()
     norm2 = torch.linalg.vector_norm(T, dim=0)
     assert bool(torch.all(norm2 <= norm0))
+    X = T[:, torch.from_numpy(cols).cuda()].cpu().numpy()
+    ref = workloads.hyperdiffusion(n, sigma, w["C0"][:, cols], 2)
+    assert np.all(colerr(X, ref) <= 2 * d4_tol(sigma))
+
+
+@pytest.mark.parametrize("seg", [32, 64])
+@pytest.mark.parametrize("n,m", [(4133, 1000), (700, 4097), (64, 130)])
+def test_single_pass_deterministic(torch, seg, n, m):
+    """The single-pass schedule gives the same bits on every run (the
+    look-back replays the serial interface chain whatever the timing), agrees
+    with the oracle, and reports no timed-out wait."""
+    print_case(test="onepass_det", seg=seg, n=n, m=m)
+    F = np.random.Generator(np.random.PCG64(n + m)).uniform(-1, 1, (n, m))
+    ref = oracle.solve(oracle.assemble_d4(n, 50.0), F)
+    with pb.Plan.factor_d4(n, 50.0) as p:
+        p.set_schedule(4, seg)
+        assert p.schedule_for(m) == (4, seg)
+        outs = []
+        for _ in range(3):
+            T = torch.from_numpy(F).cuda()
+            p.solve_(T)
+            outs.append(T)
+        torch.cuda.synchronize()
+        p.check()
+        for o in outs[1:]:
+            assert torch.equal(o, outs[0])
+        assert np.all(colerr(outs[0].cpu().numpy(), ref) <= d4_tol(50.0))
+
+
+@pytest.mark.parametrize("seg", [32, 64])
+def test_single_pass_full_hyperdiff(torch, seg):
+    """The single-pass schedule on the full hyperdiffusion workload (N=4096,
+    65536 systems: 1024 tiles), two steps; sampled systems against the
+    oracle, the contraction property on all, no timed-out wait."""
+    w = inputs.hyperdiff()
+    n, sigma = w["n"], w["sigma"]
+    print_case(test="onepass_full", seg=seg)
+    cols = np.random.Generator(np.random.PCG64(78)).choice(w["C0"].shape[1], 128, replace=False)
+    cols = np.concatenate([cols, [0, 63, 64, w["C0"].shape[1] - 1]])
+    T = torch.from_numpy(w["C0"]).cuda()
+    norm0 = torch.linalg.vector_norm(T, dim=0)
+    with pb.Plan.factor_d4(n, sigma) as p:
+        p.set_schedule(4, seg)
+        assert p.schedule_for(T.shape[1]) == (4, seg)
+        p.solve_(T)
+        p.solve_(T)
+        torch.cuda.synchronize()
+        p.check()
+    assert bool(torch.all(torch.linalg.vector_norm(T, dim=0) <= norm0))
     X = T[:, torch.from_numpy(cols).cuda()].cpu().numpy()
     ref = workloads.hyperdiffusion(n, sigma, w["C0"][:, cols], 2)
     assert np.all(colerr(X, ref) <= 2 * d4_tol(sigma))
