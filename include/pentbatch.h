@@ -226,9 +226,10 @@ int pent_ch2d_step(pent_handle hx, pent_handle hy, double *C, double *R, int64_t
  * [C2 - h^T E^{-1} k]^{-1} ((f_{n-2}, f_{n-1}) - h^T E^{-1} f^) and the rest
  * E^{-1} f^ - (E^{-1} k)(x_{n-2}, x_{n-1}) (rows 0-based).  E is factored as
  * in Sec. 2.4; E^{-1} k and the 2 x 2 inverse are computed once, at factor
- * time.  Each solve runs one batched E-solve in place plus two light
- * kernels; it needs no workspace beyond the E-solve's stream-ordered
- * scratch.
+ * time.  A solve is either one single-pass kernel (the E-solve by
+ * decoupled look-back, the last two unknowns formed by the first block of
+ * every 64-system tile, the update applied before the one store) or the
+ * E-solve followed by two light kernels; both take stream-ordered scratch.
  *
  * pent_cyclic_factor: a..e HOST FP64 arrays of length n, row-indexed and
  *   wrapped: row i holds a[i] at column (i-2) mod n, b[i] at (i-1) mod n,
@@ -257,6 +258,26 @@ int pent_cyclic_cn_rhs(pent_cyclic c, const double *C, int64_t ldc, double *R, i
                        int64_t batch, void *stream);
 int pent_cyclic_bordering(pent_cyclic c, double *Z, double *minv);
 int pent_cyclic_destroy(pent_cyclic c);
+
+/* pent_cyclic_cn_step: X = A^{-1} (2C - AC), one Crank-Nicolson step of
+ *   Sec. 2.3 for A = I + sigma D4 (for a general periodic A the same
+ *   formula).  C, X DEVICE FP64, layout as above, different buffers (C is
+ *   read with two rows of halo on each side).  In the single-pass form the
+ *   right-hand side never goes to memory: C is read once and X written once.
+ * pent_cyclic_set_schedule: kind 0 automatic (single pass when every block
+ *   of one 64-system tile fits on the device at once), kind 1 the E-solve
+ *   followed by the update kernels (and, for the step, a separate stencil
+ *   kernel), kind 2 single pass with seg_rows in {32, 64} (still falls back
+ *   to kind 1 when the blocks would not fit).
+ * pent_cyclic_query_schedule: the form a solve (cn = 0) or step (cn = 1) of
+ *   `batch` systems runs: kind 1 or 2, seg_rows 0 unless kind 2.
+ * pent_cyclic_check: blocking; PENT_TIMEOUT if a single-pass wait on this
+ *   handle ran out since the last check (values of that call are wrong). */
+int pent_cyclic_cn_step(pent_cyclic c, const double *C, int64_t ldc, double *X, int64_t ldx,
+                        int64_t batch, void *stream);
+int pent_cyclic_set_schedule(pent_cyclic c, int kind, int seg_rows);
+int pent_cyclic_query_schedule(pent_cyclic c, int64_t batch, int cn, int *kind, int *seg_rows);
+int pent_cyclic_check(pent_cyclic c);
 
 /* ----------------------------------------------------------- inspection --
  * Copy the handle's data to HOST arrays of n doubles each (blocking).

@@ -128,8 +128,12 @@ const SegRec *seg_cache_locked(pent_plan *p, int seg_rows, int *st)
         return c.d_seg;
     }
     const int64_t nseg = (p->n + seg_rows - 1) / seg_rows;
+    // padded with all-zero records to a multiple of kSegPad segments, so
+    // kernels that take segments in groups read no past-the-end record
+    const int64_t nalloc = (nseg + kSegPad - 1) / kSegPad * kSegPad;
     SegRec *d = nullptr;
-    hipError_t e = hipMalloc(&d, sizeof(SegRec) * nseg);
+    hipError_t e = hipMalloc(&d, sizeof(SegRec) * nalloc);
+    if (e == hipSuccess) e = hipMemset(d, 0, sizeof(SegRec) * nalloc);
     if (e == hipSuccess) e = launch_seg_prep(p->d_fwd, p->d_bwd, p->n, seg_rows, d, 0);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -235,8 +239,7 @@ void io_schedule(const pent_plan *p, int64_t batch, bool inplace64, int *kind, i
         // every unit of one tile must fit on the device at once (with room
         // to spare for other work); else the three-kernel form
         const int cap = p->onepass_cap[*seg_rows == 32 ? 0 : 1];
-        const int64_t nseg = (p->n + *seg_rows - 1) / *seg_rows;
-        if (cap <= 0 || nseg > cap / 4 ||
+        if (cap <= 0 || onepass_groups(p->n, *seg_rows) > cap / 4 ||
             onepass_units(p->n, *seg_rows, batch) > (int64_t)UINT32_MAX / 2)
             *kind = 2;
     }
@@ -328,8 +331,11 @@ struct pent_cyclic_s {
     int64_t n = 0;
     pent_plan *E = nullptr;     // factors of the leading (n-2) x (n-2) block
     double *d_cd = nullptr;     // 5n cyclic diagonals
-    double *d_Z = nullptr;      // (n-2) x 2, ld 2: E^{-1} k
+    double *d_Z = nullptr;      // E->npad x 2, ld 2: E^{-1} k (rows past n-2 zero)
     CycAux *d_aux = nullptr;    // sparse h^T and [C2 - h^T Z]^{-1}
+    int kind = 0;               // 0 automatic, 1 E-solve + update kernels, 2 single pass
+    int seg_rows = 32;          // single-pass segment height
+    int cap[2][2] = {{0, 0}, {0, 0}};  // co-resident single-pass units [seg 32/64][solve/CN]
 };
 
 namespace {
@@ -369,7 +375,7 @@ pent_cyclic new_cyclic(int64_t n, int *st)
         return nullptr;
     }
     hipError_t e = hipMalloc(&c->d_cd, sizeof(double) * 5 * n);
-    if (e == hipSuccess) e = hipMalloc(&c->d_Z, sizeof(double) * 2 * (n - 2));
+    if (e == hipSuccess) e = hipMalloc(&c->d_Z, sizeof(double) * 2 * c->E->npad);
     if (e == hipSuccess) e = hipMalloc(&c->d_aux, sizeof(CycAux));
     if (e != hipSuccess) {
         free_cyclic(c);
@@ -386,7 +392,7 @@ pent_cyclic new_cyclic(int64_t n, int *st)
 pent_cyclic finish_cyclic(pent_cyclic c)
 {
     const int64_t n = c->n;
-    hipError_t e = launch_cyc_build(c->d_cd, n, c->E->d_diag, c->d_Z, 0);
+    hipError_t e = launch_cyc_build(c->d_cd, n, c->E->npad, c->E->d_diag, c->d_Z, 0);
     if (e != hipSuccess) {
         free_cyclic(c);
         ret(hip_status(e));
@@ -418,6 +424,35 @@ pent_cyclic finish_cyclic(pent_cyclic c)
     c->magic = kCyclicMagic;
     ret(PENT_OK);
     return c;
+}
+
+// Whether a periodic solve (cn: the Crank-Nicolson step) of `batch` systems
+// runs as one pass: schedule kind 0 or 2, and every block of one 64-system
+// tile fits on the device at once with room to spare.  Queries the device
+// once per handle and variant.
+bool cyc_single_pass(pent_cyclic c, int64_t batch, bool cn)
+{
+    if (c->kind == 1) return false;
+    const int sr = c->seg_rows;
+    int &cap = c->cap[sr == 32 ? 0 : 1][cn ? 1 : 0];
+    if (cap == 0) cap = cyc_onepass_capacity(sr, cn);
+    return cap > 0 && cyc_onepass_groups(c->n, sr) <= cap / 4 &&
+           cyc_onepass_units(c->n, sr, batch) <= (int64_t)UINT32_MAX / 2;
+}
+
+int cyc_run_single(pent_cyclic c, bool cn, const double *F, int64_t ldf, double *X, int64_t ldx,
+                   int64_t batch, hipStream_t s)
+{
+    int st;
+    const SegRec *seg = seg_cache(c->E, c->seg_rows, &st);
+    if (!seg) return st;
+    void *scratch = nullptr;
+    hipError_t e = hipMallocAsync(&scratch, cyc_onepass_scratch_bytes(c->n, c->seg_rows, batch), s);
+    if (e != hipSuccess) return hip_status(e);
+    e = launch_cyc_onepass(c->E->d_fwd, c->E->d_bwd, seg, c->d_cd, c->d_Z, c->d_aux, c->n,
+                           c->seg_rows, cn, F, ldf, X, ldx, batch, scratch, c->E->d_err, s);
+    const hipError_t e2 = hipFreeAsync(scratch, s);
+    return hip_status(e != hipSuccess ? e : e2);
 }
 
 void free_group(pent_group g)
@@ -1159,9 +1194,53 @@ int pent_cyclic_solve(pent_cyclic c, double *F, int64_t batch, int64_t ld, void 
     if (batch == 0) return ret(PENT_OK);
     if (!F) return ret(PENT_INVALID_VALUE);
     const hipStream_t s = (hipStream_t)stream;
+    if (cyc_single_pass(c, batch, false)) return ret(cyc_run_single(c, false, F, ld, F, ld, batch, s));
     int st = solve_io_scratch(c->E, F, ld, F, ld, batch, s);
     if (st != PENT_OK) return ret(st);
     return ret(hip_status(launch_cyc_correct(c->d_aux, c->d_Z, F, c->n, batch, ld, s)));
+}
+
+int pent_cyclic_cn_step(pent_cyclic c, const double *C, int64_t ldc, double *X, int64_t ldx,
+                        int64_t batch, void *stream)
+{
+    if (!cvalid(c) || batch < 0 || ldc < batch || ldx < batch) return ret(PENT_INVALID_VALUE);
+    if (batch == 0) return ret(PENT_OK);
+    if (!C || !X || (const void *)C == (const void *)X) return ret(PENT_INVALID_VALUE);
+    const hipStream_t s = (hipStream_t)stream;
+    if (cyc_single_pass(c, batch, true)) return ret(cyc_run_single(c, true, C, ldc, X, ldx, batch, s));
+    int st = hip_status(launch_cn_rhs(c->d_cd, c->n, C, ldc, X, ldx, batch, s));
+    if (st != PENT_OK) return ret(st);
+    return pent_cyclic_solve(c, X, batch, ldx, stream);
+}
+
+int pent_cyclic_set_schedule(pent_cyclic c, int kind, int seg_rows)
+{
+    if (!cvalid(c)) return ret(PENT_INVALID_VALUE);
+    if (kind == 0 || kind == 1) {
+        c->kind = kind;
+        return ret(PENT_OK);
+    }
+    if (kind == 2 && (seg_rows == 32 || seg_rows == 64)) {
+        c->kind = 2;
+        c->seg_rows = seg_rows;
+        return ret(PENT_OK);
+    }
+    return ret(PENT_INVALID_VALUE);
+}
+
+int pent_cyclic_query_schedule(pent_cyclic c, int64_t batch, int cn, int *kind, int *seg_rows)
+{
+    if (!cvalid(c) || batch < 0 || !kind || !seg_rows) return ret(PENT_INVALID_VALUE);
+    const bool one = cyc_single_pass(c, batch, cn != 0);
+    *kind = one ? 2 : 1;
+    *seg_rows = one ? c->seg_rows : 0;
+    return ret(PENT_OK);
+}
+
+int pent_cyclic_check(pent_cyclic c)
+{
+    if (!cvalid(c)) return ret(PENT_INVALID_VALUE);
+    return pent_check(c->E);
 }
 
 int pent_cyclic_cn_rhs(pent_cyclic c, const double *C, int64_t ldc, double *R, int64_t ldr,

@@ -90,6 +90,7 @@ struct CycAux {
 };
 
 constexpr int kMaxSegCaches = 3;  // seg_rows 16, 32, 64
+constexpr int kSegPad = 16;       // segment records are padded to a multiple of this
 
 struct SegCache {
     int seg_rows = 0;
@@ -239,9 +240,11 @@ hipError_t launch_ch2d_rhs(const double *C, double *R, int64_t ny, int64_t ninst
 
 // ---- single-pass partitioned sweep (onepass.hip) ----
 // Units = (64-system tile, segment); scratch = status words + exchange area.
+int onepass_waves(int seg_rows);                     // segments (waves) per workgroup
+int64_t onepass_groups(int64_t n, int seg_rows);     // workgroups per 64-system tile
 int64_t onepass_units(int64_t n, int seg_rows, int64_t batch);
 size_t onepass_scratch_bytes(int64_t n, int seg_rows, int64_t batch);
-int onepass_capacity(int seg_rows);  // co-resident units on the current device
+int onepass_capacity(int seg_rows);  // co-resident workgroups on the current device
 hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg, int64_t n,
                           int seg_rows, const void *Fin, bool f32, int64_t ldf, double *X,
                           int64_t ldx, int64_t batch, void *scratch, unsigned int *err,
@@ -250,8 +253,21 @@ hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *se
 // ---- periodic matrices by bordering (cyclic.hip) ----
 // cd: 5n cyclic row-indexed diagonals on the device (a, b, c, d, e blocks).
 hipError_t launch_cyc_assemble_d4(double *cd, int64_t n, double sigma, hipStream_t s);
-// ed: 5(n-2) diagonals of the leading block E; K: (n-2) x 2, ld 2.
-hipError_t launch_cyc_build(const double *cd, int64_t n, double *ed, double *K, hipStream_t s);
+// ed: 5(n-2) diagonals of the leading block E; K: zrows x 2, ld 2 (rows past
+// n-2 zero).
+hipError_t launch_cyc_build(const double *cd, int64_t n, int64_t zrows, double *ed, double *K,
+                            hipStream_t s);
+// Single-pass bordered solve (cn = false: F in place allowed) or
+// Crank-Nicolson step X = A^{-1} (2C - AC) (cn = true: Fin = C, X apart).
+int64_t cyc_onepass_groups(int64_t n, int seg_rows);  // workgroups per 64-system tile
+int64_t cyc_onepass_units(int64_t n, int seg_rows, int64_t batch);
+size_t cyc_onepass_scratch_bytes(int64_t n, int seg_rows, int64_t batch);
+int cyc_onepass_capacity(int seg_rows, bool cn);
+hipError_t launch_cyc_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg,
+                              const double *cd, const double *Z, const CycAux *aux, int64_t n,
+                              int seg_rows, bool cn, const double *Fin, int64_t ldf, double *X,
+                              int64_t ldx, int64_t batch, void *scratch, unsigned int *err,
+                              hipStream_t s);
 hipError_t launch_cyc_finish(const double *cd, int64_t n, const double *Z, CycAux *aux,
                              hipStream_t s);
 // F rows 0..n-3 hold y = E^{-1} f^ on entry; rows n-2, n-1 hold f's tail.

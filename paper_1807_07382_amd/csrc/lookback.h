@@ -1,0 +1,553 @@
+// lookback.h -- device pieces of the single-pass sweeps (onepass.hip,
+// cyclic.hip): ticketing, status words, the interface link, and the forward
+// and backward phases of one (tile, segment) block held in registers.
+//
+// By linearity (Sec. 2.4's recurrences are affine in the carried pair), a
+// segment's outgoing forward state is
+//     out_s = e_s + Tf_s y_s,        y_s = out_{s-1},  y_0 = 0,
+// with e_s the outgoing state of a zero-start forward sweep, and its
+// outgoing (upward) backward state is
+//     up_s = a_s + Tb_s z_s,         z_s = up_{s+1},   z_{last} = 0,
+// with a_s the top of a zero-start backward sweep over the TRUE forward
+// values.  Tf and Tb depend on A only (SegRec).  The carries travel between
+// the blocks of a tile through a small exchange area with decoupled
+// look-back: a block publishes its aggregate (e_s, or a_s) when its
+// neighbour's inclusive value is not there yet, looks back (forward) or
+// ahead (backward) until it meets an inclusive value, replays the chain from
+// there, and publishes its own inclusive value.
+#pragma once
+
+#include "internal.h"
+
+namespace pent {
+namespace lb {
+
+typedef __attribute__((address_space(4))) const FwdRec *CFwd;
+typedef __attribute__((address_space(4))) const BwdRec *CBwd;
+typedef __attribute__((address_space(4))) const SegRec *CSeg;
+
+constexpr int kSpin = 1 << 20;  // polls per wait before giving up
+
+// Units are numbered through kTicketLines counters, one per 128-byte line,
+// counter c serving the blocks with blockIdx % kTicketLines == c: ticket k
+// of counter c is unit k * kTicketLines + c, so the grid (one block per
+// unit) hands out every unit exactly once.  Blocks of one counter start in
+// ticket order, and the counters advance together, so a unit only ever
+// waits on units that hold a slot or on later units of its own tile; one
+// counter for all blocks would serialise every block start on one address.
+constexpr int kTicketLines = 64;
+constexpr int kTicketStride = 32;  // words per counter line
+constexpr int kTicketWords = kTicketLines * kTicketStride;
+
+// Every lane joins the atomic (lanes other than 0 add zero) and lane 0's
+// result is read back: no branch depends on the lane index alone.
+__device__ __forceinline__ unsigned int take_unit(unsigned int *ctr)
+{
+    const unsigned int c = blockIdx.x % kTicketLines;
+    const unsigned int r = atomicAdd(&ctr[c * kTicketStride], threadIdx.x == 0 ? 1u : 0u);
+    return (unsigned int)__builtin_amdgcn_readlane((int)r, 0) * kTicketLines + c;
+}
+
+// Exchanged values and status words move with agent-scope relaxed atomics
+// (loads and stores with the agent-coherence bit), never with acquire /
+// release operations: on this GPU those write back or invalidate the whole
+// L2 of the calling XCD, and with thousands of waves polling they flush
+// everyone's cached records.  Ordering comes from waiting for the wave's
+// own stores to complete before the status store (store_fence), and on the
+// reading side from loading the values only after the status was seen.
+__device__ __forceinline__ void xstore(double *p, double v)
+{
+    __hip_atomic_store((unsigned long long *)p, (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double xload(const double *p)
+{
+    return __longlong_as_double((long long)__hip_atomic_load(
+        (unsigned long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+// Every earlier memory operation of the wave has completed (s_waitcnt
+// vmcnt(0)); the compiler moves no memory operation across it.
+__device__ __forceinline__ void store_fence()
+{
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__device__ __forceinline__ unsigned int poll(unsigned int *p)
+{
+    const unsigned int v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return (unsigned int)__builtin_amdgcn_readlane((int)v, 0);
+}
+
+// The wave's exchange stores (xstore) are complete before the status is.
+__device__ __forceinline__ void publish(unsigned int *p, unsigned int v)
+{
+    store_fence();
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Status of a neighbour once it is non-zero (1 aggregate, 2 inclusive); on
+// timeout the error word is raised and 2 is returned so the wave finishes.
+__device__ __forceinline__ unsigned int wait_status(unsigned int *p, unsigned int *err)
+{
+    for (int i = 0; i < kSpin; i++) {
+        const unsigned int v = poll(p);
+        if (v != 0) return v;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    atomicOr(err, 1u);
+    return 2;
+}
+
+template <int K, typename TI>
+__device__ __forceinline__ void load_rows(double (&v)[K], const TI *base, int64_t ld, int L)
+{
+    if (L == K) {
+#pragma unroll
+        for (int k = 0; k < K; k++) v[k] = (double)__builtin_nontemporal_load(base + k * ld);
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; k++) v[k] = (k < L) ? (double)base[k * ld] : 0.0;
+    }
+}
+
+// Forward recurrence over the segment from (p2, p1); STORE writes g over v.
+template <int K, bool STORE>
+__device__ __forceinline__ void forward(double (&v)[K], CFwd fwd, int64_t r0, double &p2, double &p1)
+{
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const double ra = fwd[r0 + k].ra, ap = fwd[r0 + k].ap, bp = fwd[r0 + k].bp;
+        const double g = fma(-bp, p1, fma(-ap, p2, ra * v[k]));
+        if (STORE) v[k] = g;
+        p2 = p1;
+        p1 = g;
+    }
+}
+
+// Back substitution over the segment from (q1, q2) = (x_{r0+K}, x_{r0+K+1});
+// on exit (q1, q2) = (x_{r0}, x_{r0+1}).  STORE writes x over v.
+template <int K, bool STORE>
+__device__ __forceinline__ void backward(double (&v)[K], CBwd bwd, int64_t r0, double &q1, double &q2)
+{
+#pragma unroll
+    for (int k = K - 1; k >= 0; k--) {
+        const double gm = bwd[r0 + k].gm, dl = bwd[r0 + k].dl;
+        const double x = fma(-gm, q1, fma(-dl, q2, v[k]));
+        if (STORE) v[k] = x;
+        q2 = q1;
+        q1 = x;
+    }
+}
+
+// One link of the interface chain, (y0, y1) <- w + T (y0, y1), T column-major.
+// Publishers and look-back use this one function with explicit fused
+// multiply-adds, so a carry has the same bits whichever path produced it.
+__device__ __forceinline__ void link(double w0, double w1, double t0, double t1, double t2,
+                                     double t3, double &y0, double &y1)
+{
+    const double n0 = fma(t2, y1, fma(t0, y0, w0));
+    const double n1 = fma(t3, y1, fma(t1, y0, w1));
+    y0 = n0;
+    y1 = n1;
+}
+
+// Exchange area of one unit: 8 rows of 64 doubles (lane = system):
+// 0,1 forward aggregate e; 2,3 forward inclusive out; 4,5 backward
+// aggregate a; 6,7 backward inclusive up.
+constexpr int kExRows = 8;
+
+// One status word per lane: lane l reads word[base + l] when it is in
+// [lo, hi], else reports 0 (not counted as missing).
+__device__ __forceinline__ unsigned int lane_status(unsigned int *word, int64_t idx, bool in)
+{
+    const unsigned int v = in ? __hip_atomic_load(word + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    return v;
+}
+
+// Forward phase of block s (rows r0.., unit u, tile's first unit u0): on
+// exit v holds g and the block's inclusive value is posted.
+// Look-back by windows of 64 segments (lane l looks at segment hi - l): the
+// nearest segment with an inclusive value is found once every segment in
+// between has posted its aggregate; the chain is then replayed from that
+// inclusive value through the aggregates, innermost first -- bit for bit the
+// serial recurrence y_{p+1} = e_p + Tf_p y_p whatever the timing.  Segment 0
+// only ever posts inclusive values, so every look-back ends.
+template <int K>
+__device__ __forceinline__ void forward_phase(double (&v)[K], CFwd fwd, CSeg seg, int64_t r0, int s,
+                                              int nseg, unsigned int u, unsigned int *fst,
+                                              double *ex, unsigned int *err)
+{
+    const int lane = threadIdx.x;
+    const unsigned int u0 = u - (unsigned int)s;
+    double *me = ex + (int64_t)u * (kExRows * 64) + lane;
+    double y0 = 0.0, y1 = 0.0;
+    if (s > 0) {
+        double e0 = 0.0, e1 = 0.0;
+        forward<K, false>(v, fwd, r0, e0, e1);
+        int hi = s - 1, pstar = s - 1;
+        bool posted = false;
+        for (int spin = 0;; spin++) {
+            const int p = hi - lane;
+            const unsigned int st = lane_status(fst, (int64_t)u0 + p, p >= 0);
+            const unsigned long long incl = __ballot(st == 2);
+            const unsigned long long none = __ballot(p >= 0 && st == 0);
+            if (incl != 0) {
+                const int l = __builtin_ctzll(incl);
+                if ((none & ((1ull << l) - 1)) == 0) {
+                    pstar = hi - l;
+                    break;
+                }
+            } else if (none == 0 && hi >= 64) {
+                hi -= 64;  // a full window of aggregates: look further back
+                continue;
+            }
+            if (!posted) {
+                xstore(&me[0], e0);
+                xstore(&me[64], e1);
+                publish(&fst[u], 1u);
+                posted = true;
+            }
+            if (spin >= kSpin) {
+                atomicOr(err, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (pstar < s - 1 && !posted) {
+            xstore(&me[0], e0);
+            xstore(&me[64], e1);
+            publish(&fst[u], 1u);
+        }
+        const double *nb = ex + (int64_t)(u0 + pstar) * (kExRows * 64) + lane;
+        y0 = xload(&nb[2 * 64]);
+        y1 = xload(&nb[3 * 64]);
+        for (int q0 = pstar + 1; q0 < s; q0 += 8) {
+            double w0[8], w1[8];
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const double *ag = ex + (int64_t)(u0 + q0 + i) * (kExRows * 64) + lane;
+                w0[i] = q0 + i < s ? xload(&ag[0]) : 0.0;
+                w1[i] = q0 + i < s ? xload(&ag[64]) : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const int q = q0 + i;
+                if (q < s) link(w0[i], w1[i], seg[q].tf[0], seg[q].tf[1], seg[q].tf[2], seg[q].tf[3], y0, y1);
+            }
+        }
+        if (s < nseg - 1) {
+            double o0 = y0, o1 = y1;
+            link(e0, e1, seg[s].tf[0], seg[s].tf[1], seg[s].tf[2], seg[s].tf[3], o0, o1);
+            xstore(&me[2 * 64], o0);
+            xstore(&me[3 * 64], o1);
+            publish(&fst[u], 2u);
+        }
+        forward<K, true>(v, fwd, r0, y0, y1);
+    } else {
+        forward<K, true>(v, fwd, r0, y0, y1);  // zero start is the true start
+        if (nseg > 1) {
+            xstore(&me[2 * 64], y0);
+            xstore(&me[3 * 64], y1);
+            publish(&fst[u], 2u);
+        }
+    }
+}
+
+// Backward phase, the mirror image (look-ahead by windows, lane l at segment
+// lo + l; the last segment only ever posts inclusive values): on exit v
+// holds x.
+template <int K>
+__device__ __forceinline__ void backward_phase(double (&v)[K], CBwd bwd, CSeg seg, int64_t r0, int s,
+                                               int nseg, unsigned int u, unsigned int *bst,
+                                               double *ex, unsigned int *err)
+{
+    const int lane = threadIdx.x;
+    const unsigned int u0 = u - (unsigned int)s;
+    double *me = ex + (int64_t)u * (kExRows * 64) + lane;
+    double z0 = 0.0, z1 = 0.0;
+    if (s < nseg - 1) {
+        double a0 = 0.0, a1 = 0.0;
+        backward<K, false>(v, bwd, r0, a0, a1);
+        int lo = s + 1, pstar = s + 1;
+        bool posted = false;
+        for (int spin = 0;; spin++) {
+            const int p = lo + lane;
+            const unsigned int st = lane_status(bst, (int64_t)u0 + p, p < nseg);
+            const unsigned long long incl = __ballot(st == 2);
+            const unsigned long long none = __ballot(p < nseg && st == 0);
+            if (incl != 0) {
+                const int l = __builtin_ctzll(incl);
+                if ((none & ((1ull << l) - 1)) == 0) {
+                    pstar = lo + l;
+                    break;
+                }
+            } else if (none == 0 && lo + 64 < nseg) {
+                lo += 64;
+                continue;
+            }
+            if (!posted) {
+                xstore(&me[4 * 64], a0);
+                xstore(&me[5 * 64], a1);
+                publish(&bst[u], 1u);
+                posted = true;
+            }
+            if (spin >= kSpin) {
+                atomicOr(err, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (pstar > s + 1 && !posted) {
+            xstore(&me[4 * 64], a0);
+            xstore(&me[5 * 64], a1);
+            publish(&bst[u], 1u);
+        }
+        const double *nb = ex + (int64_t)(u0 + pstar) * (kExRows * 64) + lane;
+        z0 = xload(&nb[6 * 64]);
+        z1 = xload(&nb[7 * 64]);
+        for (int q0 = pstar - 1; q0 > s; q0 -= 8) {
+            double w0[8], w1[8];
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const double *ag = ex + (int64_t)(u0 + q0 - i) * (kExRows * 64) + lane;
+                w0[i] = q0 - i > s ? xload(&ag[4 * 64]) : 0.0;
+                w1[i] = q0 - i > s ? xload(&ag[5 * 64]) : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const int q = q0 - i;
+                if (q > s) link(w0[i], w1[i], seg[q].tb[0], seg[q].tb[1], seg[q].tb[2], seg[q].tb[3], z0, z1);
+            }
+        }
+        if (s > 0) {
+            double o0 = z0, o1 = z1;
+            link(a0, a1, seg[s].tb[0], seg[s].tb[1], seg[s].tb[2], seg[s].tb[3], o0, o1);
+            xstore(&me[6 * 64], o0);
+            xstore(&me[7 * 64], o1);
+            publish(&bst[u], 2u);
+        }
+        backward<K, true>(v, bwd, r0, z0, z1);
+    } else {
+        backward<K, true>(v, bwd, r0, z0, z1);  // nothing below the last segment
+        if (s > 0) {
+            xstore(&me[6 * 64], z0);
+            xstore(&me[7 * 64], z1);
+            publish(&bst[u], 2u);
+        }
+    }
+}
+
+// ---- grouped form: a workgroup of W waves takes W consecutive segments
+// (one per wave) of one tile; the waves exchange their carries through LDS,
+// and only the group's carries go through device memory.  The chain is
+// canonical at two levels, so results do not depend on timing:
+//   group level:   Y_{g+1} = E_g + TG_g Y_g,  E_g = the group's zero-start
+//                  aggregate (its segments linked innermost first),
+//                  TG_g = Tf of its segments multiplied in one fixed order;
+//   inside a group: y of wave w = Y_g linked through e_0 .. e_{w-1};
+// and the mirror image backward (TBG_g = Tb_{s0} ... Tb_{s0+W-1}).
+
+// M <- T M for 2x2 column-major matrices, explicit fused multiply-adds.
+__device__ __forceinline__ void mat_lmul(double t0, double t1, double t2, double t3, double &m0,
+                                         double &m1, double &m2, double &m3)
+{
+    const double n0 = fma(t2, m1, t0 * m0), n1 = fma(t3, m1, t1 * m0);
+    const double n2 = fma(t2, m3, t0 * m2), n3 = fma(t3, m3, t1 * m2);
+    m0 = n0;
+    m1 = n1;
+    m2 = n2;
+    m3 = n3;
+}
+
+// TG = Tf_{s0+W-1} ... Tf_{s0} (forward) or TBG = Tb_{s0} ... Tb_{s0+W-1}.
+template <int W, bool FWD>
+__device__ __forceinline__ void group_matrix(CSeg seg, int64_t s0, double &m0, double &m1,
+                                             double &m2, double &m3)
+{
+    m0 = 1.0;
+    m1 = 0.0;
+    m2 = 0.0;
+    m3 = 1.0;
+#pragma unroll
+    for (int i = 0; i < W; i++) {
+        const int64_t q = FWD ? s0 + i : s0 + W - 1 - i;
+        if (FWD) mat_lmul(seg[q].tf[0], seg[q].tf[1], seg[q].tf[2], seg[q].tf[3], m0, m1, m2, m3);
+        else mat_lmul(seg[q].tb[0], seg[q].tb[1], seg[q].tb[2], seg[q].tb[3], m0, m1, m2, m3);
+    }
+}
+
+// Group-level look-back (FWD) or look-ahead: the incoming carry of group g
+// of the tile whose first group unit is u0, given this group's aggregate
+// (c0, c1), which is posted unless the neighbour's inclusive value is
+// already there.  Statuses: 1 aggregate posted, 2 inclusive posted; the
+// first group (forward) and the last group (backward) post only inclusive
+// values.  Exchange rows: forward 0,1 aggregate, 2,3 inclusive; backward
+// 4,5 aggregate, 6,7 inclusive.
+template <int W, bool FWD>
+__device__ __forceinline__ void group_carry(CSeg seg, int g, int ngroups, unsigned int u0,
+                                            unsigned int *st_word, double *ex, unsigned int *err,
+                                            double c0, double c1, double &y0, double &y1)
+{
+    const int lane = threadIdx.x & 63;
+    const int ra = FWD ? 0 : 4;  // aggregate rows
+    double *me = ex + (int64_t)(u0 + g) * (kExRows * 64) + lane;
+    // the aggregate goes out first: later groups can use it while this one
+    // is still looking
+    xstore(&me[ra * 64], c0);
+    xstore(&me[(ra + 1) * 64], c1);
+    publish(&st_word[u0 + g], 1u);
+    int base = FWD ? g - 1 : g + 1, pstar = base;
+    for (int spin = 0;; spin++) {
+        const int p = FWD ? base - lane : base + lane;
+        const bool in = FWD ? p >= 0 : p < ngroups;
+        const unsigned int st = lane_status(st_word, (int64_t)u0 + p, in);
+        const unsigned long long incl = __ballot(st == 2);
+        const unsigned long long none = __ballot(in && st == 0);
+        if (incl != 0) {
+            const int l = __builtin_ctzll(incl);
+            if ((none & ((1ull << l) - 1)) == 0) {
+                pstar = FWD ? base - l : base + l;
+                break;
+            }
+        } else if (none == 0 && (FWD ? base >= 64 : base + 64 < ngroups)) {
+            base = FWD ? base - 64 : base + 64;
+            continue;
+        }
+        if (spin >= kSpin) {
+            atomicOr(err, 1u);
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    const double *nb = ex + (int64_t)(u0 + pstar) * (kExRows * 64) + lane;
+    y0 = xload(&nb[(ra + 2) * 64]);
+    y1 = xload(&nb[(ra + 3) * 64]);
+    // replay the groups between pstar and g, innermost first, 8 at a time,
+    // the loads of the next 8 in flight while the current 8 are linked
+    const int cnt = FWD ? g - 1 - pstar : pstar - g - 1;
+    auto group_at = [&](int i) { return FWD ? pstar + 1 + i : pstar - 1 - i; };
+    double w0[8], w1[8], n0[8], n1[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const double *ag = ex + (int64_t)(u0 + group_at(i)) * (kExRows * 64) + lane;
+        w0[i] = i < cnt ? xload(&ag[ra * 64]) : 0.0;
+        w1[i] = i < cnt ? xload(&ag[(ra + 1) * 64]) : 0.0;
+    }
+    for (int i0 = 0; i0 < cnt; i0 += 8) {
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            const int k = i0 + 8 + i;
+            const double *ag = ex + (int64_t)(u0 + group_at(k)) * (kExRows * 64) + lane;
+            n0[i] = k < cnt ? xload(&ag[ra * 64]) : 0.0;
+            n1[i] = k < cnt ? xload(&ag[(ra + 1) * 64]) : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            if (i0 + i < cnt) {
+                double m0, m1, m2, m3;
+                group_matrix<W, FWD>(seg, (int64_t)group_at(i0 + i) * W, m0, m1, m2, m3);
+                link(w0[i], w1[i], m0, m1, m2, m3, y0, y1);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            w0[i] = n0[i];
+            w1[i] = n1[i];
+        }
+    }
+}
+
+// Both sweeps of the block held by wave w of group g (rows r0 .. r0+K-1):
+// on exit v holds x.  sh: LDS [W + 1][2][64].
+template <int K, int W>
+__device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd, CSeg seg,
+                                             int64_t r0, int w, int g, int ngroups,
+                                             unsigned int u0, unsigned int *fst,
+                                             unsigned int *bst, double *ex, unsigned int *err,
+                                             double (*sh)[2][64])
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t s0 = (int64_t)g * W;
+    // forward: zero-start aggregates of the waves, then the group's carry
+    {
+        double e0 = 0.0, e1 = 0.0;
+        forward<K, false>(v, fwd, r0, e0, e1);
+        sh[w][0][lane] = e0;
+        sh[w][1][lane] = e1;
+    }
+    __syncthreads();
+    if (w == 0) {
+        double E0 = 0.0, E1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < W; i++)
+            link(sh[i][0][lane], sh[i][1][lane], seg[s0 + i].tf[0], seg[s0 + i].tf[1],
+                 seg[s0 + i].tf[2], seg[s0 + i].tf[3], E0, E1);
+        double Y0 = 0.0, Y1 = 0.0;
+        if (g > 0) group_carry<W, true>(seg, g, ngroups, u0, fst, ex, err, E0, E1, Y0, Y1);
+        if (g < ngroups - 1) {
+            double m0, m1, m2, m3, o0 = Y0, o1 = Y1;
+            group_matrix<W, true>(seg, s0, m0, m1, m2, m3);
+            link(E0, E1, m0, m1, m2, m3, o0, o1);
+            double *me = ex + (int64_t)(u0 + g) * (kExRows * 64) + lane;
+            xstore(&me[2 * 64], o0);
+            xstore(&me[3 * 64], o1);
+            publish(&fst[u0 + g], 2u);
+        }
+        sh[W][0][lane] = Y0;
+        sh[W][1][lane] = Y1;
+    }
+    __syncthreads();
+    {
+        double y0 = sh[W][0][lane], y1 = sh[W][1][lane];
+        for (int i = 0; i < w; i++)
+            link(sh[i][0][lane], sh[i][1][lane], seg[s0 + i].tf[0], seg[s0 + i].tf[1],
+                 seg[s0 + i].tf[2], seg[s0 + i].tf[3], y0, y1);
+        forward<K, true>(v, fwd, r0, y0, y1);
+    }
+    __syncthreads();  // sh is reused below
+    // backward: zero-start aggregates over the true g, then the group's carry
+    {
+        double a0 = 0.0, a1 = 0.0;
+        backward<K, false>(v, bwd, r0, a0, a1);
+        sh[w][0][lane] = a0;
+        sh[w][1][lane] = a1;
+    }
+    __syncthreads();
+    if (w == 0) {
+        double A0 = 0.0, A1 = 0.0;
+#pragma unroll
+        for (int i = W - 1; i >= 0; i--)
+            link(sh[i][0][lane], sh[i][1][lane], seg[s0 + i].tb[0], seg[s0 + i].tb[1],
+                 seg[s0 + i].tb[2], seg[s0 + i].tb[3], A0, A1);
+        double Z0 = 0.0, Z1 = 0.0;
+        if (g < ngroups - 1) group_carry<W, false>(seg, g, ngroups, u0, bst, ex, err, A0, A1, Z0, Z1);
+        if (g > 0) {
+            double m0, m1, m2, m3, o0 = Z0, o1 = Z1;
+            group_matrix<W, false>(seg, s0, m0, m1, m2, m3);
+            link(A0, A1, m0, m1, m2, m3, o0, o1);
+            double *me = ex + (int64_t)(u0 + g) * (kExRows * 64) + lane;
+            xstore(&me[6 * 64], o0);
+            xstore(&me[7 * 64], o1);
+            publish(&bst[u0 + g], 2u);
+        }
+        sh[W][0][lane] = Z0;
+        sh[W][1][lane] = Z1;
+    }
+    __syncthreads();
+    {
+        double z0 = sh[W][0][lane], z1 = sh[W][1][lane];
+        for (int i = W - 1; i > w; i--)
+            link(sh[i][0][lane], sh[i][1][lane], seg[s0 + i].tb[0], seg[s0 + i].tb[1],
+                 seg[s0 + i].tb[2], seg[s0 + i].tb[3], z0, z1);
+        backward<K, true>(v, bwd, r0, z0, z1);
+    }
+}
+
+}  // namespace lb
+}  // namespace pent

@@ -63,6 +63,10 @@ SIGNATURES = {
     "pent_cyclic_cn_rhs": (_I, [_P, _P, _I64, _P, _I64, _I64, _P]),
     "pent_cyclic_bordering": (_I, [_P, _P, _P]),
     "pent_cyclic_destroy": (_I, [_P]),
+    "pent_cyclic_cn_step": (_I, [_P, _P, _I64, _P, _I64, _I64, _P]),
+    "pent_cyclic_set_schedule": (_I, [_P, _I, _I]),
+    "pent_cyclic_query_schedule": (_I, [_P, _I64, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "pent_cyclic_check": (_I, [_P]),
     "pent_get_factors": (_I, [_P, _P, _P, _P, _P]),
     "pent_get_diagonals": (_I, [_P, _P, _P, _P, _P, _P]),
     "pent_size": (_I64, [_P]),
@@ -465,17 +469,46 @@ class Cyclic:
                                         _stream_ptr(stream)), "cyclic cn_rhs")
         return R
 
+    def cn_step(self, C, X, stream=None):
+        """X = A^{-1} (2C - AC): one Crank-Nicolson step from C into X (cuda
+        float64, shape (n, batch), different buffers)."""
+        self._shape_ok(C, "C")
+        self._shape_ok(X, "X")
+        if X.shape != C.shape:
+            raise ValueError("C and X must have the same shape")
+        m = C.shape[1]
+        _check(lib().pent_cyclic_cn_step(self._h, _dptr(C, "float64"), max(C.stride(0), m),
+                                         _dptr(X, "float64"), max(X.stride(0), m), m,
+                                         _stream_ptr(stream)), "cyclic cn_step")
+        return X
+
     def cn_steps_(self, C, steps: int, R=None, stream=None):
-        """Advance C by ``steps`` Crank-Nicolson steps: R = 2C - AC, then
-        C = A^{-1} R.  R is scratch of C's shape (allocated when absent)."""
+        """Advance ``steps`` Crank-Nicolson steps ping-ponging between C and
+        R (scratch of C's shape, allocated when absent); returns (state,
+        other buffer)."""
         import torch
         if R is None:
             R = torch.empty_like(C)
         for _ in range(int(steps)):
-            self.cn_rhs(C, R, stream)
-            self.solve_(R, stream)
+            self.cn_step(C, R, stream)
             C, R = R, C
         return C, R
+
+    def set_schedule(self, kind: int, seg_rows: int = 32):
+        """0 automatic, 1 E-solve + update kernels, 2 single pass."""
+        _check(lib().pent_cyclic_set_schedule(self._h, int(kind), int(seg_rows)),
+               "cyclic set_schedule")
+
+    def schedule_for(self, batch: int, cn: bool = False):
+        k, sr = _I(0), _I(0)
+        _check(lib().pent_cyclic_query_schedule(self._h, int(batch), int(bool(cn)),
+                                                ctypes.byref(k), ctypes.byref(sr)),
+               "cyclic query_schedule")
+        return int(k.value), int(sr.value)
+
+    def check(self):
+        """Raise PentError(TIMEOUT) if a single-pass wait ran out (blocking)."""
+        _check(lib().pent_cyclic_check(self._h), "cyclic check")
 
     def bordering(self):
         """(Z = E^{-1} k of shape (n-2, 2), [C2 - h^T Z]^{-1} of shape (2, 2))."""

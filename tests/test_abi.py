@@ -117,6 +117,10 @@ def test_cyclic_rejects_bad_arguments_without_hip():
     assert L.pent_cyclic_cn_rhs(None, buf, 1, buf, 1, 1, None) == pb.INVALID_VALUE
     assert L.pent_cyclic_bordering(None, buf, buf) == pb.INVALID_VALUE
     assert L.pent_cyclic_destroy(None) == pb.OK
+    assert L.pent_cyclic_cn_step(None, buf, 1, buf, 1, 1, None) == pb.INVALID_VALUE
+    assert L.pent_cyclic_set_schedule(None, 0, 32) == pb.INVALID_VALUE
+    assert L.pent_cyclic_check(None) == pb.INVALID_VALUE
+    assert L.pent_check(None) == pb.INVALID_VALUE
     junk = (ctypes.c_uint64 * 64)()
     h = ctypes.cast(junk, ctypes.c_void_p)
     assert L.pent_cyclic_solve(h, buf, 1, 1, None) == pb.INVALID_VALUE

@@ -37,16 +37,22 @@ def rhs(n, batch, seed):
     return np.random.Generator(np.random.PCG64(seed)).uniform(-1, 1, (n, batch))
 
 
-GENERAL = [(5, 1), (6, 3), (7, 64), (9, 65), (64, 200), (1000, 130), (4097, 33)]
+GENERAL = [(5, 1), (6, 3), (7, 64), (9, 65), (34, 3), (35, 70), (64, 200), (66, 64), (67, 9),
+           (1000, 130), (4097, 33)]
+# (kind, seg_rows): E-solve + update kernels; single pass with 32 / 64 rows
+SCHEDULES = [(1, 0), (2, 32), (2, 64)]
 
 
+@pytest.mark.parametrize("kind,seg", SCHEDULES)
 @pytest.mark.parametrize("n,batch", GENERAL)
-def test_cyclic_general_against_oracle(torch, n, batch):
-    print_case(test="cyclic_general", n=n, batch=batch)
+def test_cyclic_general_against_oracle(torch, n, batch, kind, seg):
+    print_case(test="cyclic_general", n=n, batch=batch, kind=kind, seg=seg)
     dg = random_dominant(n, seed=n)
     F = rhs(n, batch, seed=n + 1)
     ref = cyclic.solve_cyclic(cyclic.bordering(dg), F)
     with pb.Cyclic.factor(*dg) as cy:
+        cy.set_schedule(kind, seg or 32)
+        assert cy.schedule_for(batch)[0] == kind
         T = torch.from_numpy(F.copy()).cuda()
         cy.solve_(T)
         torch.cuda.synchronize()
@@ -54,30 +60,34 @@ def test_cyclic_general_against_oracle(torch, n, batch):
     assert np.all(colerr(X, ref) <= 64 * U * varah_kappa(dg))
 
 
+@pytest.mark.parametrize("kind,seg", SCHEDULES)
 @pytest.mark.parametrize("sigma", [0.01, 50.0, 1e4])
 @pytest.mark.parametrize("n,batch", [(5, 7), (256, 256), (4096, 65), (5000, 3)])
-def test_cyclic_d4_against_oracle(torch, n, batch, sigma):
+def test_cyclic_d4_against_oracle(torch, n, batch, sigma, kind, seg):
     """Periodic I + sigma D4: eigenvalues in [1, 1 + 16 sigma], so the
     non-periodic parity tolerance applies unchanged."""
-    print_case(test="cyclic_d4", n=n, batch=batch, sigma=sigma)
+    print_case(test="cyclic_d4", n=n, batch=batch, sigma=sigma, kind=kind, seg=seg)
     F = rhs(n, batch, seed=7)
     ref = cyclic.solve_cyclic(cyclic.bordering(cyclic.cyclic_d4(n, sigma)), F)
     with pb.Cyclic.factor_d4(n, sigma) as cy:
+        cy.set_schedule(kind, seg or 32)
         T = torch.from_numpy(F.copy()).cuda()
         cy.solve_(T)
         torch.cuda.synchronize()
         assert np.all(colerr(T.cpu().numpy(), ref) <= d4_tol(sigma))
 
 
-def test_cyclic_leading_dimension(torch):
+@pytest.mark.parametrize("kind,seg", SCHEDULES)
+def test_cyclic_leading_dimension(torch, kind, seg):
     """ld > batch: the padding columns are left untouched."""
     n, batch, pad = 300, 70, 9
-    print_case(test="cyclic_ld", n=n, batch=batch)
+    print_case(test="cyclic_ld", n=n, batch=batch, kind=kind)
     dg = random_dominant(n, seed=3)
     F = rhs(n, batch, seed=4)
     buf = torch.full((n, batch + pad), 7.0, dtype=torch.float64, device="cuda")
     buf[:, :batch] = torch.from_numpy(F).cuda()
     with pb.Cyclic.factor(*dg) as cy:
+        cy.set_schedule(kind, seg or 32)
         cy.solve_(buf[:, :batch])
         torch.cuda.synchronize()
     ref = cyclic.solve_cyclic(cyclic.bordering(dg), F)
@@ -115,6 +125,73 @@ def test_cn_rhs_against_oracle(torch, sigma):
         got = R.cpu().numpy()
     # six products and six sums of terms bounded by (2 + 16 sigma) max|C|
     assert np.max(np.abs(got - ref)) <= 16 * U * (2 + 16 * sigma) * np.max(np.abs(C))
+
+
+@pytest.mark.parametrize("kind,seg", SCHEDULES)
+@pytest.mark.parametrize("sigma", [0.1, 21.5, 1e3])
+@pytest.mark.parametrize("n,batch", [(5, 3), (37, 65), (100, 130), (4097, 64)])
+def test_cn_step_against_oracle(torch, n, batch, sigma, kind, seg):
+    """One Crank-Nicolson step X = A^{-1}(2C - AC) (the single-pass form
+    builds the right-hand side in registers) against the oracle's step."""
+    print_case(test="cn_step", n=n, batch=batch, sigma=sigma, kind=kind, seg=seg)
+    C = rhs(n, batch, seed=n + batch)
+    ref = cyclic.cn_run(sigma, C, 1)
+    with pb.Cyclic.factor_d4(n, sigma) as cy:
+        cy.set_schedule(kind, seg or 32)
+        assert cy.schedule_for(batch, cn=True)[0] == kind
+        Ct = torch.from_numpy(C).cuda()
+        X = torch.full_like(Ct, 5.0)
+        cy.cn_step(Ct, X)
+        torch.cuda.synchronize()
+        cy.check()
+        got = X.cpu().numpy()
+        assert torch.equal(Ct, torch.from_numpy(C).cuda())   # C is only read
+    # stencil rounding (16 u (2 + 16 sigma) |C|) through A^{-1} (norm <= 1)
+    # plus the solve's own error
+    assert np.max(np.abs(got - ref)) <= 4 * d4_tol(sigma) * np.max(np.abs(C))
+
+
+@pytest.mark.parametrize("seg", [32, 64])
+def test_cn_step_single_pass_deterministic(torch, seg):
+    """The single-pass step gives the same bits on every run and for a
+    system wherever it sits in the batch."""
+    n, batch, sigma = 1500, 300, 50.0
+    print_case(test="cn_det", seg=seg)
+    C = rhs(n, batch, seed=9)
+    with pb.Cyclic.factor_d4(n, sigma) as cy:
+        cy.set_schedule(2, seg)
+        outs = []
+        for perm in (np.arange(batch), np.arange(batch), np.roll(np.arange(batch), 77)):
+            Ct = torch.from_numpy(np.ascontiguousarray(C[:, perm])).cuda()
+            X = torch.empty_like(Ct)
+            cy.cn_step(Ct, X)
+            inv = np.argsort(perm)
+            outs.append(X[:, torch.from_numpy(inv).cuda()])
+        torch.cuda.synchronize()
+        cy.check()
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+
+
+def test_periodic_full_size_sampled(torch):
+    """The periodic Crank-Nicolson workload at full size (N=4096, 65536
+    systems, the automatic schedule the benchmark uses), three steps; 64
+    sampled systems against the oracle's steps."""
+    from paper_1807_07382_amd import inputs
+    w = inputs.periodic()
+    n, sigma = w["n"], w["sigma"]
+    batch = w["C0"].shape[1]
+    print_case(test="periodic_full", n=n, batch=batch)
+    cols = np.random.Generator(np.random.PCG64(79)).choice(batch, 60, replace=False)
+    cols = np.concatenate([cols, [0, 63, 64, batch - 1]])
+    with pb.Cyclic.factor_d4(n, sigma) as cy:
+        C = torch.from_numpy(w["C0"]).cuda()
+        C, _ = cy.cn_steps_(C, 3)
+        torch.cuda.synchronize()
+        cy.check()
+        X = C[:, torch.from_numpy(cols).cuda()].cpu().numpy()
+    ref = cyclic.cn_run(sigma, w["C0"][:, cols], 3)
+    assert np.max(np.abs(X - ref)) <= 3 * 4 * d4_tol(sigma)
 
 
 def test_cn_steps_fourier_modes(torch):
@@ -195,3 +272,7 @@ def test_cyclic_zero_pivot_and_errors(torch):
         assert L.pent_cyclic_cn_rhs(cy.handle, T.data_ptr(), 4, T.data_ptr(), 4, 4,
                                     None) == pb.INVALID_VALUE
         assert L.pent_cyclic_solve(cy.handle, T.data_ptr(), 0, 0, None) == pb.OK
+        assert L.pent_cyclic_cn_step(cy.handle, T.data_ptr(), 4, T.data_ptr(), 4, 4,
+                                     None) == pb.INVALID_VALUE
+        assert L.pent_cyclic_set_schedule(cy.handle, 2, 16) == pb.INVALID_VALUE
+        assert L.pent_cyclic_set_schedule(cy.handle, 3, 32) == pb.INVALID_VALUE
