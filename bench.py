@@ -41,13 +41,16 @@ SCHEDULE_NAMES = {1: "lane", 2: "partitioned", 3: "tile", 4: "onepass"}
 
 
 # kernel source file of each schedule (the counters go stale when it changes)
-SCHEDULE_SOURCES = {"lane": "sweep.hip", "partitioned": "sweep.hip", "tile": "tile.hip",
-                    "onepass": "onepass.hip"}
+SCHEDULE_SOURCES = {"lane": ("sweep.hip",), "partitioned": ("sweep.hip",), "tile": ("tile.hip",),
+                    "onepass": ("onepass.hip", "lookback.h")}
 
 
-def kernel_source_hash(name: str) -> str:
-    with open(os.path.join(ROOT, "paper_1807_07382_amd", "csrc", name), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+def kernel_source_hash(names) -> str:
+    h = hashlib.sha256()
+    for name in (names,) if isinstance(names, str) else names:
+        with open(os.path.join(ROOT, "paper_1807_07382_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_for(kernel: str, workload: str):
@@ -441,20 +444,29 @@ def run_periodic(args, torch):
     def step():
         state["C"], state["R"] = cy.cn_steps_(state["C"], 1, state["R"], stream)
 
+    form = cy.schedule_for(batch, cn=True)
     for _ in range(args.warmup):
         step()
     ms = _timed(torch, stream, step, steps)
     X = state["C"][:, torch.from_numpy(probe).cuda()].cpu().numpy()
     ref = cyclic.cn_run(sigma, w["C0"][:, probe], args.warmup + steps)
     err = float(np.max(np.max(np.abs(X - ref), axis=0) / np.max(np.abs(ref), axis=0)))
+    # the other form of the same step, for comparison (same data, timing only)
+    other = 1 if form[0] == 2 else 2
+    cy.set_schedule(other, 64)
+    step()
+    ms_other = _timed(torch, stream, step, max(5, steps // 5))
     cy.close()
+    names = {1: "stencil, E-solve, update (three passes)", 2: "single pass"}
     alg = BYTES_PER_UNKNOWN_FP64 * n * batch  # one CN step: read C once, write C' once
     gbs = alg / (ms / 1e3) / 1e9
     return dict(metric=METRIC, value=batch / (ms / 1e3), unit="RHS-solves/s", n_gpus=1,
                 steps=steps, warmup=args.warmup, ms_per_step=ms, higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
                 config=dict(workload="periodic", n=n, systems=batch, sigma=sigma,
-                            scheme="Crank-Nicolson, periodic (bordering)"),
+                            scheme="Crank-Nicolson, periodic (bordering)",
+                            form=names[form[0]], seg_rows=form[1]),
+                other_form=dict(form=names[other], ms_per_step=ms_other),
                 roofline=dict(bound="hbm", achieved=gbs, peak=PEAK_HBM_GBS, unit="GB/s",
                               frac=gbs / PEAK_HBM_GBS, traffic=None),
                 parity=dict(probe_systems=len(probe), max_rel_err_vs_oracle=err,

@@ -288,7 +288,11 @@ int pent_get_diagonals(pent_handle h, double *a, double *b, double *c, double *d
 int64_t pent_size(pent_handle h); /* n, or -1 for a bad handle */
 
 /* Force a schedule for this handle (tests and tuning):
- *   kind 0: automatic (default);
+ *   kind 0: automatic (default): the resident tile for small solves
+ *           (n <= 4096 and n * batch <= 8M), the single pass (kind 4, 64
+ *           rows) for 1024 <= n <= 2048, and for n <= 4096 with FP64 input
+ *           in place, when a tile of its blocks fits on the device; else
+ *           the partitioned form (kind 2);
  *   kind 1: one lane per system, both sweeps in one kernel (the paper's
  *           one-thread-per-system schedule, Sec. 2.4 last paragraph);
  *   kind 2: partitioned: seg_rows consecutive rows per lane, several lanes

@@ -90,6 +90,13 @@ pent_plan *new_plan(int64_t n, int *st)
     return p;
 }
 
+// Co-resident single-pass units on the current device (queried once per plan).
+void query_onepass_cap(pent_plan *p, int seg_rows)
+{
+    int &cap = p->onepass_cap[seg_rows == 32 ? 0 : 1];
+    if (cap == 0) cap = onepass_capacity(seg_rows);
+}
+
 // Factor the diagonals already in p->d_diag; blocks.  Consumes p on error.
 pent_handle finish_factor(pent_plan *p)
 {
@@ -111,6 +118,7 @@ pent_handle finish_factor(pent_plan *p)
         ret(PENT_ZERO_PIVOT);
         return nullptr;
     }
+    query_onepass_cap(p, 64);  // occupancy only; lets the default pick the single pass
     p->magic = kMagic;
     ret(PENT_OK);
     return p;
@@ -200,6 +208,12 @@ void choose_schedule(const pent_plan *p, int64_t batch, int *kind, int *seg_rows
     } else if (tile_rows_for(p->n) > 0 && p->n * batch <= (int64_t)8 << 20) {
         *kind = 3;
         *seg_rows = 0;
+    } else if (p->onepass_cap[1] > 0 && p->n >= 1024 && p->n <= 4096) {
+        // measured: the single pass wins while a tile is shallow (n <= 2048)
+        // and ties at n = 4096 (FP64 in place; io_schedule keeps FP32
+        // input there on kind 2); deeper tiles favour the partitioned form
+        *kind = 4;
+        *seg_rows = 64;
     } else {
         *kind = 2;
         *seg_rows = p->n <= 2048 ? 32 : 64;
@@ -212,12 +226,6 @@ void choose_schedule(const pent_plan *p, int64_t batch, int *kind, int *seg_rows
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-// Co-resident single-pass units on the current device (queried once per plan).
-void query_onepass_cap(pent_plan *p, int seg_rows)
-{
-    int &cap = p->onepass_cap[seg_rows == 32 ? 0 : 1];
-    if (cap == 0) cap = onepass_capacity(seg_rows);
-}
 
 // Scratch of the partitioned and single-pass schedules for `batch` systems
 // (0 for the others).
@@ -235,6 +243,10 @@ size_t summ_bytes(const pent_plan *p, int kind, int seg_rows, int64_t batch)
 void io_schedule(const pent_plan *p, int64_t batch, bool inplace64, int *kind, int *seg_rows)
 {
     choose_schedule(p, batch, kind, seg_rows);
+    if (p->sched_kind == 0 && *kind == 4 && p->n > 2048 && !inplace64) {
+        *kind = 2;
+        *seg_rows = 64;
+    }
     if (*kind == 4) {
         // every unit of one tile must fit on the device at once (with room
         // to spare for other work); else the three-kernel form
@@ -330,8 +342,9 @@ struct pent_cyclic_s {
     uint64_t magic = 0;
     int64_t n = 0;
     pent_plan *E = nullptr;     // factors of the leading (n-2) x (n-2) block
-    double *d_cd = nullptr;     // 5n cyclic diagonals
+    double *d_cd = nullptr;     // cyclic diagonals, 5 blocks of cyc_ld(n), zero-padded
     double *d_Z = nullptr;      // E->npad x 2, ld 2: E^{-1} k (rows past n-2 zero)
+    double *d_W = nullptr;      // E->npad x 2, ld 2: (h^T E^{-1})^T (rows past n-2 zero)
     CycAux *d_aux = nullptr;    // sparse h^T and [C2 - h^T Z]^{-1}
     int kind = 0;               // 0 automatic, 1 E-solve + update kernels, 2 single pass
     int seg_rows = 32;          // single-pass segment height
@@ -355,6 +368,7 @@ void free_cyclic(pent_cyclic c)
     if (c->E) free_plan(c->E);
     if (c->d_cd) (void)hipFree(c->d_cd);
     if (c->d_Z) (void)hipFree(c->d_Z);
+    if (c->d_W) (void)hipFree(c->d_W);
     if (c->d_aux) (void)hipFree(c->d_aux);
     c->magic = 0;
     delete c;
@@ -374,8 +388,10 @@ pent_cyclic new_cyclic(int64_t n, int *st)
         free_cyclic(c);
         return nullptr;
     }
-    hipError_t e = hipMalloc(&c->d_cd, sizeof(double) * 5 * n);
+    hipError_t e = hipMalloc(&c->d_cd, sizeof(double) * 5 * cyc_ld(n));
+    if (e == hipSuccess) e = hipMemset(c->d_cd, 0, sizeof(double) * 5 * cyc_ld(n));
     if (e == hipSuccess) e = hipMalloc(&c->d_Z, sizeof(double) * 2 * c->E->npad);
+    if (e == hipSuccess) e = hipMalloc(&c->d_W, sizeof(double) * 2 * c->E->npad);
     if (e == hipSuccess) e = hipMalloc(&c->d_aux, sizeof(CycAux));
     if (e != hipSuccess) {
         free_cyclic(c);
@@ -407,6 +423,27 @@ pent_cyclic finish_cyclic(pent_cyclic c)
     }
     int st = solve_io_scratch(c->E, c->d_Z, 2, c->d_Z, 2, 2, 0);
     if (st == PENT_OK) st = hip_status(launch_cyc_finish(c->d_cd, n, c->d_Z, c->d_aux, 0));
+    // (h^T E^{-1})^T = E^{-T} h: factor E^T (same leading minors as E) and
+    // solve with the two border rows as right-hand sides
+    if (st == PENT_OK) {
+        pent_plan *Et = new_plan(n - 2, &st);
+        if (Et) {
+            hipError_t e2 = launch_cyc_build_transposed(c->d_cd, n, c->E->npad, Et->d_diag, c->d_W, 0);
+            if (e2 != hipSuccess) {
+                free_plan(Et);
+                st = hip_status(e2);
+            } else {
+                Et = finish_factor(Et);  // frees Et itself on error
+                if (!Et) {
+                    st = g_status;
+                } else {
+                    st = solve_io_scratch(Et, c->d_W, 2, c->d_W, 2, 2, 0);
+                    if (st == PENT_OK) st = hip_status(hipDeviceSynchronize());
+                    free_plan(Et);
+                }
+            }
+        }
+    }
     CycAux aux;
     if (st == PENT_OK)
         st = hip_status(hipMemcpy(&aux, c->d_aux, sizeof(CycAux), hipMemcpyDeviceToHost));
@@ -449,7 +486,7 @@ int cyc_run_single(pent_cyclic c, bool cn, const double *F, int64_t ldf, double 
     void *scratch = nullptr;
     hipError_t e = hipMallocAsync(&scratch, cyc_onepass_scratch_bytes(c->n, c->seg_rows, batch), s);
     if (e != hipSuccess) return hip_status(e);
-    e = launch_cyc_onepass(c->E->d_fwd, c->E->d_bwd, seg, c->d_cd, c->d_Z, c->d_aux, c->n,
+    e = launch_cyc_onepass(c->E->d_fwd, c->E->d_bwd, seg, c->d_cd, c->d_Z, c->d_W, c->d_aux, c->n,
                            c->seg_rows, cn, F, ldf, X, ldx, batch, scratch, c->E->d_err, s);
     const hipError_t e2 = hipFreeAsync(scratch, s);
     return hip_status(e != hipSuccess ? e : e2);
@@ -1157,7 +1194,7 @@ pent_cyclic pent_cyclic_factor(int64_t n, const double *a, const double *b, cons
     const double *src[5] = {a, b, c, d, e};
     hipError_t err = hipSuccess;
     for (int k = 0; k < 5 && err == hipSuccess; k++)
-        err = hipMemcpy(cy->d_cd + k * n, src[k], sizeof(double) * n, hipMemcpyHostToDevice);
+        err = hipMemcpy(cy->d_cd + k * cyc_ld(n), src[k], sizeof(double) * n, hipMemcpyHostToDevice);
     if (err != hipSuccess) {
         free_cyclic(cy);
         ret(hip_status(err));

@@ -22,7 +22,7 @@ namespace {
 
 __device__ __forceinline__ double cyc_coef(const double *cd, int64_t n, int64_t i, int o)
 {
-    return cd[(o + 2) * n + i];  // o in -2..2 -> a, b, c, d, e
+    return cd[(o + 2) * cyc_ld(n) + i];  // o in -2..2 -> a, b, c, d, e
 }
 
 __global__ void k_cyc_assemble_d4(double *__restrict__ cd, int64_t n, double sigma)
@@ -30,11 +30,12 @@ __global__ void k_cyc_assemble_d4(double *__restrict__ cd, int64_t n, double sig
 #pragma clang fp contract(off)
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int64_t ld = cyc_ld(n);
     cd[i] = sigma;
-    cd[n + i] = -4.0 * sigma;
-    cd[2 * n + i] = 1.0 + 6.0 * sigma;
-    cd[3 * n + i] = -4.0 * sigma;
-    cd[4 * n + i] = sigma;
+    cd[ld + i] = -4.0 * sigma;
+    cd[2 * ld + i] = 1.0 + 6.0 * sigma;
+    cd[3 * ld + i] = -4.0 * sigma;
+    cd[4 * ld + i] = sigma;
 }
 
 // E's diagonals (m = n-2 rows), zero outside the (m x m) block.
@@ -43,11 +44,12 @@ __global__ void k_cyc_build_E(const double *__restrict__ cd, int64_t n, double *
     const int64_t m = n - 2;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= m) return;
+    const int64_t ld = cyc_ld(n);
     ed[i] = (i >= 2) ? cd[i] : 0.0;
-    ed[m + i] = (i >= 1) ? cd[n + i] : 0.0;
-    ed[2 * m + i] = cd[2 * n + i];
-    ed[3 * m + i] = (i + 1 < m) ? cd[3 * n + i] : 0.0;
-    ed[4 * m + i] = (i + 2 < m) ? cd[4 * n + i] : 0.0;
+    ed[m + i] = (i >= 1) ? cd[ld + i] : 0.0;
+    ed[2 * m + i] = cd[2 * ld + i];
+    ed[3 * m + i] = (i + 1 < m) ? cd[3 * ld + i] : 0.0;
+    ed[4 * m + i] = (i + 2 < m) ? cd[4 * ld + i] : 0.0;
 }
 
 // K (m x 2, batch-fastest, ld 2): column s = entries of A in column m + s;
@@ -72,6 +74,39 @@ __global__ void k_cyc_build_k(const double *__restrict__ cd, int64_t n, int64_t 
     }
     K[2 * i] = k0;
     K[2 * i + 1] = k1;
+}
+
+// E^T's diagonals: row i of E^T is column i of E.
+__global__ void k_cyc_build_Et(const double *__restrict__ cd, int64_t n, double *__restrict__ etd)
+{
+    const int64_t m = n - 2;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const int64_t ld = cyc_ld(n);
+    etd[i] = (i >= 2) ? cd[4 * ld + i - 2] : 0.0;            // E[i-2][i]
+    etd[m + i] = (i >= 1) ? cd[3 * ld + i - 1] : 0.0;        // E[i-1][i]
+    etd[2 * m + i] = cd[2 * ld + i];                          // E[i][i]
+    etd[3 * m + i] = (i + 1 < m) ? cd[ld + i + 1] : 0.0;     // E[i+1][i]
+    etd[4 * m + i] = (i + 2 < m) ? cd[i + 2] : 0.0;          // E[i+2][i]
+}
+
+// H (rows x 2, ld 2): H[i][q] = A[m+q][i] for i < m (the border rows h^T),
+// zero for i >= m.
+__global__ void k_cyc_build_H(const double *__restrict__ cd, int64_t n, int64_t rows,
+                              double *__restrict__ H)
+{
+    const int64_t m = n - 2;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows) return;
+    double h0 = 0.0, h1 = 0.0;
+    if (i < m) {
+        for (int o = -2; o <= 2; o++) {
+            if (((m + o) % n + n) % n == i) h0 += cyc_coef(cd, n, m, o);
+            if (((m + 1 + o) % n + n) % n == i) h1 += cyc_coef(cd, n, m + 1, o);
+        }
+    }
+    H[2 * i] = h0;
+    H[2 * i + 1] = h1;
 }
 
 // Sparse h^T, C2 and [C2 - h^T Z]^{-1}, one lane.
@@ -150,7 +185,9 @@ __global__ void k_cn_rhs(const double *__restrict__ cd, int64_t n, const double 
     for (int64_t i = blockIdx.y; i < n; i += gridDim.y) {
         double acc = 2.0 * C[i * ldc + j];
         for (int o = -2; o <= 2; o++) {
-            const int64_t col = ((i + o) % n + n) % n;
+            int64_t col = i + o;  // n >= 5: one wrap at most
+            col += col < 0 ? n : 0;
+            col -= col >= n ? n : 0;
             acc -= cyc_coef(cd, n, i, o) * C[col * ldc + j];
         }
         R[i * ldr + j] = acc;
@@ -158,38 +195,50 @@ __global__ void k_cn_rhs(const double *__restrict__ cd, int64_t n, const double 
 }
 
 // ---- single pass: the bordered solve (and the Crank-Nicolson step) in one
-// kernel.  Blocks (64-system tile, segment of the E rows) hold their rows in
-// registers from load to store; the E-solve runs by look-back (lookback.h);
-// then the blocks holding rows m-2 and m-1 post y there, the tile's first
-// block (which holds y_0, y_1 after the backward chain) forms
-// x_tail = Minv (f_tail - h^T y) and posts it, and every block applies
-// x^ = y - Z x_tail to its rows before the one store.
+// kernel.  Workgroups (64-system tile, W consecutive segments of the E rows,
+// one per wave) hold their rows in registers from load to store; the E-solve
+// runs by look-back (lookback.h).  The last two unknowns need
+// h^T E^{-1} f^ = sum over rows of (h^T E^{-1})[q][i] f_i: every block forms
+// its part from the precomputed (h^T E^{-1})^T while f is in registers, every
+// group posts the sum of its waves' parts, and the tile's last group (which
+// finishes first: nothing lies below it) adds the groups' parts in order,
+// forms x_tail = Minv ((f_{n-2}, f_{n-1}) - h^T E^{-1} f^) and posts it.
+// Every block then applies x^ = y - Z x_tail to its rows before the one
+// store.  This is the paper's bordering formula with hT E^{-1} precomputed.
 //
 // With CN the block loads C rows r0-2 .. r0+K+1 (periodic) instead of f and
 // forms f = 2C - AC in registers (the explicit half of the step); C and X
-// must then be different buffers.  The first block forms f_tail the same way.
-//
-// Tile words (per tile): [0] x_tail posted, [1] number of posted end rows (2).
-// Tile exchange (per tile, 4 x 64 doubles): x_tail (2), y_{m-2}, y_{m-1}.
+// must then be different buffers.  The last group forms f's tail the same
+// way.
 using namespace lb;
 
-// f_i = 2 C_i - (A C)_i for row i, C rows i-2 .. i+2 in c0..c4.
-__device__ __forceinline__ double cn_row(const double *__restrict__ cd, int64_t n, int64_t i,
-                                         double c0, double c1, double c2, double c3, double c4)
+typedef __attribute__((address_space(4))) const double *CDbl;
+
+// f_i = 2 C_i - (A C)_i for row i, C rows i-2 .. i+2 in c0..c4; the
+// coefficients are wave-uniform (scalar loads), ld = cyc_ld(n).
+__device__ __forceinline__ double cn_row(CDbl cd, int64_t ld, int64_t i, double c0, double c1,
+                                         double c2, double c3, double c4)
 {
     double acc = 2.0 * c2;
     acc = fma(-cd[i], c0, acc);
-    acc = fma(-cd[n + i], c1, acc);
-    acc = fma(-cd[2 * n + i], c2, acc);
-    acc = fma(-cd[3 * n + i], c3, acc);
-    acc = fma(-cd[4 * n + i], c4, acc);
+    acc = fma(-cd[ld + i], c1, acc);
+    acc = fma(-cd[2 * ld + i], c2, acc);
+    acc = fma(-cd[3 * ld + i], c3, acc);
+    acc = fma(-cd[4 * ld + i], c4, acc);
     return acc;
 }
 
+// r mod n for a window index r in [-2, n + K + 1]; the division only runs
+// when n is smaller than the window (wave-uniform, so scalar code).
 __device__ __forceinline__ int64_t wrap(int64_t r, int64_t n)
 {
-    r %= n;
-    return r < 0 ? r + n : r;
+    if (r < 0) r += n;
+    if (r >= n) r -= n;
+    if (r < 0 || r >= n) {
+        r %= n;
+        if (r < 0) r += n;
+    }
+    return r;
 }
 
 __device__ __forceinline__ unsigned int wait_nonzero(unsigned int *p, unsigned int want,
@@ -207,18 +256,20 @@ __device__ __forceinline__ unsigned int wait_nonzero(unsigned int *p, unsigned i
 template <int K, int W, bool CN>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(K == 64 ? 2 : 3))) void k_cyc_onepass(
     const FwdRec *fwd_, const BwdRec *bwd_, const SegRec *seg_, const double *__restrict__ cd_,
-    const double *__restrict__ Z_, const CycAux *__restrict__ aux, int64_t n, int ngroups,
-    const double *Fin, int64_t ldf, double *X, int64_t ldx, int64_t batch, unsigned int *ctr,
-    unsigned int *fst, unsigned int *bst, unsigned int *tst, double *ex, double *tex,
-    unsigned int *err)
+    const double *__restrict__ Z_, const double *__restrict__ Wt_, const CycAux *__restrict__ aux,
+    int64_t n, int ngroups, const double *Fin, int64_t ldf, double *X, int64_t ldx, int64_t batch,
+    unsigned int *ctr, unsigned int *fst, unsigned int *bst, unsigned int *pst, unsigned int *tst,
+    double *ex, double *pex, double *tex, unsigned int *err)
 {
-    typedef __attribute__((address_space(4))) const double *CDbl;
     __shared__ double sh[W + 1][2][64];
+    __shared__ double sp[W][2][64];
     __shared__ unsigned int s_unit;
     const CFwd fwd = (CFwd)fwd_;
     const CBwd bwd = (CBwd)bwd_;
     const CSeg seg = (CSeg)seg_;
     const CDbl Z = (CDbl)Z_;
+    const CDbl Wt = (CDbl)Wt_;
+    const CDbl cd = (CDbl)cd_;
     const int64_t m = n - 2;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
     const int lane = threadIdx.x & 63;
@@ -232,30 +283,52 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(K == 64 
     const int64_t r0 = ((int64_t)g * W + w) * K;
     const int64_t rem = m - r0;
     const int L = (int)(rem < 0 ? 0 : rem < K ? rem : K);  // E rows in this block
-    const bool first = g == 0 && w == 0;                  // holds rows 0, 1
+    const bool last = g == ngroups - 1 && w == 0;  // forms x_tail for the tile
     const double *col = Fin + jj;
     double v[K];
-    double ft0 = 0.0, ft1 = 0.0;  // f_m, f_{m+1} (first block only)
+    double ft0 = 0.0, ft1 = 0.0;  // f_m, f_{m+1} (tail block only)
     if (CN) {
-        double wv[K + 4];
-#pragma unroll
-        for (int k = 0; k < K + 4; k++)
-            wv[k] = (act && k < L + 4 && L > 0) ? col[wrap(r0 - 2 + k, n) * ldf] : 0.0;
-        if (first) {
-            const double cm2 = act ? col[(m - 2) * ldf] : 0.0;
-            const double cm1 = act ? col[(m - 1) * ldf] : 0.0;
-            // rows m, m+1 = wv[0], wv[1]; rows 0, 1 = wv[2], wv[3]
-            ft0 = cn_row(cd_, n, m, cm2, cm1, wv[0], wv[1], wv[2]);
-            ft1 = cn_row(cd_, n, m + 1, cm1, wv[0], wv[1], wv[2], wv[3]);
+        // C rows r0 .. r0+K-1 into v (two rows past the block's last E row are
+        // needed by the stencil: for a short last block they sit in v, else in
+        // the halo h2, h3), rows r0-2, r0-1 in h0, h1; all periodic.  f is then
+        // formed in place with the two overwritten originals kept rolling.
+        const int Lc = L + 2 < K ? L + 2 : K;
+        double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
+        if (act && L > 0) {
+            h0 = col[wrap(r0 - 2, n) * ldf];
+            h1 = col[wrap(r0 - 1, n) * ldf];
+            if (L + 1 >= K) h2 = col[wrap(r0 + K, n) * ldf];
+            if (L + 2 >= K) h3 = col[wrap(r0 + K + 1, n) * ldf];
         }
+        // rows r0 .. r0+Lc-1 <= m+1 never wrap (only the halo rows can)
+        const double *base = col + (L > 0 ? r0 * ldf : 0);
+        if (Lc == K) {
+#pragma unroll
+            for (int k = 0; k < K; k++) v[k] = act ? __builtin_nontemporal_load(base + k * ldf) : 0.0;
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; k++) v[k] = (act && k < Lc) ? base[k * ldf] : 0.0;
+        }
+        if (last) {
+            const double cm2 = act ? col[(m - 2) * ldf] : 0.0, cm1 = act ? col[(m - 1) * ldf] : 0.0;
+            const double c_m = act ? col[m * ldf] : 0.0, c_m1 = act ? col[(m + 1) * ldf] : 0.0;
+            const double c0 = act ? col[0] : 0.0, c1 = act ? col[ldf] : 0.0;
+            ft0 = cn_row(cd, cyc_ld(n), m, cm2, cm1, c_m, c_m1, c0);
+            ft1 = cn_row(cd, cyc_ld(n), m + 1, cm1, c_m, c_m1, c0, c1);
+        }
+        double p2 = h0, p1 = h1;  // C_{k-2}, C_{k-1}
 #pragma unroll
         for (int k = 0; k < K; k++) {
-            const double f = cn_row(cd_, n, k < L ? r0 + k : 0, wv[k], wv[k + 1], wv[k + 2], wv[k + 3],
-                                    wv[k + 4]);
-            wv[k] = k < L ? f : 0.0;  // wv[k] is not needed by later rows
+            const double ck = v[k];
+            const double n1 = k + 1 < K ? v[k + 1] : h2;
+            const double n2 = k + 2 < K ? v[k + 2] : (k + 2 == K ? h2 : h3);
+            // rows past the E rows read zero padding (no select: the
+            // addresses stay affine in k, scalar loads with immediate offsets)
+            const double f = cn_row(cd, cyc_ld(n), r0 + k, p2, p1, ck, n1, n2);
+            v[k] = k < L ? f : 0.0;
+            p2 = p1;
+            p1 = ck;
         }
-#pragma unroll
-        for (int k = 0; k < K; k++) v[k] = wv[k];
     } else {
         const double *base = col + (L > 0 ? r0 * ldf : 0);
         if (L == K) {
@@ -265,55 +338,90 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(K == 64 
 #pragma unroll
             for (int k = 0; k < K; k++) v[k] = (act && k < L) ? base[k * ldf] : 0.0;
         }
-        if (first) {
+        if (last) {
             ft0 = act ? col[m * ldf] : 0.0;
             ft1 = act ? col[(m + 1) * ldf] : 0.0;
         }
     }
 
+    // partial products of the border rows with the block: p_q = sum over its
+    // rows of (h^T E^{-1})[q][i] f_i, rows in order; the group's sum (waves
+    // in order) is posted for the tile's last group, which adds the groups
+    // in order: h^T E^{-1} f^ with one fixed summation order.
+    {
+        double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            const int64_t i = r0 + k;
+            p0 = fma(Wt[2 * i], v[k], p0);
+            p1 = fma(Wt[2 * i + 1], v[k], p1);
+        }
+        sp[w][0][lane] = p0;
+        sp[w][1][lane] = p1;
+    }
+    __syncthreads();
+    if (w == 0) {
+        double P0 = 0.0, P1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < W; i++) {
+            P0 += sp[i][0][lane];
+            P1 += sp[i][1][lane];
+        }
+        double *mp = pex + (int64_t)u * 128 + lane;
+        xstore(&mp[0], P0);
+        xstore(&mp[64], P1);
+        publish(&pst[u], 1u);
+    }
+
     group_phases<K, W>(v, fwd, bwd, seg, r0, w, g, ngroups, u - (unsigned int)g, fst, bst, ex, err,
                        sh);
 
-    // post y_{m-2}, y_{m-1} if this block holds them
-    double *tx = tex + (int64_t)t * 256 + lane;
-    const int64_t k2 = m - 2 - r0, k1 = m - 1 - r0;
-    const bool has2 = k2 >= 0 && k2 < L, has1 = k1 >= 0 && k1 < L;
-    if (has2 || has1) {
-        double y2 = 0.0, y1 = 0.0;
-#pragma unroll
-        for (int k = 0; k < K; k++) {
-            if (k == k2) y2 = v[k];
-            if (k == k1) y1 = v[k];
-        }
-        if (has2) xstore(&tx[128], y2);
-        if (has1) xstore(&tx[192], y1);
-        store_fence();
-        atomicAdd(&tst[2 * t + 1], threadIdx.x % 64 == 0 ? (unsigned int)(has2 + has1) : 0u);
-    }
-
+    double *tx = tex + (int64_t)t * 128 + lane;
     double xt0, xt1;
-    if (first) {
-        wait_nonzero(&tst[2 * t + 1], 2u, err);
-        const double ym2 = xload(&tx[128]), ym1 = xload(&tx[192]);
-        double r0v = ft0, r1v = ft1;
-        const int nh = aux->nh;
-        for (int q = 0; q < nh; q++) {
-            const int64_t c = aux->hcol[q];
-            const double y = c == 0 ? v[0] : c == 1 ? v[1] : c == m - 2 ? ym2 : ym1;
-            if (aux->hq[q] == 0) r0v = fma(-aux->hv[q], y, r0v);
-            else r1v = fma(-aux->hv[q], y, r1v);
+    if (last) {
+        // every group's partial products, in group order (windows of 64)
+        const unsigned int u0 = u - (unsigned int)g;
+        for (int b0 = 0; b0 < ngroups; b0 += 64) {
+            for (int spin = 0;; spin++) {
+                const bool in = b0 + lane < ngroups;
+                const unsigned int st = lane_status(pst, (int64_t)u0 + b0 + lane, in);
+                if (__ballot(in && st == 0) == 0) break;
+                if (spin >= kSpin) {
+                    atomicOr(err, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
         }
+        double d0 = 0.0, d1 = 0.0;
+        for (int q0 = 0; q0 < ngroups; q0 += 8) {
+            double a0[8], a1[8];
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                const double *pp = pex + (int64_t)(u0 + q0 + i) * 128 + lane;
+                a0[i] = q0 + i < ngroups ? xload(&pp[0]) : 0.0;
+                a1[i] = q0 + i < ngroups ? xload(&pp[64]) : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                if (q0 + i < ngroups) {
+                    d0 += a0[i];
+                    d1 += a1[i];
+                }
+            }
+        }
+        const double r0v = ft0 - d0, r1v = ft1 - d1;
         xt0 = fma(aux->minv[1], r1v, aux->minv[0] * r0v);
         xt1 = fma(aux->minv[3], r1v, aux->minv[2] * r0v);
         xstore(&tx[0], xt0);
         xstore(&tx[64], xt1);
-        publish(&tst[2 * t], 1u);
+        publish(&tst[t], 1u);
         if (act) {
             X[jj + m * ldx] = xt0;
             X[jj + (m + 1) * ldx] = xt1;
         }
     } else {
-        wait_nonzero(&tst[2 * t], 1u, err);
+        wait_nonzero(&tst[t], 1u, err);
         xt0 = xload(&tx[0]);
         xt1 = xload(&tx[64]);
     }
@@ -357,11 +465,13 @@ int64_t cyc_onepass_units(int64_t n, int seg_rows, int64_t batch)
     return (batch + 63) / 64 * cyc_groups(n, seg_rows);
 }
 
+// words: tickets, forward / backward / partial-product statuses per unit,
+// x_tail status per tile
 static size_t cyc_words(int64_t n, int seg_rows, int64_t batch)
 {
     const int64_t units = cyc_onepass_units(n, seg_rows, batch);
     const int64_t tiles = (batch + 63) / 64;
-    return (size_t)(kTicketWords + 2 * units + 2 * tiles);
+    return (size_t)(kTicketWords + 3 * units + tiles);
 }
 
 size_t cyc_onepass_scratch_bytes(int64_t n, int seg_rows, int64_t batch)
@@ -369,7 +479,7 @@ size_t cyc_onepass_scratch_bytes(int64_t n, int seg_rows, int64_t batch)
     const int64_t units = cyc_onepass_units(n, seg_rows, batch);
     const int64_t tiles = (batch + 63) / 64;
     const size_t wbytes = (cyc_words(n, seg_rows, batch) * sizeof(unsigned int) + 255) / 256 * 256;
-    return wbytes + (size_t)(units * 8 * 64 + tiles * 4 * 64) * sizeof(double);
+    return wbytes + (size_t)(units * (8 + 2) * 64 + tiles * 2 * 64) * sizeof(double);
 }
 
 template <int K, int W>
@@ -397,7 +507,8 @@ int cyc_onepass_capacity(int seg_rows, bool cn)
 }
 
 hipError_t launch_cyc_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg,
-                              const double *cd, const double *Z, const CycAux *aux, int64_t n,
+                              const double *cd, const double *Z, const double *Wt,
+                              const CycAux *aux, int64_t n,
                               int seg_rows, bool cn, const double *Fin, int64_t ldf, double *X,
                               int64_t ldx, int64_t batch, void *scratch, unsigned int *err,
                               hipStream_t s)
@@ -410,18 +521,20 @@ hipError_t launch_cyc_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec
     const int64_t words = (int64_t)cyc_words(n, seg_rows, batch);
     unsigned int *w = (unsigned int *)scratch;
     unsigned int *ctr = w, *fst = w + kTicketWords, *bst = w + kTicketWords + units,
-                 *tst = w + kTicketWords + 2 * units;
+                 *pst = w + kTicketWords + 2 * units, *tst = w + kTicketWords + 3 * units;
     const size_t wbytes = ((size_t)words * sizeof(unsigned int) + 255) / 256 * 256;
     double *ex = (double *)((char *)scratch + wbytes);
-    double *tex = ex + units * 8 * 64;
+    double *pex = ex + units * 8 * 64;
+    double *tex = pex + units * 2 * 64;
     hipLaunchKernelGGL(k_cyc_zero, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, w, words);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int ng = (int)ngroups;
-    void *args[] = {(void *)&fwd, (void *)&bwd, (void *)&seg, (void *)&cd, (void *)&Z, (void *)&aux,
-                    (void *)&n, (void *)&ng, (void *)&Fin, (void *)&ldf, (void *)&X, (void *)&ldx,
-                    (void *)&batch, (void *)&ctr, (void *)&fst, (void *)&bst, (void *)&tst,
-                    (void *)&ex, (void *)&tex, (void *)&err};
+    void *args[] = {(void *)&fwd, (void *)&bwd, (void *)&seg, (void *)&cd, (void *)&Z, (void *)&Wt,
+                    (void *)&aux, (void *)&n, (void *)&ng, (void *)&Fin, (void *)&ldf, (void *)&X,
+                    (void *)&ldx, (void *)&batch, (void *)&ctr, (void *)&fst, (void *)&bst,
+                    (void *)&pst, (void *)&tst, (void *)&ex, (void *)&pex, (void *)&tex,
+                    (void *)&err};
     return hipLaunchKernel(cyc_fn_kw(seg_rows, W, cn), dim3((unsigned)units), dim3(64 * W), args, 0,
                            s);
 }
@@ -442,6 +555,18 @@ hipError_t launch_cyc_build(const double *cd, int64_t n, int64_t zrows, double *
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_cyc_build_k, dim3((unsigned)((zrows + 255) / 256)), dim3(256), 0, s, cd, n,
                        zrows, K);
+    return hipGetLastError();
+}
+
+hipError_t launch_cyc_build_transposed(const double *cd, int64_t n, int64_t zrows, double *etd,
+                                       double *H, hipStream_t s)
+{
+    const int64_t m = n - 2;
+    hipLaunchKernelGGL(k_cyc_build_Et, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, cd, n, etd);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cyc_build_H, dim3((unsigned)((zrows + 255) / 256)), dim3(256), 0, s, cd, n,
+                       zrows, H);
     return hipGetLastError();
 }
 

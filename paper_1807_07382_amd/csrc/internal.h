@@ -251,7 +251,10 @@ hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *se
                           hipStream_t s);
 
 // ---- periodic matrices by bordering (cyclic.hip) ----
-// cd: 5n cyclic row-indexed diagonals on the device (a, b, c, d, e blocks).
+// cd: cyclic row-indexed diagonals on the device, five blocks (a, b, c, d, e)
+// of cyc_ld(n) doubles each; entries past row n-1 are zero (so kernels may
+// read coefficients of padded rows without a guard).
+__host__ __device__ inline int64_t cyc_ld(int64_t n) { return (n + kRecPad - 1) / kRecPad * kRecPad; }
 hipError_t launch_cyc_assemble_d4(double *cd, int64_t n, double sigma, hipStream_t s);
 // ed: 5(n-2) diagonals of the leading block E; K: zrows x 2, ld 2 (rows past
 // n-2 zero).
@@ -264,12 +267,17 @@ int64_t cyc_onepass_units(int64_t n, int seg_rows, int64_t batch);
 size_t cyc_onepass_scratch_bytes(int64_t n, int seg_rows, int64_t batch);
 int cyc_onepass_capacity(int seg_rows, bool cn);
 hipError_t launch_cyc_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg,
-                              const double *cd, const double *Z, const CycAux *aux, int64_t n,
+                              const double *cd, const double *Z, const double *Wt,
+                              const CycAux *aux, int64_t n,
                               int seg_rows, bool cn, const double *Fin, int64_t ldf, double *X,
                               int64_t ldx, int64_t batch, void *scratch, unsigned int *err,
                               hipStream_t s);
 hipError_t launch_cyc_finish(const double *cd, int64_t n, const double *Z, CycAux *aux,
                              hipStream_t s);
+// etd: 5(n-2) diagonals of E^T; H: zrows x 2, ld 2, H[i][q] = A[n-2+q][i]
+// for i < n-2, zero below.
+hipError_t launch_cyc_build_transposed(const double *cd, int64_t n, int64_t zrows, double *etd,
+                                       double *H, hipStream_t s);
 // F rows 0..n-3 hold y = E^{-1} f^ on entry; rows n-2, n-1 hold f's tail.
 // On exit F holds x.  No scratch.
 hipError_t launch_cyc_correct(const CycAux *aux, const double *Z, double *F, int64_t n,
