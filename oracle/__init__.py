@@ -215,3 +215,37 @@ def dense(diags: Diagonals) -> np.ndarray:
             if 0 <= k < n:
                 A[i, k] = v[i]
     return A
+
+
+class SystemZeroPivot(ArithmeticError):
+    """Factorisation of one system's own matrix stopped (system j, row i)."""
+
+    def __init__(self, system: int, row: int):
+        super().__init__(f"system {system}: zero or non-finite pivot at row {row}")
+        self.system = system
+        self.row = row
+
+
+def rewrite_solve(a, b, c, d, e, F) -> np.ndarray:
+    """Every system with its own matrix, factored and solved in one call
+    (the paper's refactor-every-step benchmark mode, Sec. 3): column j of
+    a..e (each of shape (n, batch), row-indexed like `Diagonals`, batch
+    fastest) is the matrix of system j, column j of F its right-hand side.
+    Each system goes through the Sec. 2.4 factorisation and sweeps above.
+    Raises SystemZeroPivot(j, i)."""
+    arrs = [np.asarray(x, dtype=np.float64) for x in (a, b, c, d, e)]
+    F = np.asarray(F, dtype=np.float64)
+    n, m = F.shape
+    if any(x.shape != (n, m) for x in arrs):
+        raise ValueError("diagonals and F must all have shape (n, batch)")
+    X = np.empty_like(F)
+    for j in range(m):
+        dg = Diagonals(*(np.ascontiguousarray(x[:, j]) for x in arrs))
+        try:
+            fac = factor(dg)
+        except ZeroPivot as exc:
+            raise SystemZeroPivot(j, exc.row) from None
+        col = np.array(F[:, j:j + 1], order="C", copy=True)  # never the caller's F
+        solve_inplace(dg, fac, col)
+        X[:, j] = col[:, 0]
+    return X
