@@ -217,6 +217,26 @@ int pent_ch2d_rhs(const double *C, double *R, int64_t ny, int64_t ninst, int64_t
 int pent_ch2d_step(pent_handle hx, pent_handle hy, double *C, double *R, int64_t ny,
                    int64_t ninst, int64_t nx, const double *dt, double h, void *stream);
 
+/* ------------------------------------------- per-system matrices --
+ * Every system with its own matrix, factored and solved in one call: the
+ * paper's refactor-every-step mode (Sec. 3), for matrices that change
+ * between time steps (or differ between systems).  a..e: DEVICE FP64, the
+ * row-indexed diagonals of system j at a[i*ldm + j] (same convention as
+ * pent_factor; a[0], a[1], b[0], d[n-1], e[n-2], e[n-1] of each system are
+ * ignored); read only.  F: DEVICE FP64, F[i*ld + j], overwritten with X.
+ * ldm, ld >= batch.  work: DEVICE, at least pent_rewrite_workspace_size(n,
+ * batch) bytes (16 n batch + 256), caller-owned; asynchronous on `stream`.
+ * No pivoting (Sec. 2.4): a zero or non-finite pivot leaves that system's
+ * X non-finite; pent_rewrite_check (blocking, after the solve) reports the
+ * lowest-numbered such system and its row as PENT_ZERO_PIVOT.
+ * Returns PENT_INVALID_VALUE / PENT_SIZE_MISMATCH synchronously before any
+ * HIP call. */
+size_t pent_rewrite_workspace_size(int64_t n, int64_t batch);
+int pent_solve_rewrite(int64_t n, const double *a, const double *b, const double *c,
+                       const double *d, const double *e, int64_t ldm, double *F, int64_t batch,
+                       int64_t ld, void *work, size_t work_bytes, void *stream);
+int pent_rewrite_check(const void *work, int64_t n, int64_t *system, int64_t *row);
+
 /* ------------------------------------------------ periodic matrices --
  * Cyclic pentadiagonal matrices (Sec. 2.3): the periodic fourth-derivative
  * matrix wraps round the corners, so row i couples columns (i-2) mod n ..

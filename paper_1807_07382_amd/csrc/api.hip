@@ -1308,6 +1308,42 @@ int pent_cyclic_destroy(pent_cyclic c)
     return ret(PENT_OK);
 }
 
+size_t pent_rewrite_workspace_size(int64_t n, int64_t batch)
+{
+    if (n < 1 || batch < 0) return 0;
+    return rewrite_workspace_bytes(n, batch);
+}
+
+int pent_solve_rewrite(int64_t n, const double *a, const double *b, const double *c,
+                       const double *d, const double *e, int64_t ldm, double *F, int64_t batch,
+                       int64_t ld, void *work, size_t work_bytes, void *stream)
+{
+    if (n < 1 || n > INT32_MAX || batch < 0 || ldm < batch || ld < batch)
+        return ret(PENT_INVALID_VALUE);
+    if (batch == 0) return ret(PENT_OK);
+    if (!a || !b || !c || !d || !e || !F || !work) return ret(PENT_INVALID_VALUE);
+    if (work_bytes < rewrite_workspace_bytes(n, batch)) return ret(PENT_SIZE_MISMATCH);
+    return ret(hip_status(launch_rewrite(a, b, c, d, e, ldm, n, F, batch, ld, work,
+                                         (hipStream_t)stream)));
+}
+
+int pent_rewrite_check(const void *work, int64_t n, int64_t *system, int64_t *row)
+{
+    if (!work || n < 1) return ret(PENT_INVALID_VALUE);
+    unsigned long long key = 0;
+    hipError_t e = hipMemcpy(&key, work, sizeof(key), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return ret(hip_status(e));
+    if (key == ~0ull) {
+        if (system) *system = -1;
+        if (row) *row = -1;
+        return ret(PENT_OK);
+    }
+    if (system) *system = (int64_t)(key / (unsigned long long)n);
+    if (row) *row = (int64_t)(key % (unsigned long long)n);
+    g_pivot_row = (int64_t)(key % (unsigned long long)n);
+    return ret(PENT_ZERO_PIVOT);
+}
+
 int pent_solve_strided(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream)
 {
     if (!valid(h) || batch < 0 || ld < h->n) return ret(PENT_INVALID_VALUE);

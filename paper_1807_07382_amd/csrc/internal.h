@@ -250,6 +250,14 @@ hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *se
                           int64_t ldx, int64_t batch, void *scratch, unsigned int *err,
                           hipStream_t s);
 
+// ---- per-system matrices, refactored every call (rewrite.hip) ----
+// work: 256 bytes of header (first failing pivot key, system * n + row) and
+// gamma, delta (n x batch each, row stride batch).
+size_t rewrite_workspace_bytes(int64_t n, int64_t batch);
+hipError_t launch_rewrite(const double *a, const double *b, const double *c, const double *d,
+                          const double *e, int64_t ldm, int64_t n, double *F, int64_t batch,
+                          int64_t ld, void *work, hipStream_t s);
+
 // ---- periodic matrices by bordering (cyclic.hip) ----
 // cd: cyclic row-indexed diagonals on the device, five blocks (a, b, c, d, e)
 // of cyc_ld(n) doubles each; entries past row n-1 are zero (so kernels may

@@ -32,6 +32,7 @@ CAHN2D = dict(nx=1024, ninst=32, sigma=200.0, steps=50, seed=3)
 PRECISION = dict(n=8192, batch=131072, sigmas=(1.0, 1e2, 1e4), seed=4)
 GROUP = dict(count=48, steps=200, seed=5)
 PERIODIC = dict(n=4096, sigma=50.0, batch=65536, steps=250, seed=6)
+REWRITE = dict(n=1024, batch=65536, seed=7)
 
 
 def rng(seed: int) -> np.random.Generator:
@@ -66,6 +67,13 @@ def periodic(seed: int = PERIODIC["seed"], n: int = PERIODIC["n"],
     """Periodic Crank-Nicolson hyperdiffusion batch: C^0 uniform[-1, 1) per
     system (the step matrix is the same for every system)."""
     return dict(n=n, sigma=PERIODIC["sigma"], C0=uniform(seed, (n, batch)))
+
+
+def rewrite(seed: int = REWRITE["seed"], n: int = REWRITE["n"], batch: int = REWRITE["batch"]):
+    """A matrix per system: sigma_j = 10^U(-2, 4) (system j = I + sigma_j D4),
+    right-hand sides uniform[-1, 1)."""
+    g = rng(seed)
+    return dict(n=n, sigma=10.0 ** g.uniform(-2.0, 4.0, size=batch), F=uniform(seed + 1000, (n, batch)))
 
 
 def cahn2d(seed: int = CAHN2D["seed"], nx: int = CAHN2D["nx"], ninst: int = CAHN2D["ninst"]):

@@ -67,6 +67,10 @@ SIGNATURES = {
     "pent_cyclic_set_schedule": (_I, [_P, _I, _I]),
     "pent_cyclic_query_schedule": (_I, [_P, _I64, _I, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "pent_cyclic_check": (_I, [_P]),
+    "pent_rewrite_workspace_size": (ctypes.c_size_t, [_I64, _I64]),
+    "pent_solve_rewrite": (_I, [_I64, _P, _P, _P, _P, _P, _I64, _P, _I64, _I64, _P,
+                                ctypes.c_size_t, _P]),
+    "pent_rewrite_check": (_I, [_P, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     "pent_get_factors": (_I, [_P, _P, _P, _P, _P]),
     "pent_get_diagonals": (_I, [_P, _P, _P, _P, _P, _P]),
     "pent_size": (_I64, [_P]),
@@ -389,6 +393,42 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+class SystemZeroPivotError(PentError):
+    def __init__(self, system: int, row: int):
+        super().__init__(ZERO_PIVOT, f"system {system} stopped at row {row}")
+        self.system = system
+        self.row = row
+
+
+def solve_rewrite_(a, b, c, d, e, F, work=None, stream=None, check=False):
+    """Overwrite F (cuda float64, shape (n, batch)) with the solutions of the
+    systems whose own matrices are the columns of a..e (cuda float64, shape
+    (n, batch), row-indexed), factoring every system in this call.  With
+    ``check`` the call synchronises and raises SystemZeroPivotError."""
+    import torch
+    n, m = F.shape
+    for x in (a, b, c, d, e):
+        if x.shape != (n, m) or (m > 1 and x.stride(1) != 1) or x.stride(0) != a.stride(0):
+            raise ValueError("diagonals must have F's shape, unit batch stride, one row stride")
+    if m > 1 and F.stride(1) != 1:
+        raise ValueError("F needs unit batch stride")
+    nbytes = lib().pent_rewrite_workspace_size(n, m)
+    if work is None:
+        work = torch.empty(nbytes, dtype=torch.uint8, device=F.device)
+    _check(lib().pent_solve_rewrite(n, *[_dptr(x, "float64") for x in (a, b, c, d, e)],
+                                    max(a.stride(0), m), _dptr(F, "float64"), m,
+                                    max(F.stride(0), m), work.data_ptr(),
+                                    work.numel() * work.element_size(), _stream_ptr(stream)),
+           "solve_rewrite")
+    if check:
+        sy, ro = _I64(0), _I64(0)
+        st = lib().pent_rewrite_check(work.data_ptr(), n, ctypes.byref(sy), ctypes.byref(ro))
+        if st == ZERO_PIVOT:
+            raise SystemZeroPivotError(int(sy.value), int(ro.value))
+        _check(st, "rewrite_check")
+    return F
 
 
 class Cyclic:

@@ -125,3 +125,19 @@ def test_cyclic_rejects_bad_arguments_without_hip():
     h = ctypes.cast(junk, ctypes.c_void_p)
     assert L.pent_cyclic_solve(h, buf, 1, 1, None) == pb.INVALID_VALUE
     assert L.pent_cyclic_destroy(h) == pb.INVALID_VALUE
+
+
+def test_rewrite_rejects_bad_arguments_without_hip():
+    L = pb.lib()
+    buf = (ctypes.c_double * 64)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    need = L.pent_rewrite_workspace_size(8, 4)
+    assert need == 256 + 16 * 8 * 4
+    assert L.pent_rewrite_workspace_size(0, 4) == 0
+    assert L.pent_solve_rewrite(0, p, p, p, p, p, 4, p, 4, 4, p, need, None) == pb.INVALID_VALUE
+    assert L.pent_solve_rewrite(8, p, p, p, p, p, 3, p, 4, 4, p, need, None) == pb.INVALID_VALUE
+    assert L.pent_solve_rewrite(8, p, p, p, p, p, 4, p, 4, 3, p, need, None) == pb.INVALID_VALUE
+    assert L.pent_solve_rewrite(8, None, p, p, p, p, 4, p, 4, 4, p, need, None) == pb.INVALID_VALUE
+    assert L.pent_solve_rewrite(8, p, p, p, p, p, 4, p, 4, 4, p, need - 1, None) == pb.SIZE_MISMATCH
+    assert L.pent_solve_rewrite(8, p, p, p, p, p, 4, p, 0, 4, p, need, None) == pb.OK
+    assert L.pent_rewrite_check(None, 8, None, None) == pb.INVALID_VALUE
