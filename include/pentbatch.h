@@ -178,13 +178,17 @@ int pent_group_autotune(pent_group g, const int64_t *batch, int *variant_out, do
  * manual tuning).  0..3: one workgroup per work item, 64/32/64/32 rows per
  * segment with 8/8/4/4 waves; 4, 5: one-wave tasks (item, segment) drawn
  * independently, 64/32 rows per segment, pass-2 tasks waiting (bounded) on
- * a per-item flag the last pass-1 task sets.  PENT_INVALID_VALUE for an
- * unknown variant. */
+ * a per-item flag the last pass-1 task sets; 6: the single pass over all
+ * matrices (pent_set_schedule kind 4 with 64-row segments, two per
+ * workgroup, units of every matrix in one launch; f read once, x written
+ * once), which falls back to variant 0 when the deepest 64-system tile
+ * would not fit on the device at once.  PENT_INVALID_VALUE for an unknown
+ * variant. */
 int pent_group_set_variant(pent_group g, int variant);
 
 /* Blocking check of the group's device status after its solves: PENT_OK, or
- * PENT_TIMEOUT if a bounded wait of variants 4/5 ran out (then results of
- * that launch are incomplete). */
+ * PENT_TIMEOUT if a bounded wait of variants 4, 5 or 6 ran out (then results
+ * of that launch are incomplete). */
 int pent_group_check(pent_group g);
 
 /* Capture `steps` consecutive group solves (mode as above) on `stream` into

@@ -330,6 +330,10 @@ struct pent_group_s {
     int ntasks64 = 0, ntasks32 = 0;
     unsigned int *d_cnt = nullptr;  // per-item pass-1 completion count
     unsigned int *d_ready = nullptr;  // per-item interface-ready flag
+    GroupUnit *d_units = nullptr;   // single-pass unit table (variant 6)
+    int64_t nunits = 0;
+    int64_t max_groups = 0;         // deepest tile of the single pass, in units
+    int onepass_cap = 0;            // co-resident single-pass workgroups (0: unknown)
     int variant = 0;                // group kernel variant (autotuned)
 };
 
@@ -347,7 +351,7 @@ struct pent_cyclic_s {
     double *d_W = nullptr;      // E->npad x 2, ld 2: (h^T E^{-1})^T (rows past n-2 zero)
     CycAux *d_aux = nullptr;    // sparse h^T and [C2 - h^T Z]^{-1}
     int kind = 0;               // 0 automatic, 1 E-solve + update kernels, 2 single pass
-    int seg_rows = 32;          // single-pass segment height
+    int seg_rows = 64;          // single-pass segment height
     int cap[2][2] = {{0, 0}, {0, 0}};  // co-resident single-pass units [seg 32/64][solve/CN]
 };
 
@@ -502,6 +506,7 @@ void free_group(pent_group g)
     if (g->d_tasks32) (void)hipFree(g->d_tasks32);
     if (g->d_cnt) (void)hipFree(g->d_cnt);
     if (g->d_ready) (void)hipFree(g->d_ready);
+    if (g->d_units) (void)hipFree(g->d_units);
     g->magic = 0;
     delete g;
 }
@@ -518,9 +523,31 @@ int64_t group_summ_doubles(const pent_group g, const int64_t *batch)
     return 2 * tot;
 }
 
+constexpr int kGroupOnepassVariant = 6;  // the single pass over all matrices
+int group_variant_count() { return group_variants() + 1; }
+
+int64_t group_onepass_units(const pent_group g, const int64_t *batch)
+{
+    const int64_t rows = group_onepass_rows();
+    int64_t u = 0;
+    for (size_t k = 0; k < g->plans.size(); k++)
+        u += (batch[k] + 63) / 64 * ((g->plans[k]->n + rows - 1) / rows);
+    return u;
+}
+
+// Whether the bound work list can run as one single pass: every workgroup of
+// the deepest tile fits on the device at once, with room to spare.
+bool group_onepass_ok(pent_group g)
+{
+    if (g->onepass_cap == 0) g->onepass_cap = group_onepass_capacity();
+    return g->onepass_cap > 0 && g->max_groups <= g->onepass_cap / 4 &&
+           g->nunits <= (int64_t)UINT32_MAX / 2;
+}
+
 size_t group_ws_bytes(const pent_group g, const int64_t *batch)
 {
     size_t b = align256(sizeof(double) * (size_t)group_summ_doubles(g, batch));
+    b = std::max(b, group_onepass_scratch_bytes(group_onepass_units(g, batch)));
     for (size_t k = 0; k < g->plans.size(); k++) {
         int kind, seg_rows;
         io_schedule(g->plans[k], batch[k], true, &kind, &seg_rows);
@@ -579,10 +606,23 @@ int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64
         for (int64_t sg = 0; sg < (n + 31) / 32; sg++) t32.push_back(make_int2((int)i, (int)sg));
     }
     if (t32.size() > (size_t)INT32_MAX / 2) return PENT_NOT_SUPPORTED;
+    // unit table of the single pass: every item's row groups, consecutive,
+    // items in work-list order (longest first)
+    std::vector<GroupUnit> units;
+    int64_t max_groups = 0;
+    const int64_t orows = group_onepass_rows();
+    for (size_t i = 0; i < items.size(); i++) {
+        const int64_t ng = (mats[items[i].mat].n + orows - 1) / orows;
+        max_groups = std::max(max_groups, ng);
+        const int64_t u0 = (int64_t)units.size();
+        for (int64_t q = 0; q < ng; q++)
+            units.push_back(GroupUnit{items[i].mat, (int)q, (int)ng, 0, items[i].col0, u0});
+    }
     GroupMat *dm = nullptr;
     GroupItem *di = nullptr;
     int2 *d64 = nullptr, *d32 = nullptr;
     unsigned int *dc = nullptr, *dr = nullptr;
+    GroupUnit *du = nullptr;
     const size_t ni = std::max<size_t>(items.size(), 1);
     hipError_t e = hipMalloc(&dm, sizeof(GroupMat) * std::max<size_t>(cnt, 1));
     if (e == hipSuccess) e = hipMalloc(&di, sizeof(GroupItem) * ni);
@@ -590,6 +630,9 @@ int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64
     if (e == hipSuccess) e = hipMalloc(&d32, sizeof(int2) * std::max<size_t>(t32.size(), 1));
     if (e == hipSuccess) e = hipMalloc(&dc, sizeof(unsigned int) * ni);
     if (e == hipSuccess) e = hipMalloc(&dr, sizeof(unsigned int) * ni);
+    if (e == hipSuccess) e = hipMalloc(&du, sizeof(GroupUnit) * std::max<size_t>(units.size(), 1));
+    if (e == hipSuccess && !units.empty())
+        e = hipMemcpy(du, units.data(), sizeof(GroupUnit) * units.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess && cnt) e = hipMemcpy(dm, mats.data(), sizeof(GroupMat) * cnt, hipMemcpyHostToDevice);
     if (e == hipSuccess && !items.empty())
         e = hipMemcpy(di, items.data(), sizeof(GroupItem) * items.size(), hipMemcpyHostToDevice);
@@ -601,13 +644,18 @@ int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64
     if (e == hipSuccess) e = launch_zero_u32(dr, (int)ni, 0);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
-        for (void *q : {(void *)dm, (void *)di, (void *)d64, (void *)d32, (void *)dc, (void *)dr})
+        for (void *q : {(void *)dm, (void *)di, (void *)d64, (void *)d32, (void *)dc, (void *)dr,
+                        (void *)du})
             if (q) (void)hipFree(q);
         return hip_status(e);
     }
     for (void *q : {(void *)g->d_mats, (void *)g->d_items, (void *)g->d_tasks64,
-                    (void *)g->d_tasks32, (void *)g->d_cnt, (void *)g->d_ready})
+                    (void *)g->d_tasks32, (void *)g->d_cnt, (void *)g->d_ready,
+                    (void *)g->d_units})
         if (q) (void)hipFree(q);
+    g->d_units = du;
+    g->nunits = (int64_t)units.size();
+    g->max_groups = max_groups;
     g->d_mats = dm;
     g->d_items = di;
     g->d_tasks64 = d64;
@@ -630,7 +678,13 @@ int group_enqueue(pent_group g, int mode, void *work, hipStream_t s)
 {
     if (mode == 0) {
         if (g->nitems == 0) return PENT_OK;
-        const int v = g->variant;
+        int v = g->variant;
+        if (v == kGroupOnepassVariant) {
+            if (group_onepass_ok(g))
+                return hip_status(launch_group_onepass(g->d_mats, g->d_units, g->nunits, work,
+                                                       &g->d_ctr[2], s));
+            v = 0;  // a tile too deep for the device: the persistent kernel
+        }
         const bool tasks = group_variant_is_tasks(v);
         const bool k64 = group_variant_seg_rows(v) == 64;
         const int ntasks = k64 ? g->ntasks64 : g->ntasks32;
@@ -1040,7 +1094,8 @@ int pent_group_autotune(pent_group g, const int64_t *batch, int *variant_out, do
     const int saved = g->variant;
     int best_v = saved;
     double best = 1e300;
-    for (int v = 0; st == PENT_OK && v < group_variants(); v++) {
+    for (int v = 0; st == PENT_OK && v < group_variant_count(); v++) {
+        if (v == kGroupOnepassVariant && !group_onepass_ok(g)) continue;
         g->variant = v;
         double ms = 0.0;
         st = time_ms([&] { return group_enqueue(g, 0, work, s); }, s, 3, &ms);
@@ -1064,7 +1119,7 @@ int pent_group_autotune(pent_group g, const int64_t *batch, int *variant_out, do
 
 int pent_group_set_variant(pent_group g, int variant)
 {
-    if (!gvalid(g) || variant < 0 || variant >= group_variants()) return ret(PENT_INVALID_VALUE);
+    if (!gvalid(g) || variant < 0 || variant >= group_variant_count()) return ret(PENT_INVALID_VALUE);
     g->variant = variant;
     return ret(PENT_OK);
 }

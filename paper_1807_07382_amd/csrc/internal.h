@@ -89,6 +89,18 @@ struct CycAux {
     double minv[4];
 };
 
+// One unit of the single-pass group solve: rows [g*rows, (g+1)*rows) of
+// the 64 systems of matrix `mat` that start at col0; u0 = index of the
+// first unit of that tile (its units are consecutive).
+struct GroupUnit {
+    int mat;
+    int g;
+    int ngroups;
+    int pad;
+    int64_t col0;
+    int64_t u0;
+};
+
 constexpr int kMaxSegCaches = 3;  // seg_rows 16, 32, 64
 constexpr int kSegPad = 16;       // segment records are padded to a multiple of this
 
@@ -257,6 +269,13 @@ size_t rewrite_workspace_bytes(int64_t n, int64_t batch);
 hipError_t launch_rewrite(const double *a, const double *b, const double *c, const double *d,
                           const double *e, int64_t ldm, int64_t n, double *F, int64_t batch,
                           int64_t ld, void *work, hipStream_t s);
+
+// ---- single pass over many matrices (onepass.hip, group variant 6) ----
+int group_onepass_rows();              // rows per unit (segments x 64 rows)
+int group_onepass_capacity();          // co-resident workgroups on the current device
+size_t group_onepass_scratch_bytes(int64_t units);
+hipError_t launch_group_onepass(const GroupMat *mats, const GroupUnit *units, int64_t nunits,
+                                void *scratch, unsigned int *err, hipStream_t s);
 
 // ---- periodic matrices by bordering (cyclic.hip) ----
 // cd: cyclic row-indexed diagonals on the device, five blocks (a, b, c, d, e)

@@ -64,6 +64,48 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(K == 64 
     }
 }
 
+// Many matrices in one launch: the unit table lists (matrix, 64-system
+// tile, row group) with each tile's groups consecutive; otherwise as
+// k_onepass.
+template <int K, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(K == 64 ? 2 : 3))) void k_group_onepass(
+    const GroupMat *__restrict__ mats, const GroupUnit *__restrict__ units, unsigned int *ctr,
+    unsigned int *fst, unsigned int *bst, double *ex, unsigned int *err)
+{
+    __shared__ double sh[W + 1][2][64];
+    __shared__ unsigned int s_unit;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+    const int lane = threadIdx.x & 63;
+    if (w == 0) s_unit = take_unit(ctr);  // every lane of wave 0 stores the same value
+    __syncthreads();
+    const unsigned int u = (unsigned int)__builtin_amdgcn_readfirstlane((int)s_unit);
+    const GroupUnit un = units[u];
+    const GroupMat m = mats[un.mat];
+    const CFwd fwd = (CFwd)m.fwd;
+    const CBwd bwd = (CBwd)m.bwd;
+    const CSeg seg = (CSeg)m.seg64;
+    const int64_t j = un.col0 + lane;
+    const bool act = j < m.batch;
+    const int64_t jj = act ? j : 0;
+    const int64_t r0 = ((int64_t)un.g * W + w) * K;
+    const int64_t rem = m.n - r0;
+    const int L = (int)(rem < 0 ? 0 : rem < K ? rem : K);
+    double v[K];
+    load_rows<K, double>(v, m.F + jj + (L > 0 ? r0 * m.ld : 0), m.ld, act ? L : 0);
+    group_phases<K, W>(v, fwd, bwd, seg, r0, w, un.g, un.ngroups, (unsigned int)un.u0, fst, bst, ex,
+                       err, sh);
+    if (!act || L == 0) return;
+    double *base = m.F + jj + r0 * m.ld;
+    if (L == K) {
+#pragma unroll
+        for (int k = 0; k < K; k++) __builtin_nontemporal_store(v[k], base + k * m.ld);
+    } else {
+#pragma unroll
+        for (int k = 0; k < K; k++)
+            if (k < L) base[k * m.ld] = v[k];
+    }
+}
+
 __global__ void k_zero_words(unsigned int *p, int64_t count)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -154,6 +196,47 @@ hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *se
                     (void *)&fst, (void *)&bst, (void *)&ex, (void *)&err};
     e = hipLaunchKernel(fn, dim3((unsigned)units), dim3(64 * W), args, 0, s);
     return e;
+}
+
+// ---- group variant 6: 64-row segments, two per workgroup
+constexpr int kGroupK = 64, kGroupW = 2;
+
+int group_onepass_rows() { return kGroupK * kGroupW; }
+
+int group_onepass_capacity()
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, (const void *)k_group_onepass<kGroupK, kGroupW>, 64 * kGroupW, 0) != hipSuccess)
+        return 0;
+    return cus * per_cu;
+}
+
+size_t group_onepass_scratch_bytes(int64_t units)
+{
+    const size_t words = (size_t)(kTicketWords + 2 * units);
+    const size_t wbytes = (words * sizeof(unsigned int) + 255) / 256 * 256;
+    return wbytes + (size_t)units * kExRows * 64 * sizeof(double);
+}
+
+hipError_t launch_group_onepass(const GroupMat *mats, const GroupUnit *units, int64_t nunits,
+                                void *scratch, unsigned int *err, hipStream_t s)
+{
+    if (nunits <= 0) return hipSuccess;
+    if (nunits > (int64_t)UINT32_MAX / 2) return hipErrorInvalidValue;
+    const int64_t words = kTicketWords + 2 * nunits;
+    unsigned int *w = (unsigned int *)scratch;
+    unsigned int *ctr = w, *fst = w + kTicketWords, *bst = w + kTicketWords + nunits;
+    const size_t wbytes = ((size_t)words * sizeof(unsigned int) + 255) / 256 * 256;
+    double *ex = (double *)((char *)scratch + wbytes);
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, w, words);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_group_onepass<kGroupK, kGroupW>), dim3((unsigned)nunits), dim3(64 * kGroupW),
+                       0, s, mats, units, ctr, fst, bst, ex, err);
+    return hipGetLastError();
 }
 
 }  // namespace pent

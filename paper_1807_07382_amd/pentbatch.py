@@ -534,7 +534,7 @@ class Cyclic:
             C, R = R, C
         return C, R
 
-    def set_schedule(self, kind: int, seg_rows: int = 32):
+    def set_schedule(self, kind: int, seg_rows: int = 64):
         """0 automatic, 1 E-solve + update kernels, 2 single pass."""
         _check(lib().pent_cyclic_set_schedule(self._h, int(kind), int(seg_rows)),
                "cyclic set_schedule")

@@ -51,7 +51,7 @@ def test_cyclic_general_against_oracle(torch, n, batch, kind, seg):
     F = rhs(n, batch, seed=n + 1)
     ref = cyclic.solve_cyclic(cyclic.bordering(dg), F)
     with pb.Cyclic.factor(*dg) as cy:
-        cy.set_schedule(kind, seg or 32)
+        cy.set_schedule(kind, seg or 64)
         assert cy.schedule_for(batch)[0] == kind
         T = torch.from_numpy(F.copy()).cuda()
         cy.solve_(T)
@@ -70,7 +70,7 @@ def test_cyclic_d4_against_oracle(torch, n, batch, sigma, kind, seg):
     F = rhs(n, batch, seed=7)
     ref = cyclic.solve_cyclic(cyclic.bordering(cyclic.cyclic_d4(n, sigma)), F)
     with pb.Cyclic.factor_d4(n, sigma) as cy:
-        cy.set_schedule(kind, seg or 32)
+        cy.set_schedule(kind, seg or 64)
         T = torch.from_numpy(F.copy()).cuda()
         cy.solve_(T)
         torch.cuda.synchronize()
@@ -87,7 +87,7 @@ def test_cyclic_leading_dimension(torch, kind, seg):
     buf = torch.full((n, batch + pad), 7.0, dtype=torch.float64, device="cuda")
     buf[:, :batch] = torch.from_numpy(F).cuda()
     with pb.Cyclic.factor(*dg) as cy:
-        cy.set_schedule(kind, seg or 32)
+        cy.set_schedule(kind, seg or 64)
         cy.solve_(buf[:, :batch])
         torch.cuda.synchronize()
     ref = cyclic.solve_cyclic(cyclic.bordering(dg), F)
@@ -137,7 +137,7 @@ def test_cn_step_against_oracle(torch, n, batch, sigma, kind, seg):
     C = rhs(n, batch, seed=n + batch)
     ref = cyclic.cn_run(sigma, C, 1)
     with pb.Cyclic.factor_d4(n, sigma) as cy:
-        cy.set_schedule(kind, seg or 32)
+        cy.set_schedule(kind, seg or 64)
         assert cy.schedule_for(batch, cn=True)[0] == kind
         Ct = torch.from_numpy(C).cuda()
         X = torch.full_like(Ct, 5.0)

@@ -78,14 +78,15 @@ def test_group_deterministic_and_ld(torch):
     g.close()
 
 
-@pytest.mark.parametrize("mode", [0, 1])
-def test_graph_replays_match_eager(torch, mode):
+@pytest.mark.parametrize("mode,variant", [(0, 0), (1, 0), (0, 6)])
+def test_graph_replays_match_eager(torch, mode, variant):
     """A captured graph of 3 steps, replayed 3 times with eager work and
     synchronisations in between: every replay equals the eager result."""
-    print_case(test="graph", mode=mode)
+    print_case(test="graph", mode=mode, variant=variant)
     shapes = [(0.3, 200, 33), (5e3, 3000, 100), (1.0, 64, 8)]
     mats, plans, Ts = make(torch, shapes, seed=11)
     g = pb.Group(plans)
+    g.set_variant(variant)
     init = [T.clone() for T in Ts]
     # eager reference: 3 steps
     for _ in range(3):
@@ -193,7 +194,7 @@ def test_autotune_group_keeps_data(torch):
     torch.cuda.synchronize()
     after_one = [T.clone() for T in Ts]
     v, ms = g.autotune(Ts)
-    assert 0 <= v < 6 and ms > 0
+    assert 0 <= v < 7 and ms > 0
     for a, T in zip(after_one, Ts):
         assert torch.equal(a, T)     # tuning ran on scratch blocks
     g.solve_(Ts)
@@ -205,7 +206,7 @@ def test_autotune_group_keeps_data(torch):
     g.close()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6])
 def test_group_every_variant(torch, variant):
     """Each persistent-kernel variant (64 or 32 rows per segment, 8 or 4
     waves per workgroup) against the oracle, two steps."""
@@ -221,4 +222,28 @@ def test_group_every_variant(torch, variant):
     refs = workloads.group_run(mats, 2)
     for (sigma, _), T, ref in zip(mats, Ts, refs):
         assert np.all(colerr(T.cpu().numpy(), ref) <= 2 * d4_tol(sigma))
+    g.close()
+
+
+def test_group_single_pass_full_shapes(torch):
+    """Variant 6 (the single pass over all matrices) on the 48-matrix
+    workload at its full sizes, 3 steps; sampled systems against the oracle
+    and no timed-out wait."""
+    print_case(test="group_full_v6")
+    mats = inputs.group()
+    plans = [pb.Plan.factor_d4(F.shape[0], s) for s, F in mats]
+    Ts = [torch.from_numpy(F).cuda() for _, F in mats]
+    g = pb.Group(plans)
+    g.set_variant(6)
+    steps = 3
+    for _ in range(steps):
+        g.solve_(Ts)
+    torch.cuda.synchronize()
+    g.check()
+    for k, ((sigma, F), T) in enumerate(zip(mats, Ts)):
+        r = F.shape[1]
+        cols = np.unique(np.array([0, r // 2, r - 1]))
+        ref = workloads.group_run([(sigma, np.ascontiguousarray(F[:, cols]))], steps)[0]
+        X = T[:, torch.from_numpy(cols).cuda()].cpu().numpy()
+        assert np.all(colerr(X, ref) <= steps * d4_tol(sigma)), (k, sigma, F.shape)
     g.close()
