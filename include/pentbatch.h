@@ -333,7 +333,10 @@ int64_t pent_size(pent_handle h); /* n, or -1 for a bad handle */
  *           the blocks of one 64-system tile could not all be resident at
  *           once.  Its waits are bounded; a wait that runs out (only possible
  *           when other work holds most of the device) leaves wrong values in
- *           that solve and is reported by pent_check.
+ *           that solve and is reported by pent_check.  The number of
+ *           segments per workgroup (2 for 64 rows, 4 for 32) can be set to
+ *           2, 4 or 8 with the environment variable PENT_ONEPASS_WAVES,
+ *           read once per process (tuning).
  * Returns PENT_INVALID_VALUE for an unknown kind or seg_rows. */
 int pent_set_schedule(pent_handle h, int kind, int seg_rows);
 

@@ -254,7 +254,7 @@ __device__ __forceinline__ unsigned int wait_nonzero(unsigned int *p, unsigned i
 }
 
 template <int K, int W, bool CN>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(K == 64 ? 2 : 3))) void k_cyc_onepass(
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_cyc_onepass(
     const FwdRec *fwd_, const BwdRec *bwd_, const SegRec *seg_, const double *__restrict__ cd_,
     const double *__restrict__ Z_, const double *__restrict__ Wt_, const CycAux *__restrict__ aux,
     int64_t n, int ngroups, const double *Fin, int64_t ldf, double *X, int64_t ldx, int64_t batch,

@@ -382,6 +382,8 @@ __device__ __forceinline__ void group_matrix(CSeg seg, int64_t s0, double &m0, d
     }
 }
 
+constexpr int kRB = 4;  // replay batch (register budget: v plus 4 kRB doubles)
+
 // Group-level look-back (FWD) or look-ahead: the incoming carry of group g
 // of the tile whose first group unit is u0, given this group's aggregate
 // (c0, c1), which is posted unless the neighbour's inclusive value is
@@ -428,27 +430,27 @@ __device__ __forceinline__ void group_carry(CSeg seg, int g, int ngroups, unsign
     const double *nb = ex + (int64_t)(u0 + pstar) * (kExRows * 64) + lane;
     y0 = xload(&nb[(ra + 2) * 64]);
     y1 = xload(&nb[(ra + 3) * 64]);
-    // replay the groups between pstar and g, innermost first, 8 at a time,
-    // the loads of the next 8 in flight while the current 8 are linked
+    // replay the groups between pstar and g, innermost first, kRB at a time,
+    // the loads of the next kRB in flight while the current kRB are linked
     const int cnt = FWD ? g - 1 - pstar : pstar - g - 1;
     auto group_at = [&](int i) { return FWD ? pstar + 1 + i : pstar - 1 - i; };
-    double w0[8], w1[8], n0[8], n1[8];
+    double w0[kRB], w1[kRB], n0[kRB], n1[kRB];
 #pragma unroll
-    for (int i = 0; i < 8; i++) {
+    for (int i = 0; i < kRB; i++) {
         const double *ag = ex + (int64_t)(u0 + group_at(i)) * (kExRows * 64) + lane;
         w0[i] = i < cnt ? xload(&ag[ra * 64]) : 0.0;
         w1[i] = i < cnt ? xload(&ag[(ra + 1) * 64]) : 0.0;
     }
-    for (int i0 = 0; i0 < cnt; i0 += 8) {
+    for (int i0 = 0; i0 < cnt; i0 += kRB) {
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
-            const int k = i0 + 8 + i;
+        for (int i = 0; i < kRB; i++) {
+            const int k = i0 + kRB + i;
             const double *ag = ex + (int64_t)(u0 + group_at(k)) * (kExRows * 64) + lane;
             n0[i] = k < cnt ? xload(&ag[ra * 64]) : 0.0;
             n1[i] = k < cnt ? xload(&ag[(ra + 1) * 64]) : 0.0;
         }
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
+        for (int i = 0; i < kRB; i++) {
             if (i0 + i < cnt) {
                 double m0, m1, m2, m3;
                 group_matrix<W, FWD>(seg, (int64_t)group_at(i0 + i) * W, m0, m1, m2, m3);
@@ -456,7 +458,7 @@ __device__ __forceinline__ void group_carry(CSeg seg, int g, int ngroups, unsign
             }
         }
 #pragma unroll
-        for (int i = 0; i < 8; i++) {
+        for (int i = 0; i < kRB; i++) {
             w0[i] = n0[i];
             w1[i] = n1[i];
         }

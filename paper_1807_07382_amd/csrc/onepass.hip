@@ -23,10 +23,12 @@ namespace {
 using namespace lb;
 
 // Grouped form: a workgroup of W waves holds W consecutive segments of one
-// 64-system tile (K rows each); see lookback.h.  64-row blocks need up to
-// 256 vector registers (two waves per SIMD), 32-row blocks fit three.
+// 64-system tile (K rows each); see lookback.h.  Three waves per SIMD (at
+// most 168 vector registers): for 64-row blocks this spills a few values of
+// the look-back path, and measured faster than two waves per SIMD without
+// spills (more blocks resident while carries are in flight).
 template <int K, int W, typename TI>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(K == 64 ? 2 : 3))) void k_onepass(
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_onepass(
     const FwdRec *fwd_, const BwdRec *bwd_, const SegRec *seg_, int64_t n, int ngroups,
     const TI *Fin, int64_t ldf, double *X, int64_t ldx, int64_t batch, unsigned int *ctr,
     unsigned int *fst, unsigned int *bst, double *ex, unsigned int *err)
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(K == 64 
 // tile, row group) with each tile's groups consecutive; otherwise as
 // k_onepass.
 template <int K, int W>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(K == 64 ? 2 : 3))) void k_group_onepass(
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_group_onepass(
     const GroupMat *__restrict__ mats, const GroupUnit *__restrict__ units, unsigned int *ctr,
     unsigned int *fst, unsigned int *bst, double *ex, unsigned int *err)
 {
