@@ -55,8 +55,8 @@ def kernel_source_hash(names) -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel: str, workload: str):
-    """HBM bytes moved by one step (all kernels of one solve) from the
+def traffic_for(kernel: str, workload: str, sources=None):
+    """HBM bytes moved by one step (all kernels of one step) from the
     committed rocprofv3 counter summary, if it was taken on the current kernel
     sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -64,8 +64,9 @@ def traffic_for(kernel: str, workload: str):
         return None
     with open(path) as fh:
         rec = json.load(fh).get(f"{kernel}@{workload}")
-    base = "".join(c for c in kernel if not c.isdigit())
-    if not rec or rec.get("source_hash") != kernel_source_hash(SCHEDULE_SOURCES[base]):
+    if sources is None:
+        sources = SCHEDULE_SOURCES["".join(c for c in kernel if not c.isdigit())]
+    if not rec or rec.get("source_hash") != kernel_source_hash(sources):
         return None
     return rec.get("bytes_per_step")
 
@@ -289,7 +290,10 @@ def run_group(args, torch):
                 config=dict(workload="group", matrices=len(mats), unknowns_per_step=unknowns,
                             systems=systems, graph_steps=steps, kernel_variant=variant),
                 roofline=dict(bound="hbm", achieved=gbs, peak=PEAK_HBM_GBS, unit="GB/s",
-                              frac=gbs / PEAK_HBM_GBS, traffic=None),
+                              frac=gbs / PEAK_HBM_GBS,
+                              traffic=traffic_for("group_onepass64", "group",
+                                                  ("onepass.hip", "lookback.h"))
+                              if variant == 6 else None),
                 persistent=res[0],
                 per_matrix=dict(res[1], ms_per_step=res[1]["ms"] / steps,
                                 speedup_of_persistent=res[1]["ms"] / res[0]["ms"]))
@@ -470,7 +474,10 @@ def run_periodic(args, torch):
                             form=names[form[0]], seg_rows=form[1]),
                 other_form=dict(form=names[other], ms_per_step=ms_other),
                 roofline=dict(bound="hbm", achieved=gbs, peak=PEAK_HBM_GBS, unit="GB/s",
-                              frac=gbs / PEAK_HBM_GBS, traffic=None),
+                              frac=gbs / PEAK_HBM_GBS,
+                              traffic=traffic_for("cyc_onepass64", "periodic",
+                                                  ("cyclic.hip", "lookback.h"))
+                              if form == (2, 64) else None),
                 parity=dict(probe_systems=len(probe), max_rel_err_vs_oracle=err,
                             oracle_steps=args.warmup + steps))
 

@@ -382,7 +382,7 @@ __device__ __forceinline__ void group_matrix(CSeg seg, int64_t s0, double &m0, d
     }
 }
 
-constexpr int kRB = 4;  // replay batch (register budget: v plus 4 kRB doubles)
+constexpr int kRB = 2;  // replay batch: 2 measured best (4 spills more at three waves per SIMD, 1 waits longer)
 
 // Group-level look-back (FWD) or look-ahead: the incoming carry of group g
 // of the tile whose first group unit is u0, given this group's aggregate
