@@ -382,19 +382,32 @@ __device__ __forceinline__ void group_matrix(CSeg seg, int64_t s0, double &m0, d
     }
 }
 
-constexpr int kRB = 2;  // replay batch: 2 measured best (4 spills more at three waves per SIMD, 1 waits longer)
+// Aggregates staged in LDS per round trip of the replay.
+constexpr int kStage = 16;
+constexpr int kCoherentLoad = 16;  // cache-policy bits of a direct load: sc1, as xload
+
+// One group's aggregate pair for the tile's 64 systems (1 KB: row ra then
+// row ra+1 of its exchange block) straight into LDS row dst, without
+// passing through registers: lane l moves values 2l, 2l+1.
+__device__ __forceinline__ void stage_load(const double *blk, double *dst)
+{
+    __builtin_amdgcn_global_load_lds(
+        (const __attribute__((address_space(1))) void *)(blk + 2 * (threadIdx.x & 63)),
+        (__attribute__((address_space(3))) void *)dst, 16, 0, kCoherentLoad);
+}
 
 // Group-level look-back (FWD) or look-ahead: the incoming carry of group g
 // of the tile whose first group unit is u0, given this group's aggregate
-// (c0, c1), which is posted unless the neighbour's inclusive value is
-// already there.  Statuses: 1 aggregate posted, 2 inclusive posted; the
-// first group (forward) and the last group (backward) post only inclusive
-// values.  Exchange rows: forward 0,1 aggregate, 2,3 inclusive; backward
-// 4,5 aggregate, 6,7 inclusive.
+// (c0, c1), which is posted first.  Statuses: 1 aggregate posted, 2
+// inclusive posted; the first group (forward) and the last group (backward)
+// post only inclusive values.  Exchange rows: forward 0,1 aggregate, 2,3
+// inclusive; backward 4,5 aggregate, 6,7 inclusive.  stage: LDS
+// [kStage][128].
 template <int W, bool FWD>
 __device__ __forceinline__ void group_carry(CSeg seg, int g, int ngroups, unsigned int u0,
                                             unsigned int *st_word, double *ex, unsigned int *err,
-                                            double c0, double c1, double &y0, double &y1)
+                                            double c0, double c1, double &y0, double &y1,
+                                            double (*stage)[128])
 {
     const int lane = threadIdx.x & 63;
     const int ra = FWD ? 0 : 4;  // aggregate rows
@@ -427,52 +440,41 @@ __device__ __forceinline__ void group_carry(CSeg seg, int g, int ngroups, unsign
         }
         __builtin_amdgcn_s_sleep(1);
     }
+    // replay the groups between pstar and g, innermost first: each round
+    // trip brings up to kStage aggregates into LDS at once (the replay is
+    // latency-bound, and registers hold the block), then links them in order
+    const int cnt = FWD ? g - 1 - pstar : pstar - g - 1;
+    auto group_at = [&](int i) { return FWD ? pstar + 1 + i : pstar - 1 - i; };
     const double *nb = ex + (int64_t)(u0 + pstar) * (kExRows * 64) + lane;
     y0 = xload(&nb[(ra + 2) * 64]);
     y1 = xload(&nb[(ra + 3) * 64]);
-    // replay the groups between pstar and g, innermost first, kRB at a time,
-    // the loads of the next kRB in flight while the current kRB are linked
-    const int cnt = FWD ? g - 1 - pstar : pstar - g - 1;
-    auto group_at = [&](int i) { return FWD ? pstar + 1 + i : pstar - 1 - i; };
-    double w0[kRB], w1[kRB], n0[kRB], n1[kRB];
+    for (int c = 0; c < cnt; c += kStage) {
+        const int m = cnt - c < kStage ? cnt - c : kStage;
 #pragma unroll
-    for (int i = 0; i < kRB; i++) {
-        const double *ag = ex + (int64_t)(u0 + group_at(i)) * (kExRows * 64) + lane;
-        w0[i] = i < cnt ? xload(&ag[ra * 64]) : 0.0;
-        w1[i] = i < cnt ? xload(&ag[(ra + 1) * 64]) : 0.0;
-    }
-    for (int i0 = 0; i0 < cnt; i0 += kRB) {
+        for (int i = 0; i < kStage; i++)
+            if (i < m) stage_load(ex + (int64_t)(u0 + group_at(c + i)) * (kExRows * 64) + ra * 64, stage[i]);
+        store_fence();  // the direct loads have landed in LDS
 #pragma unroll
-        for (int i = 0; i < kRB; i++) {
-            const int k = i0 + kRB + i;
-            const double *ag = ex + (int64_t)(u0 + group_at(k)) * (kExRows * 64) + lane;
-            n0[i] = k < cnt ? xload(&ag[ra * 64]) : 0.0;
-            n1[i] = k < cnt ? xload(&ag[(ra + 1) * 64]) : 0.0;
-        }
-#pragma unroll
-        for (int i = 0; i < kRB; i++) {
-            if (i0 + i < cnt) {
+        for (int i = 0; i < kStage; i++) {
+            if (i < m) {
                 double m0, m1, m2, m3;
-                group_matrix<W, FWD>(seg, (int64_t)group_at(i0 + i) * W, m0, m1, m2, m3);
-                link(w0[i], w1[i], m0, m1, m2, m3, y0, y1);
+                group_matrix<W, FWD>(seg, (int64_t)group_at(c + i) * W, m0, m1, m2, m3);
+                link(stage[i][lane], stage[i][64 + lane], m0, m1, m2, m3, y0, y1);
             }
         }
-#pragma unroll
-        for (int i = 0; i < kRB; i++) {
-            w0[i] = n0[i];
-            w1[i] = n1[i];
-        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);  // LDS reads before the next chunk's loads
+        __builtin_amdgcn_s_waitcnt(0xC07F);       // lgkmcnt(0)
     }
 }
 
 // Both sweeps of the block held by wave w of group g (rows r0 .. r0+K-1):
-// on exit v holds x.  sh: LDS [W + 1][2][64].
+// on exit v holds x.  sh: LDS [W + 1][2][64]; stage: LDS [kStage][128].
 template <int K, int W>
 __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd, CSeg seg,
                                              int64_t r0, int w, int g, int ngroups,
                                              unsigned int u0, unsigned int *fst,
                                              unsigned int *bst, double *ex, unsigned int *err,
-                                             double (*sh)[2][64])
+                                             double (*sh)[2][64], double (*stage)[128])
 {
     const int lane = threadIdx.x & 63;
     const int64_t s0 = (int64_t)g * W;
@@ -491,7 +493,7 @@ __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd,
             link(sh[i][0][lane], sh[i][1][lane], seg[s0 + i].tf[0], seg[s0 + i].tf[1],
                  seg[s0 + i].tf[2], seg[s0 + i].tf[3], E0, E1);
         double Y0 = 0.0, Y1 = 0.0;
-        if (g > 0) group_carry<W, true>(seg, g, ngroups, u0, fst, ex, err, E0, E1, Y0, Y1);
+        if (g > 0) group_carry<W, true>(seg, g, ngroups, u0, fst, ex, err, E0, E1, Y0, Y1, stage);
         if (g < ngroups - 1) {
             double m0, m1, m2, m3, o0 = Y0, o1 = Y1;
             group_matrix<W, true>(seg, s0, m0, m1, m2, m3);
@@ -528,7 +530,7 @@ __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd,
             link(sh[i][0][lane], sh[i][1][lane], seg[s0 + i].tb[0], seg[s0 + i].tb[1],
                  seg[s0 + i].tb[2], seg[s0 + i].tb[3], A0, A1);
         double Z0 = 0.0, Z1 = 0.0;
-        if (g < ngroups - 1) group_carry<W, false>(seg, g, ngroups, u0, bst, ex, err, A0, A1, Z0, Z1);
+        if (g < ngroups - 1) group_carry<W, false>(seg, g, ngroups, u0, bst, ex, err, A0, A1, Z0, Z1, stage);
         if (g > 0) {
             double m0, m1, m2, m3, o0 = Z0, o1 = Z1;
             group_matrix<W, false>(seg, s0, m0, m1, m2, m3);

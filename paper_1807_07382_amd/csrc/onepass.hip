@@ -34,6 +34,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     unsigned int *fst, unsigned int *bst, double *ex, unsigned int *err)
 {
     __shared__ double sh[W + 1][2][64];
+    __shared__ double stage[kStage][128];
     __shared__ unsigned int s_unit;
     const CFwd fwd = (CFwd)fwd_;
     const CBwd bwd = (CBwd)bwd_;
@@ -53,7 +54,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     double v[K];
     load_rows<K, TI>(v, Fin + jj + (L > 0 ? r0 * ldf : 0), ldf, act ? L : 0);
     group_phases<K, W>(v, fwd, bwd, seg, r0, w, g, ngroups, u - (unsigned int)g, fst, bst, ex, err,
-                       sh);
+                       sh, stage);
     if (!act || L == 0) return;
     double *base = X + jj + r0 * ldx;
     if (L == K) {
@@ -75,6 +76,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     unsigned int *fst, unsigned int *bst, double *ex, unsigned int *err)
 {
     __shared__ double sh[W + 1][2][64];
+    __shared__ double stage[kStage][128];
     __shared__ unsigned int s_unit;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
     const int lane = threadIdx.x & 63;
@@ -95,7 +97,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     double v[K];
     load_rows<K, double>(v, m.F + jj + (L > 0 ? r0 * m.ld : 0), m.ld, act ? L : 0);
     group_phases<K, W>(v, fwd, bwd, seg, r0, w, un.g, un.ngroups, (unsigned int)un.u0, fst, bst, ex,
-                       err, sh);
+                       err, sh, stage);
     if (!act || L == 0) return;
     double *base = m.F + jj + r0 * m.ld;
     if (L == K) {
