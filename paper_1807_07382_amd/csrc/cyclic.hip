@@ -261,8 +261,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     unsigned int *ctr, unsigned int *fst, unsigned int *bst, unsigned int *pst, unsigned int *tst,
     double *ex, double *pex, double *tex, unsigned int *err)
 {
-    __shared__ double sh[W + 1][2][64];
-    __shared__ double stage[kStage][128];
+    PENT_GROUP_LDS(W);
     __shared__ double sp[W][2][64];
     __shared__ unsigned int s_unit;
     const CFwd fwd = (CFwd)fwd_;
@@ -375,7 +374,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
 
     group_phases<K, W>(v, fwd, bwd, seg, r0, w, g, ngroups, u - (unsigned int)g, fst, bst, ex, err,
-                       sh, stage);
+                       sh, agg, mat);
 
     double *tx = tex + (int64_t)t * 128 + lane;
     double xt0, xt1;

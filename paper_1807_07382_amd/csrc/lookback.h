@@ -144,6 +144,18 @@ __device__ __forceinline__ void backward(double (&v)[K], CBwd bwd, int64_t r0, d
     }
 }
 
+// The same pointer, opaque to the optimiser: each sweep over a block loads
+// its coefficients afresh instead of keeping the first sweep's (64 rows of
+// them, and their products with the block) alive until the second, which
+// runs out of registers.
+template <typename P>
+__device__ __forceinline__ P fresh(P p)
+{
+    unsigned long long a = (unsigned long long)p;
+    asm volatile("" : "+s"(a));
+    return (P)a;
+}
+
 // One link of the interface chain, (y0, y1) <- w + T (y0, y1), T column-major.
 // Publishers and look-back use this one function with explicit fused
 // multiply-adds, so a carry has the same bits whichever path produced it.
@@ -365,10 +377,12 @@ __device__ __forceinline__ void mat_lmul(double t0, double t1, double t2, double
     m3 = n3;
 }
 
-// TG = Tf_{s0+W-1} ... Tf_{s0} (forward) or TBG = Tb_{s0} ... Tb_{s0+W-1}.
-template <int W, bool FWD>
-__device__ __forceinline__ void group_matrix(CSeg seg, int64_t s0, double &m0, double &m1,
-                                             double &m2, double &m3)
+// TG = Tf_{s0+W-1} ... Tf_{s0} (forward) or TBG = Tb_{s0} ... Tb_{s0+W-1},
+// t(i, k) = entry k of the matrix of segment s0 + i.  Every caller forms a
+// group's matrix through this one function, so it has the same bits
+// wherever its factors were read from.
+template <int W, bool FWD, typename Get>
+__device__ __forceinline__ void group_product(Get t, double &m0, double &m1, double &m2, double &m3)
 {
     m0 = 1.0;
     m1 = 0.0;
@@ -376,38 +390,58 @@ __device__ __forceinline__ void group_matrix(CSeg seg, int64_t s0, double &m0, d
     m3 = 1.0;
 #pragma unroll
     for (int i = 0; i < W; i++) {
-        const int64_t q = FWD ? s0 + i : s0 + W - 1 - i;
-        if (FWD) mat_lmul(seg[q].tf[0], seg[q].tf[1], seg[q].tf[2], seg[q].tf[3], m0, m1, m2, m3);
-        else mat_lmul(seg[q].tb[0], seg[q].tb[1], seg[q].tb[2], seg[q].tb[3], m0, m1, m2, m3);
+        const int q = FWD ? i : W - 1 - i;
+        mat_lmul(t(q, 0), t(q, 1), t(q, 2), t(q, 3), m0, m1, m2, m3);
     }
+}
+
+template <int W, bool FWD>
+__device__ __forceinline__ void group_matrix(CSeg seg, int64_t s0, double &m0, double &m1,
+                                             double &m2, double &m3)
+{
+    group_product<W, FWD>([&](int i, int k) { return FWD ? seg[s0 + i].tf[k] : seg[s0 + i].tb[k]; },
+                          m0, m1, m2, m3);
 }
 
 // Aggregates staged in LDS per round trip of the replay.
 constexpr int kStage = 16;
 constexpr int kCoherentLoad = 16;  // cache-policy bits of a direct load: sc1, as xload
 
+// LDS of a group of W waves (declared by each kernel, as arrays: the
+// direct loads need plain LDS addresses): sh [W + 1][2][64], the waves'
+// carries; agg [kStage][128] and mat [kStage][W][4], the replay's staging
+// area (aggregate pairs of the tile's 64 systems, and the W segment matrices
+// of each of those groups).
+#define PENT_GROUP_LDS(W)                          \
+    __shared__ double sh[(W) + 1][2][64];          \
+    __shared__ double agg[pent::lb::kStage][128];  \
+    __shared__ double mat[pent::lb::kStage][(W)][4]
+
 // One group's aggregate pair for the tile's 64 systems (1 KB: row ra then
 // row ra+1 of its exchange block) straight into LDS row dst, without
-// passing through registers: lane l moves values 2l, 2l+1.
+// passing through registers: lane l moves values 2l, 2l+1.  dst goes in as
+// its LDS offset, the low half of its generic address (a cast to the LDS
+// address space would add a null check the backend cannot encode here).
 __device__ __forceinline__ void stage_load(const double *blk, double *dst)
 {
     __builtin_amdgcn_global_load_lds(
         (const __attribute__((address_space(1))) void *)(blk + 2 * (threadIdx.x & 63)),
-        (__attribute__((address_space(3))) void *)dst, 16, 0, kCoherentLoad);
+        (__attribute__((address_space(3))) void *)(uint32_t)(uintptr_t)dst, 16, 0, kCoherentLoad);
 }
+
+
 
 // Group-level look-back (FWD) or look-ahead: the incoming carry of group g
 // of the tile whose first group unit is u0, given this group's aggregate
 // (c0, c1), which is posted first.  Statuses: 1 aggregate posted, 2
 // inclusive posted; the first group (forward) and the last group (backward)
 // post only inclusive values.  Exchange rows: forward 0,1 aggregate, 2,3
-// inclusive; backward 4,5 aggregate, 6,7 inclusive.  stage: LDS
-// [kStage][128].
+// inclusive; backward 4,5 aggregate, 6,7 inclusive.
 template <int W, bool FWD>
 __device__ __forceinline__ void group_carry(CSeg seg, int g, int ngroups, unsigned int u0,
                                             unsigned int *st_word, double *ex, unsigned int *err,
                                             double c0, double c1, double &y0, double &y1,
-                                            double (*stage)[128])
+                                            double (*agg)[128], double (*mat)[W][4])
 {
     const int lane = threadIdx.x & 63;
     const int ra = FWD ? 0 : 4;  // aggregate rows
@@ -440,9 +474,10 @@ __device__ __forceinline__ void group_carry(CSeg seg, int g, int ngroups, unsign
         }
         __builtin_amdgcn_s_sleep(1);
     }
-    // replay the groups between pstar and g, innermost first: each round
-    // trip brings up to kStage aggregates into LDS at once (the replay is
-    // latency-bound, and registers hold the block), then links them in order
+    // replay the groups between pstar and g, innermost first.  The replay
+    // is latency-bound and registers hold the block, so each round trip
+    // brings up to kStage groups' aggregates and segment matrices into LDS
+    // at once; they are then linked in order.
     const int cnt = FWD ? g - 1 - pstar : pstar - g - 1;
     auto group_at = [&](int i) { return FWD ? pstar + 1 + i : pstar - 1 - i; };
     const double *nb = ex + (int64_t)(u0 + pstar) * (kExRows * 64) + lane;
@@ -452,14 +487,25 @@ __device__ __forceinline__ void group_carry(CSeg seg, int g, int ngroups, unsign
         const int m = cnt - c < kStage ? cnt - c : kStage;
 #pragma unroll
         for (int i = 0; i < kStage; i++)
-            if (i < m) stage_load(ex + (int64_t)(u0 + group_at(c + i)) * (kExRows * 64) + ra * 64, stage[i]);
+            if (i < m) stage_load(ex + (int64_t)(u0 + group_at(c + i)) * (kExRows * 64) + ra * 64, agg[i]);
+        // segment matrices, half a matrix (16 bytes) per lane and load: slot
+        // e = (i * W + q) * 2 + h lands at LDS byte 16 e of mat
+#pragma unroll
+        for (int k = 0; k < (kStage * W * 2 + 63) / 64; k++) {
+            const int e = k * 64 + lane;
+            const int i = e / (2 * W) < m ? e / (2 * W) : 0;  // slots past the chunk reload its first group
+            const int64_t q = (int64_t)group_at(c + i) * W + (e / 2) % W;
+            __builtin_amdgcn_global_load_lds(
+                (const __attribute__((address_space(1))) void *)(FWD ? &seg[q].tf[2 * (e % 2)] : &seg[q].tb[2 * (e % 2)]),
+                (__attribute__((address_space(3))) void *)(uint32_t)(uintptr_t)&mat[(32 / W) * k][0][0], 16, 0, 0);
+        }
         store_fence();  // the direct loads have landed in LDS
 #pragma unroll
         for (int i = 0; i < kStage; i++) {
             if (i < m) {
                 double m0, m1, m2, m3;
-                group_matrix<W, FWD>(seg, (int64_t)group_at(c + i) * W, m0, m1, m2, m3);
-                link(stage[i][lane], stage[i][64 + lane], m0, m1, m2, m3, y0, y1);
+                group_product<W, FWD>([&](int q, int k) { return mat[i][q][k]; }, m0, m1, m2, m3);
+                link(agg[i][lane], agg[i][64 + lane], m0, m1, m2, m3, y0, y1);
             }
         }
         __atomic_signal_fence(__ATOMIC_SEQ_CST);  // LDS reads before the next chunk's loads
@@ -468,13 +514,14 @@ __device__ __forceinline__ void group_carry(CSeg seg, int g, int ngroups, unsign
 }
 
 // Both sweeps of the block held by wave w of group g (rows r0 .. r0+K-1):
-// on exit v holds x.  sh: LDS [W + 1][2][64]; stage: LDS [kStage][128].
+// on exit v holds x.
 template <int K, int W>
 __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd, CSeg seg,
                                              int64_t r0, int w, int g, int ngroups,
                                              unsigned int u0, unsigned int *fst,
                                              unsigned int *bst, double *ex, unsigned int *err,
-                                             double (*sh)[2][64], double (*stage)[128])
+                                             double (*sh)[2][64], double (*agg)[128],
+                                             double (*mat)[W][4])
 {
     const int lane = threadIdx.x & 63;
     const int64_t s0 = (int64_t)g * W;
@@ -493,7 +540,7 @@ __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd,
             link(sh[i][0][lane], sh[i][1][lane], seg[s0 + i].tf[0], seg[s0 + i].tf[1],
                  seg[s0 + i].tf[2], seg[s0 + i].tf[3], E0, E1);
         double Y0 = 0.0, Y1 = 0.0;
-        if (g > 0) group_carry<W, true>(seg, g, ngroups, u0, fst, ex, err, E0, E1, Y0, Y1, stage);
+        if (g > 0) group_carry<W, true>(seg, g, ngroups, u0, fst, ex, err, E0, E1, Y0, Y1, agg, mat);
         if (g < ngroups - 1) {
             double m0, m1, m2, m3, o0 = Y0, o1 = Y1;
             group_matrix<W, true>(seg, s0, m0, m1, m2, m3);
@@ -512,7 +559,7 @@ __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd,
         for (int i = 0; i < w; i++)
             link(sh[i][0][lane], sh[i][1][lane], seg[s0 + i].tf[0], seg[s0 + i].tf[1],
                  seg[s0 + i].tf[2], seg[s0 + i].tf[3], y0, y1);
-        forward<K, true>(v, fwd, r0, y0, y1);
+        forward<K, true>(v, fresh(fwd), r0, y0, y1);
     }
     __syncthreads();  // sh is reused below
     // backward: zero-start aggregates over the true g, then the group's carry
@@ -530,7 +577,7 @@ __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd,
             link(sh[i][0][lane], sh[i][1][lane], seg[s0 + i].tb[0], seg[s0 + i].tb[1],
                  seg[s0 + i].tb[2], seg[s0 + i].tb[3], A0, A1);
         double Z0 = 0.0, Z1 = 0.0;
-        if (g < ngroups - 1) group_carry<W, false>(seg, g, ngroups, u0, bst, ex, err, A0, A1, Z0, Z1, stage);
+        if (g < ngroups - 1) group_carry<W, false>(seg, g, ngroups, u0, bst, ex, err, A0, A1, Z0, Z1, agg, mat);
         if (g > 0) {
             double m0, m1, m2, m3, o0 = Z0, o1 = Z1;
             group_matrix<W, false>(seg, s0, m0, m1, m2, m3);
@@ -549,7 +596,7 @@ __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd,
         for (int i = W - 1; i > w; i--)
             link(sh[i][0][lane], sh[i][1][lane], seg[s0 + i].tb[0], seg[s0 + i].tb[1],
                  seg[s0 + i].tb[2], seg[s0 + i].tb[3], z0, z1);
-        backward<K, true>(v, bwd, r0, z0, z1);
+        backward<K, true>(v, fresh(bwd), r0, z0, z1);
     }
 }
 

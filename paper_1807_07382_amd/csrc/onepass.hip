@@ -33,8 +33,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     const TI *Fin, int64_t ldf, double *X, int64_t ldx, int64_t batch, unsigned int *ctr,
     unsigned int *fst, unsigned int *bst, double *ex, unsigned int *err)
 {
-    __shared__ double sh[W + 1][2][64];
-    __shared__ double stage[kStage][128];
+    PENT_GROUP_LDS(W);
     __shared__ unsigned int s_unit;
     const CFwd fwd = (CFwd)fwd_;
     const CBwd bwd = (CBwd)bwd_;
@@ -54,7 +53,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     double v[K];
     load_rows<K, TI>(v, Fin + jj + (L > 0 ? r0 * ldf : 0), ldf, act ? L : 0);
     group_phases<K, W>(v, fwd, bwd, seg, r0, w, g, ngroups, u - (unsigned int)g, fst, bst, ex, err,
-                       sh, stage);
+                       sh, agg, mat);
     if (!act || L == 0) return;
     double *base = X + jj + r0 * ldx;
     if (L == K) {
@@ -75,8 +74,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     const GroupMat *__restrict__ mats, const GroupUnit *__restrict__ units, unsigned int *ctr,
     unsigned int *fst, unsigned int *bst, double *ex, unsigned int *err)
 {
-    __shared__ double sh[W + 1][2][64];
-    __shared__ double stage[kStage][128];
+    PENT_GROUP_LDS(W);
     __shared__ unsigned int s_unit;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
     const int lane = threadIdx.x & 63;
@@ -97,7 +95,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     double v[K];
     load_rows<K, double>(v, m.F + jj + (L > 0 ? r0 * m.ld : 0), m.ld, act ? L : 0);
     group_phases<K, W>(v, fwd, bwd, seg, r0, w, un.g, un.ngroups, (unsigned int)un.u0, fst, bst, ex,
-                       err, sh, stage);
+                       err, sh, agg, mat);
     if (!act || L == 0) return;
     double *base = m.F + jj + r0 * m.ld;
     if (L == K) {
