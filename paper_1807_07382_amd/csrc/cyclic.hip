@@ -263,6 +263,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
 {
     PENT_GROUP_LDS(W);
     __shared__ double sp[W][2][64];
+    __shared__ double sft[2][64];  // f_m, f_{m+1} of the tile (tail block), kept out of registers
     __shared__ unsigned int s_unit;
     const CFwd fwd = (CFwd)fwd_;
     const CBwd bwd = (CBwd)bwd_;
@@ -286,7 +287,6 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     const bool last = g == ngroups - 1 && w == 0;  // forms x_tail for the tile
     const double *col = Fin + jj;
     double v[K];
-    double ft0 = 0.0, ft1 = 0.0;  // f_m, f_{m+1} (tail block only)
     if (CN) {
         // C rows r0 .. r0+K-1 into v (two rows past the block's last E row are
         // needed by the stencil: for a short last block they sit in v, else in
@@ -313,19 +313,28 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
             const double cm2 = act ? col[(m - 2) * ldf] : 0.0, cm1 = act ? col[(m - 1) * ldf] : 0.0;
             const double c_m = act ? col[m * ldf] : 0.0, c_m1 = act ? col[(m + 1) * ldf] : 0.0;
             const double c0 = act ? col[0] : 0.0, c1 = act ? col[ldf] : 0.0;
-            ft0 = cn_row(cd, cyc_ld(n), m, cm2, cm1, c_m, c_m1, c0);
-            ft1 = cn_row(cd, cyc_ld(n), m + 1, cm1, c_m, c_m1, c0, c1);
+            sft[0][lane] = cn_row(cd, cyc_ld(n), m, cm2, cm1, c_m, c_m1, c0);
+            sft[1][lane] = cn_row(cd, cyc_ld(n), m + 1, cm1, c_m, c_m1, c0, c1);
         }
         double p2 = h0, p1 = h1;  // C_{k-2}, C_{k-1}
+        CDbl cdf = cd;
+        // a copy of L the compiler cannot match with the later k < L tests,
+        // so it does not keep 64 row masks live from here to the stores
+        int Ls = L;
+        asm volatile("" : "+s"(Ls));
 #pragma unroll
         for (int k = 0; k < K; k++) {
+            if (k % kSchedRows == 0) {
+                __builtin_amdgcn_sched_barrier(0);
+                cdf = fresh(cdf);
+            }
             const double ck = v[k];
             const double n1 = k + 1 < K ? v[k + 1] : h2;
             const double n2 = k + 2 < K ? v[k + 2] : (k + 2 == K ? h2 : h3);
             // rows past the E rows read zero padding (no select: the
             // addresses stay affine in k, scalar loads with immediate offsets)
-            const double f = cn_row(cd, cyc_ld(n), r0 + k, p2, p1, ck, n1, n2);
-            v[k] = k < L ? f : 0.0;
+            const double f = cn_row(cdf, cyc_ld(n), r0 + k, p2, p1, ck, n1, n2);
+            v[k] = k < Ls ? f : 0.0;
             p2 = p1;
             p1 = ck;
         }
@@ -339,8 +348,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
             for (int k = 0; k < K; k++) v[k] = (act && k < L) ? base[k * ldf] : 0.0;
         }
         if (last) {
-            ft0 = act ? col[m * ldf] : 0.0;
-            ft1 = act ? col[(m + 1) * ldf] : 0.0;
+            sft[0][lane] = act ? col[m * ldf] : 0.0;
+            sft[1][lane] = act ? col[(m + 1) * ldf] : 0.0;
         }
     }
 
@@ -350,11 +359,16 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     // in order: h^T E^{-1} f^ with one fixed summation order.
     {
         double p0 = 0.0, p1 = 0.0;
+        CDbl Wf = Wt;
 #pragma unroll
         for (int k = 0; k < K; k++) {
+            if (k % kSchedRows == 0) {
+                __builtin_amdgcn_sched_barrier(0);
+                Wf = fresh(Wf);
+            }
             const int64_t i = r0 + k;
-            p0 = fma(Wt[2 * i], v[k], p0);
-            p1 = fma(Wt[2 * i + 1], v[k], p1);
+            p0 = fma(Wf[2 * i], v[k], p0);
+            p1 = fma(Wf[2 * i + 1], v[k], p1);
         }
         sp[w][0][lane] = p0;
         sp[w][1][lane] = p1;
@@ -410,7 +424,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
                 }
             }
         }
-        const double r0v = ft0 - d0, r1v = ft1 - d1;
+        const double r0v = sft[0][lane] - d0, r1v = sft[1][lane] - d1;
         xt0 = fma(aux->minv[1], r1v, aux->minv[0] * r0v);
         xt1 = fma(aux->minv[3], r1v, aux->minv[2] * r0v);
         xstore(&tx[0], xt0);
@@ -426,10 +440,15 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
         xt1 = xload(&tx[64]);
     }
     if (!act || L == 0) return;
+    CDbl Zf = Z;  // loaded here, not hoisted over the waits above
 #pragma unroll
     for (int k = 0; k < K; k++) {
+        if (k % kSchedRows == 0) {
+            __builtin_amdgcn_sched_barrier(0);
+            Zf = fresh(Zf);
+        }
         const int64_t i = r0 + k;
-        v[k] = fma(-Z[2 * i + 1], xt1, fma(-Z[2 * i], xt0, v[k]));
+        v[k] = fma(-Zf[2 * i + 1], xt1, fma(-Zf[2 * i], xt0, v[k]));
     }
     double *base = X + jj + r0 * ldx;
     if (L == K) {

@@ -116,11 +116,33 @@ __device__ __forceinline__ void load_rows(double (&v)[K], const TI *base, int64_
 }
 
 // Forward recurrence over the segment from (p2, p1); STORE writes g over v.
+// The same pointer, opaque to the optimiser: each sweep over a block loads
+// its coefficients afresh instead of keeping the first sweep's (64 rows of
+// them, and their products with the block) alive until the second, which
+// runs out of registers.
+template <typename P>
+__device__ __forceinline__ P fresh(P p)
+{
+    unsigned long long a = (unsigned long long)p;
+    asm volatile("" : "+s"(a));
+    return (P)a;
+}
+
+// The coefficient rows come in through scalar loads, kSchedRows rows at a
+// time: each batch reads through a fresh copy of the pointer behind a
+// scheduling barrier, so the compiler cannot hoist all of a sweep's loads to
+// its start (which runs out of scalar registers and spills into vector ones).
+constexpr int kSchedRows = 8;
+
 template <int K, bool STORE>
 __device__ __forceinline__ void forward(double (&v)[K], CFwd fwd, int64_t r0, double &p2, double &p1)
 {
 #pragma unroll
     for (int k = 0; k < K; k++) {
+        if (k % kSchedRows == 0) {
+            __builtin_amdgcn_sched_barrier(0);
+            fwd = fresh(fwd);
+        }
         const double ra = fwd[r0 + k].ra, ap = fwd[r0 + k].ap, bp = fwd[r0 + k].bp;
         const double g = fma(-bp, p1, fma(-ap, p2, ra * v[k]));
         if (STORE) v[k] = g;
@@ -136,24 +158,16 @@ __device__ __forceinline__ void backward(double (&v)[K], CBwd bwd, int64_t r0, d
 {
 #pragma unroll
     for (int k = K - 1; k >= 0; k--) {
+        if ((k + 1) % kSchedRows == 0) {
+            __builtin_amdgcn_sched_barrier(0);
+            bwd = fresh(bwd);
+        }
         const double gm = bwd[r0 + k].gm, dl = bwd[r0 + k].dl;
         const double x = fma(-gm, q1, fma(-dl, q2, v[k]));
         if (STORE) v[k] = x;
         q2 = q1;
         q1 = x;
     }
-}
-
-// The same pointer, opaque to the optimiser: each sweep over a block loads
-// its coefficients afresh instead of keeping the first sweep's (64 rows of
-// them, and their products with the block) alive until the second, which
-// runs out of registers.
-template <typename P>
-__device__ __forceinline__ P fresh(P p)
-{
-    unsigned long long a = (unsigned long long)p;
-    asm volatile("" : "+s"(a));
-    return (P)a;
 }
 
 // One link of the interface chain, (y0, y1) <- w + T (y0, y1), T column-major.
@@ -559,7 +573,7 @@ __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd,
         for (int i = 0; i < w; i++)
             link(sh[i][0][lane], sh[i][1][lane], seg[s0 + i].tf[0], seg[s0 + i].tf[1],
                  seg[s0 + i].tf[2], seg[s0 + i].tf[3], y0, y1);
-        forward<K, true>(v, fresh(fwd), r0, y0, y1);
+        forward<K, true>(v, fwd, r0, y0, y1);
     }
     __syncthreads();  // sh is reused below
     // backward: zero-start aggregates over the true g, then the group's carry
@@ -596,8 +610,13 @@ __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd,
         for (int i = W - 1; i > w; i--)
             link(sh[i][0][lane], sh[i][1][lane], seg[s0 + i].tb[0], seg[s0 + i].tb[1],
                  seg[s0 + i].tb[2], seg[s0 + i].tb[3], z0, z1);
-        backward<K, true>(v, fresh(bwd), r0, z0, z1);
+        backward<K, true>(v, bwd, r0, z0, z1);
     }
+    // x is complete here: keep the compiler from sinking the sweep into the
+    // block that stores x (past a caller's waits, with every coefficient
+    // held live across them)
+#pragma unroll
+    for (int k = 0; k < K; k++) asm volatile("" : "+v"(v[k]));
 }
 
 }  // namespace lb
