@@ -179,7 +179,7 @@ int pent_group_autotune(pent_group g, const int64_t *batch, int *variant_out, do
  * segment with 8/8/4/4 waves; 4, 5: one-wave tasks (item, segment) drawn
  * independently, 64/32 rows per segment, pass-2 tasks waiting (bounded) on
  * a per-item flag the last pass-1 task sets; 6: the single pass over all
- * matrices (pent_set_schedule kind 4 with 64-row segments, two per
+ * matrices (pent_set_schedule kind 4 with 64-row segments, four per
  * workgroup, units of every matrix in one launch; f read once, x written
  * once), which falls back to variant 0 when the deepest 64-system tile
  * would not fit on the device at once.  PENT_INVALID_VALUE for an unknown
@@ -313,10 +313,9 @@ int64_t pent_size(pent_handle h); /* n, or -1 for a bad handle */
 
 /* Force a schedule for this handle (tests and tuning):
  *   kind 0: automatic (default): the resident tile for small solves
- *           (n <= 4096 and n * batch <= 8M), the single pass (kind 4, 64
- *           rows) for 1024 <= n <= 2048, and for n <= 4096 with FP64 input
- *           in place, when a tile of its blocks fits on the device; else
- *           the partitioned form (kind 2);
+ *           (n <= 4096 and n * batch <= 8M), else the single pass (kind 4,
+ *           64 rows) for n >= 1024 when a tile of its blocks fits on the
+ *           device, else the partitioned form (kind 2);
  *   kind 1: one lane per system, both sweeps in one kernel (the paper's
  *           one-thread-per-system schedule, Sec. 2.4 last paragraph);
  *   kind 2: partitioned: seg_rows consecutive rows per lane, several lanes
@@ -334,9 +333,9 @@ int64_t pent_size(pent_handle h); /* n, or -1 for a bad handle */
  *           once.  Its waits are bounded; a wait that runs out (only possible
  *           when other work holds most of the device) leaves wrong values in
  *           that solve and is reported by pent_check.  The number of
- *           segments per workgroup (2 for 64 rows, 4 for 32) can be set to
- *           2, 4 or 8 with the environment variable PENT_ONEPASS_WAVES,
- *           read once per process (tuning).
+ *           segments per workgroup (4) can be set to 2, 4 or 8 with the
+ *           environment variable PENT_ONEPASS_WAVES, read once per process
+ *           (tuning).
  * Returns PENT_INVALID_VALUE for an unknown kind or seg_rows. */
 int pent_set_schedule(pent_handle h, int kind, int seg_rows);
 

@@ -197,9 +197,10 @@ bool tile_cache(pent_plan *p, int rows, const ScanRec **scan, const double **tre
 
 // Automatic schedule (chosen from measured sweeps over sizes on MI355X): the
 // resident tile for small solves, where launch count and latency dominate
-// (it is one kernel, the partitioned sweep three); the partitioned sweep for
-// large ones, where HBM streaming dominates and the tile's one-workgroup-per-
-// CU residency cannot overlap loads with compute.
+// (it is one kernel, the partitioned sweep three); the single pass for
+// large ones (f read once and x written once; measured ahead of the
+// partitioned sweep from n = 1024 to 8192, FP64 and FP32 input), and the
+// partitioned sweep where the single pass cannot run.
 void choose_schedule(const pent_plan *p, int64_t batch, int *kind, int *seg_rows)
 {
     if (p->sched_kind != 0) {
@@ -208,10 +209,7 @@ void choose_schedule(const pent_plan *p, int64_t batch, int *kind, int *seg_rows
     } else if (tile_rows_for(p->n) > 0 && p->n * batch <= (int64_t)8 << 20) {
         *kind = 3;
         *seg_rows = 0;
-    } else if (p->onepass_cap[1] > 0 && p->n >= 1024 && p->n <= 4096) {
-        // measured: the single pass wins while a tile is shallow (n <= 2048)
-        // and ties at n = 4096 (FP64 in place; io_schedule keeps FP32
-        // input there on kind 2); deeper tiles favour the partitioned form
+    } else if (p->onepass_cap[1] > 0 && p->n >= 1024) {
         *kind = 4;
         *seg_rows = 64;
     } else {
@@ -243,10 +241,6 @@ size_t summ_bytes(const pent_plan *p, int kind, int seg_rows, int64_t batch)
 void io_schedule(const pent_plan *p, int64_t batch, bool inplace64, int *kind, int *seg_rows)
 {
     choose_schedule(p, batch, kind, seg_rows);
-    if (p->sched_kind == 0 && *kind == 4 && p->n > 2048 && !inplace64) {
-        *kind = 2;
-        *seg_rows = 64;
-    }
     if (*kind == 4) {
         // every unit of one tile must fit on the device at once (with room
         // to spare for other work); else the three-kernel form

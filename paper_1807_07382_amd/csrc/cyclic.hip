@@ -469,7 +469,14 @@ __global__ void k_cyc_zero(unsigned int *p, int64_t count)
 
 }  // namespace
 
-static int cyc_waves(int seg_rows) { return onepass_waves(seg_rows); }
+// Waves per workgroup of the periodic single pass: 2 for 64-row segments
+// (measured ahead of 4 here: the kernel carries more state per wave than
+// the plain single pass), else 4; PENT_ONEPASS_WAVES overrides.
+static int cyc_waves(int seg_rows)
+{
+    const int o = onepass_waves_override();
+    return o ? o : seg_rows == 64 ? 2 : 4;
+}
 
 static int64_t cyc_groups(int64_t n, int seg_rows)
 {

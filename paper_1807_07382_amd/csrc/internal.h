@@ -253,6 +253,7 @@ hipError_t launch_ch2d_rhs(const double *C, double *R, int64_t ny, int64_t ninst
 // ---- single-pass partitioned sweep (onepass.hip) ----
 // Units = (64-system tile, segment); scratch = status words + exchange area.
 int onepass_waves(int seg_rows);                     // segments (waves) per workgroup
+int onepass_waves_override();
 int64_t onepass_groups(int64_t n, int seg_rows);     // workgroups per 64-system tile
 int64_t onepass_units(int64_t n, int seg_rows, int64_t batch);
 size_t onepass_scratch_bytes(int64_t n, int seg_rows, int64_t batch);

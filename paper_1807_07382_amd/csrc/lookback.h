@@ -514,13 +514,25 @@ __device__ __forceinline__ void group_carry(CSeg seg, int g, int ngroups, unsign
                 (__attribute__((address_space(3))) void *)(uint32_t)(uintptr_t)&mat[(32 / W) * k][0][0], 16, 0, 0);
         }
         store_fence();  // the direct loads have landed in LDS
+        // lane i < kStage forms group i's matrix (the same function as every
+        // other path, so the same bits) and leaves it in mat[i][0]
+        if (lane < kStage) {
+            double m0, m1, m2, m3;
+            group_product<W, FWD>([&](int q, int k) { return mat[lane][q][k]; }, m0, m1, m2, m3);
+            mat[lane][0][0] = m0;
+            mat[lane][0][1] = m1;
+            mat[lane][0][2] = m2;
+            mat[lane][0][3] = m3;
+        }
+        // the serial links, without branches (slots past the chunk are
+        // computed and dropped), so the reads can run ahead of the chain
 #pragma unroll
         for (int i = 0; i < kStage; i++) {
-            if (i < m) {
-                double m0, m1, m2, m3;
-                group_product<W, FWD>([&](int q, int k) { return mat[i][q][k]; }, m0, m1, m2, m3);
-                link(agg[i][lane], agg[i][64 + lane], m0, m1, m2, m3, y0, y1);
-            }
+            double n0 = y0, n1 = y1;
+            link(agg[i][lane], agg[i][64 + lane], mat[i][0][0], mat[i][0][1], mat[i][0][2], mat[i][0][3],
+                 n0, n1);
+            y0 = i < m ? n0 : y0;
+            y1 = i < m ? n1 : y1;
         }
         __atomic_signal_fence(__ATOMIC_SEQ_CST);  // LDS reads before the next chunk's loads
         __builtin_amdgcn_s_waitcnt(0xC07F);       // lgkmcnt(0)

@@ -24,9 +24,9 @@ using namespace lb;
 
 // Grouped form: a workgroup of W waves holds W consecutive segments of one
 // 64-system tile (K rows each); see lookback.h.  Three waves per SIMD (at
-// most 168 vector registers): for 64-row blocks this spills a few values of
-// the look-back path, and measured faster than two waves per SIMD without
-// spills (more blocks resident while carries are in flight).
+// most 168 vector registers): for 64-row blocks this spills a few values,
+// and measured faster than two waves per SIMD without spills (more blocks
+// resident while carries are in flight).
 template <int K, int W, typename TI>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_onepass(
     const FwdRec *fwd_, const BwdRec *bwd_, const SegRec *seg_, int64_t n, int ngroups,
@@ -128,15 +128,26 @@ const void *onepass_fn_kw(int K, int W, bool f32)
 
 }  // namespace
 
-// Waves (segments) per workgroup of the single-pass kernel.
-int onepass_waves(int seg_rows)
+// Waves per workgroup forced by PENT_ONEPASS_WAVES (2, 4 or 8; read once),
+// or 0.
+int onepass_waves_override()
 {
     static const int env = [] {
         const char *e = std::getenv("PENT_ONEPASS_WAVES");
         const int v = e ? std::atoi(e) : 0;
         return (v == 2 || v == 4 || v == 8) ? v : 0;
     }();
-    return env ? env : (seg_rows == 64 ? 2 : 4);
+    return env;
+}
+
+// Waves (segments) per workgroup of the single-pass kernel: 4 measured best
+// for both segment lengths (shorter interface chains than 2, and unlike 8
+// still three workgroups per CU).
+int onepass_waves(int seg_rows)
+{
+    (void)seg_rows;
+    const int o = onepass_waves_override();
+    return o ? o : 4;
 }
 
 int64_t onepass_groups(int64_t n, int seg_rows)
@@ -200,8 +211,8 @@ hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *se
     return e;
 }
 
-// ---- group variant 6: 64-row segments, two per workgroup
-constexpr int kGroupK = 64, kGroupW = 2;
+// ---- group variant 6: 64-row segments, four per workgroup
+constexpr int kGroupK = 64, kGroupW = 4;
 
 int group_onepass_rows() { return kGroupK * kGroupW; }
 
