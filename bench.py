@@ -177,8 +177,8 @@ def precision_compare(torch, sigma, reps=10, seed=4):
     """FP64 sweeps against FP32 right-hand-side streams (FP64 arithmetic,
     0 and 1 refinement steps) on the precision workload: N=8192, 131072
     right-hand sides uniform[-1, 1) rounded to FP32 (drawn on the device from
-    a seeded generator).  Reports solves/s, bytes per unknown moved by the
-    partitioned schedule, the largest device backward error and the largest
+    a seeded generator).  Reports solves/s, algorithmic bytes per unknown of
+    the schedule in use, the largest device backward error and the largest
     error against the oracle on sampled systems."""
     from paper_1807_07382_amd import inputs
     from paper_1807_07382_amd import pentbatch as pb
@@ -198,6 +198,12 @@ def precision_compare(torch, sigma, reps=10, seed=4):
     ref = oracle.solve(oracle.assemble_d4(n, sigma), f_sample)
     out = dict(workload="precision", n=n, systems=m, sigma=sigma)
     with pb.Plan.factor_d4(n, sigma) as plan:
+        # bytes per unknown of one solve: the single pass reads f once, the
+        # partitioned sweep twice; x is written once (FP64)
+        one = plan.schedule_for(m)[0] == 4
+        solve64, solve32 = (16, 12) if one else (24, 16)
+        refine1 = solve32 + 20 + solve64 + 24  # + residual (f, x in; r out) + correction solve + x += d
+        out["schedule"] = "single pass" if one else "partitioned"
         nbytes = pb.lib().pent_mixed_workspace_size(plan.handle, m, 1, 1)
         work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
 
@@ -209,7 +215,7 @@ def precision_compare(torch, sigma, reps=10, seed=4):
         ms64 = _timed(torch, stream, lambda: plan.solve_mixed(F64, X, work=work, stream=stream), reps)
         plan.solve_mixed(F64, X, eta=eta, work=work, stream=stream)
         torch.cuda.synchronize()
-        out["fp64"] = dict(ms=ms64, solves_per_s=m / (ms64 / 1e3), bytes_per_unknown=24,
+        out["fp64"] = dict(ms=ms64, solves_per_s=m / (ms64 / 1e3), bytes_per_unknown=solve64,
                            max_eta=float(eta.max()), max_rel_err_vs_oracle=rel_err(X))
         for k in (0, 1):
             ms = _timed(torch, stream,
@@ -218,7 +224,7 @@ def precision_compare(torch, sigma, reps=10, seed=4):
             plan.solve_mixed(F32, X, refine_steps=k, eta=eta, work=work, stream=stream)
             torch.cuda.synchronize()
             out[f"fp32_stream_refine{k}"] = dict(
-                ms=ms, solves_per_s=m / (ms / 1e3), bytes_per_unknown=16 if k == 0 else 84,
+                ms=ms, solves_per_s=m / (ms / 1e3), bytes_per_unknown=solve32 if k == 0 else refine1,
                 max_eta=float(eta.max()), max_rel_err_vs_oracle=rel_err(X),
                 speedup_vs_fp64=ms64 / ms)
     del F32, F64, X, work
