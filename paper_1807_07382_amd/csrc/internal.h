@@ -12,6 +12,17 @@
 
 namespace pent {
 
+// The same pointer, opaque to the optimiser (an empty asm that may have
+// changed it): loads through the copy are neither merged with loads through
+// the original nor moved above this point.
+template <typename P>
+__device__ __forceinline__ P fresh(P p)
+{
+    unsigned long long a = (unsigned long long)p;
+    asm volatile("" : "+s"(a));
+    return (P)a;
+}
+
 // Per-row constants of the forward sweep, prescaled by 1/alpha_i so the
 // recurrence g_i = (f_i - a_i g_{i-2} - beta_i g_{i-1}) / alpha_i (Sec. 2.4)
 // becomes g_i = ra*f_i - ap*g_{i-2} - bp*g_{i-1}, one fused multiply-add on

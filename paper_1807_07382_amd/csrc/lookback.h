@@ -115,25 +115,15 @@ __device__ __forceinline__ void load_rows(double (&v)[K], const TI *base, int64_
     }
 }
 
-// Forward recurrence over the segment from (p2, p1); STORE writes g over v.
-// The same pointer, opaque to the optimiser: each sweep over a block loads
-// its coefficients afresh instead of keeping the first sweep's (64 rows of
-// them, and their products with the block) alive until the second, which
-// runs out of registers.
-template <typename P>
-__device__ __forceinline__ P fresh(P p)
-{
-    unsigned long long a = (unsigned long long)p;
-    asm volatile("" : "+s"(a));
-    return (P)a;
-}
-
 // The coefficient rows come in through scalar loads, kSchedRows rows at a
-// time: each batch reads through a fresh copy of the pointer behind a
-// scheduling barrier, so the compiler cannot hoist all of a sweep's loads to
-// its start (which runs out of scalar registers and spills into vector ones).
+// time: each batch reads through a fresh copy of the pointer (fresh(),
+// internal.h) behind a scheduling barrier, so the compiler can neither keep
+// the zero-start sweep's coefficients (and their products with the block)
+// alive until the true sweep nor hoist all of a sweep's loads to its start;
+// both run out of scalar registers and spill into vector ones.
 constexpr int kSchedRows = 8;
 
+// Forward recurrence over the segment from (p2, p1); STORE writes g over v.
 template <int K, bool STORE>
 __device__ __forceinline__ void forward(double (&v)[K], CFwd fwd, int64_t r0, double &p2, double &p1)
 {

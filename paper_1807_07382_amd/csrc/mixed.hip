@@ -68,6 +68,38 @@ __device__ __forceinline__ void residual_block(const double *__restrict__ diag, 
     }
 }
 
+// Interior block (rows i0-2 .. i0+kRB+1 all inside the matrix): no bounds
+// tests, and the diagonal entries come 4 rows at a time through a fresh
+// pointer, so their scalar loads neither pile up at the start (out of scalar
+// registers) nor wait one row at a time.  r is formed over f (rv holds f on
+// entry).
+template <typename TI>
+__device__ __forceinline__ void residual_interior(const double *__restrict__ diag, int64_t n,
+                                                  const TI *f, int64_t ldf, const double *x,
+                                                  int64_t ldx, int64_t j, int64_t i0,
+                                                  double (&fv)[kRB])
+{
+    double xw[kRB + 4];
+    const double *xc = x + (i0 - 2) * ldx + j;
+    const TI *fc = f + i0 * ldf + j;
+#pragma unroll
+    for (int k = 0; k < kRB + 4; k++) xw[k] = __builtin_nontemporal_load(xc + k * ldx);
+#pragma unroll
+    for (int k = 0; k < kRB; k++) fv[k] = (double)__builtin_nontemporal_load(fc + k * ldf);
+    const double *dg = diag;
+#pragma unroll
+    for (int k = 0; k < kRB; k++) {
+        if (k % 4 == 0) {
+            __builtin_amdgcn_sched_barrier(0);
+            dg = fresh(dg);
+        }
+        const int64_t i = i0 + k;
+        const double cf[5] = {dg[i], dg[n + i], dg[2 * n + i], dg[3 * n + i], dg[4 * n + i]};
+        const double xv[5] = {xw[k], xw[k + 1], xw[k + 2], xw[k + 3], xw[k + 4]};
+        fv[k] = dot2_row(fv[k], cf, xv);
+    }
+}
+
 template <typename TI>
 __global__ __launch_bounds__(64) void k_residual(const double *__restrict__ diag, int64_t n,
                                                  const TI *__restrict__ f, int64_t ldf,
@@ -78,8 +110,16 @@ __global__ __launch_bounds__(64) void k_residual(const double *__restrict__ diag
     const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (j >= batch) return;
     const int64_t i0 = (int64_t)blockIdx.y * kRB;
-    double rv[kRB], fv[kRB], xw[kRB + 4];
-    residual_block<TI, true>(diag, n, f, ldf, x, ldx, j, i0, rv, fv, xw);
+    double rv[kRB];
+    if (i0 >= 2 && i0 + kRB + 2 <= n) {
+        residual_interior<TI>(diag, n, f, ldf, x, ldx, j, i0, rv);
+        double *rc = r + i0 * ldr + j;
+#pragma unroll
+        for (int k = 0; k < kRB; k++) __builtin_nontemporal_store(rv[k], rc + k * ldr);
+        return;
+    }
+    double xw[kRB + 4];
+    residual_block<TI, true>(diag, n, f, ldf, x, ldx, j, i0, rv, rv, xw);  // r over f
 #pragma unroll
     for (int k = 0; k < kRB; k++)
         if (i0 + k < n) r[(i0 + k) * ldr + j] = rv[k];
