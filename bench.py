@@ -202,7 +202,10 @@ def precision_compare(torch, sigma, reps=10, seed=4):
         # partitioned sweep twice; x is written once (FP64)
         one = plan.schedule_for(m)[0] == 4
         solve64, solve32 = (16, 12) if one else (24, 16)
-        refine1 = solve32 + 20 + solve64 + 24  # + residual (f, x in; r out) + correction solve + x += d
+        # one correction: fused on the single pass (f and x in, x read again
+        # and written: 4 + 8 + 8 + 8), else residual (f, x in; r out: 20) +
+        # correction solve + x += d (24)
+        refine1 = solve32 + (28 if one else 20 + solve64 + 24)
         out["schedule"] = "single pass" if one else "partitioned"
         nbytes = pb.lib().pent_mixed_workspace_size(plan.handle, m, 1, 1)
         work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")

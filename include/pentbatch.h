@@ -112,7 +112,10 @@ int pent_solve_strided(pent_handle h, double *F, int64_t batch, int64_t ld, void
  *   refine_steps (0..16): iterative-refinement corrections after the solve;
  *             each evaluates r = f - A x in compensated FP64 (every product
  *             and sum carried with its rounding error), solves A d = r and
- *             sets x += d.
+ *             sets x += d.  Where the solve runs as the single pass (kind 4)
+ *             each correction is one fused pass too (the residual formed as
+ *             the blocks load, x updated in place as they store); else three
+ *             kernels (residual, solve, update).
  *   eta_out : optional DEVICE array of batch doubles; receives each system's
  *             backward error ||f - A x||_inf / (||A||_inf ||x||_inf +
  *             ||f||_inf) with the residual evaluated compensated.

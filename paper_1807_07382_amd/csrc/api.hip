@@ -73,6 +73,7 @@ pent_plan *new_plan(int64_t n, int *st)
     p->scan_rows = 0;
     p->d_err = nullptr;
     p->onepass_cap[0] = p->onepass_cap[1] = 0;
+    p->fix_cap = 0;
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipMalloc(&p->d_diag, sizeof(double) * 5 * n);
     if (e == hipSuccess) e = hipMalloc(&p->d_fac, sizeof(double) * 4 * n);
@@ -900,6 +901,24 @@ int pent_solve_mixed(pent_handle h, const void *f, int f_dtype, int64_t ld_f, do
 
     int st = solve_io(h, f, f32, ld_f, x, ld_x, batch, summ, s);
     if (st != PENT_OK) return ret(st);
+    // Corrections: where the solve ran as a single pass, each correction is
+    // one fused pass too (residual, solve and update of x in one kernel),
+    // if a tile of it fits on the device and the scratch is large enough;
+    // else residual, solve, x += d.
+    if (refine_steps > 0 && kind == 4) {
+        if (h->fix_cap == 0) h->fix_cap = onepass_fix_capacity();
+        const SegRec *seg64 = nullptr;
+        if (h->fix_cap > 0 && onepass_fix_groups(h->n) <= h->fix_cap / 4 &&
+            onepass_fix_scratch_bytes(h->n, batch) <= b_summ + b_r &&
+            (seg64 = seg_cache(h, 64, &st)) != nullptr) {
+            for (int it = 0; it < refine_steps; it++) {
+                hipError_t e = launch_onepass_fix(h->d_fwd, h->d_bwd, seg64, h->d_diag, h->n, f, f32,
+                                                  ld_f, x, ld_x, batch, summ, h->d_err, s);
+                if (e != hipSuccess) return ret(hip_status(e));
+            }
+            refine_steps = 0;
+        }
+    }
     for (int it = 0; it < refine_steps; it++) {
         hipError_t e = launch_residual(h->d_diag, h->n, f, f32, ld_f, x, ld_x, r, batch, batch, s);
         if (e != hipSuccess) return ret(hip_status(e));

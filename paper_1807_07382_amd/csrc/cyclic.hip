@@ -212,7 +212,6 @@ __global__ void k_cn_rhs(const double *__restrict__ cd, int64_t n, const double 
 // way.
 using namespace lb;
 
-typedef __attribute__((address_space(4))) const double *CDbl;
 
 // f_i = 2 C_i - (A C)_i for row i, C rows i-2 .. i+2 in c0..c4; the
 // coefficients are wave-uniform (scalar loads), ld = cyc_ld(n).

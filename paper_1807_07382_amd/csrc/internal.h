@@ -12,6 +12,11 @@
 
 namespace pent {
 
+// Read-only kernel data through the constant address space: uniform
+// indexes then compile to scalar loads (a generic pointer gives per-lane
+// flat loads, each waited for).
+typedef __attribute__((address_space(4))) const double *CDbl;
+
 // The same pointer, opaque to the optimiser (an empty asm that may have
 // changed it): loads through the copy are neither merged with loads through
 // the original nor moved above this point.
@@ -21,6 +26,26 @@ __device__ __forceinline__ P fresh(P p)
     unsigned long long a = (unsigned long long)p;
     asm volatile("" : "+s"(a));
     return (P)a;
+}
+
+// r_i of one row: f_i - sum_k coef_k * x_k, every product and partial sum
+// carried with its rounding error (TwoProduct by fused multiply-add, TwoSum;
+// the "Dot2" scheme of Ogita, Rump and Oishi, SIAM J. Sci. Comput. 26, 2005).
+__device__ __forceinline__ double dot2_row(double f, const double (&cf)[5], const double (&xv)[5])
+{
+#pragma clang fp contract(off)
+    double s = f, c = 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; k++) {
+        const double p = -cf[k] * xv[k];
+        const double pe = __builtin_fma(-cf[k], xv[k], -p);
+        const double t = s + p;
+        const double z = t - s;
+        const double te = (s - (t - z)) + (p - z);
+        s = t;
+        c = c + (te + pe);
+    }
+    return s + c;
 }
 
 // Per-row constants of the forward sweep, prescaled by 1/alpha_i so the
@@ -137,6 +162,7 @@ struct pent_plan {
     int sched_seg;           // seg_rows for kinds 2 and 4
     unsigned int *d_err;     // 1 word: a single-pass wait ran out (cleared by pent_check)
     int onepass_cap[2];      // co-resident single-pass units (32, 64 rows), 0 = not yet queried
+    int fix_cap;             // co-resident units of the fused correction, 0 = not yet queried
     std::mutex mu;           // guards seg caches (lazy build)
     pent::SegCache seg[pent::kMaxSegCaches];
     pent::ScanRec *d_scan;   // resident-tile scan constants (64 records), lazily built
@@ -269,6 +295,13 @@ int64_t onepass_groups(int64_t n, int seg_rows);     // workgroups per 64-system
 int64_t onepass_units(int64_t n, int seg_rows, int64_t batch);
 size_t onepass_scratch_bytes(int64_t n, int seg_rows, int64_t batch);
 int onepass_capacity(int seg_rows);  // co-resident workgroups on the current device
+int onepass_fix_capacity();
+int64_t onepass_fix_groups(int64_t n);
+size_t onepass_fix_scratch_bytes(int64_t n, int64_t batch);
+hipError_t launch_onepass_fix(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg64,
+                              const double *diag, int64_t n, const void *F, bool f32, int64_t ldf,
+                              double *X, int64_t ldx, int64_t batch, void *scratch,
+                              unsigned int *err, hipStream_t s);
 hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg, int64_t n,
                           int seg_rows, const void *Fin, bool f32, int64_t ldf, double *X,
                           int64_t ldx, int64_t batch, void *scratch, unsigned int *err,

@@ -18,24 +18,6 @@ __device__ __forceinline__ double ld_in(const TI *p)
     return (double)*p;
 }
 
-// r_i of one row: f_i - sum_k coef_k * x_k, compensated.
-__device__ __forceinline__ double dot2_row(double f, const double (&cf)[5], const double (&xv)[5])
-{
-#pragma clang fp contract(off)
-    double s = f, c = 0.0;
-#pragma unroll
-    for (int k = 0; k < 5; k++) {
-        const double p = -cf[k] * xv[k];
-        const double pe = __builtin_fma(-cf[k], xv[k], -p);
-        const double t = s + p;
-        const double z = t - s;
-        const double te = (s - (t - z)) + (p - z);
-        s = t;
-        c = c + (te + pe);
-    }
-    return s + c;
-}
-
 // One lane = one system and kRB consecutive rows; x rows i0-2 .. i0+kRB+1 are
 // held in registers.  Diagonal entries are wave-uniform (scalar loads).
 template <typename TI, bool STORE_R>
@@ -86,7 +68,7 @@ __device__ __forceinline__ void residual_interior(const double *__restrict__ dia
     for (int k = 0; k < kRB + 4; k++) xw[k] = __builtin_nontemporal_load(xc + k * ldx);
 #pragma unroll
     for (int k = 0; k < kRB; k++) fv[k] = (double)__builtin_nontemporal_load(fc + k * ldf);
-    const double *dg = diag;
+    CDbl dg = (CDbl)diag;
 #pragma unroll
     for (int k = 0; k < kRB; k++) {
         if (k % 4 == 0) {

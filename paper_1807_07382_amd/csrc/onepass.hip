@@ -108,6 +108,128 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
 }
 
+// The double in lane l (a wave-uniform constant index) of v.
+__device__ __forceinline__ double lane_double(double v, int l)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// r = f - A x over a block held in v (x on entry, r on exit), compensated
+// (dot2_row); rows k >= L zero.  8 rows per batch, one batch ahead: f by
+// row, and the batch's 5 x 8 diagonal entries by one gathering load (lane
+// 8 d + q holds diagonal d of row q), read out lane by lane -- no scalar
+// load latency per row.
+template <int K, typename TI>
+__device__ __forceinline__ void fix_residual(double (&v)[K], const double *diag, int64_t n,
+                                             const TI *fc, int64_t ldf, int64_t r0, int L,
+                                             double hm2, double hm1, double hp0, double hp1)
+{
+    constexpr int B = 8;
+    const int lane = threadIdx.x & 63;
+    auto frow = [&](int k) { return fc[(k < L ? k : 0) * ldf]; };
+    auto coef = [&](int c) {  // rows past the matrix read its last row (dropped)
+        const int l = lane < 5 * B ? lane : 0;
+        const int64_t row = r0 + c * B + (l % B);
+        return diag[(l / B) * n + (row < n ? row : n - 1)];
+    };
+    double p2 = hm2, p1 = hm1;
+    TI fb[B], fn[B];
+    double cb = coef(0), cn = 0.0;
+#pragma unroll
+    for (int q = 0; q < B; q++) fb[q] = frow(q);
+#pragma unroll
+    for (int c = 0; c < K / B; c++) {
+        if (c + 1 < K / B) {
+            cn = coef(c + 1);
+#pragma unroll
+            for (int q = 0; q < B; q++) fn[q] = frow((c + 1) * B + q);
+        }
+#pragma unroll
+        for (int q = 0; q < B; q++) {
+            const int k = c * B + q;
+            const double xk = v[k];
+            const double x1 = k + 1 < K ? v[k + 1] : hp0;
+            const double x2 = k + 2 < K ? v[k + 2] : (k + 2 == K ? hp0 : hp1);
+            const double cf[5] = {lane_double(cb, q), lane_double(cb, B + q), lane_double(cb, 2 * B + q),
+                                  lane_double(cb, 3 * B + q), lane_double(cb, 4 * B + q)};
+            const double xv[5] = {p2, p1, xk, x1, x2};
+            const double r = dot2_row((double)fb[q], cf, xv);
+            v[k] = k < L ? r : 0.0;
+            p2 = p1;
+            p1 = xk;
+        }
+        cb = cn;
+#pragma unroll
+        for (int q = 0; q < B; q++) fb[q] = fn[q];
+    }
+}
+
+// One refinement correction in a single pass: each block forms the
+// residual r = f - A x of its rows from f and x (x with two halo rows each
+// side, zero outside the matrix; compensated, dot2_row), solves A d = r by
+// the same look-back sweeps, and adds d to x in place.  The update cannot
+// race the neighbours' halo reads: a block stores only after its tile's
+// carries have passed through both neighbours, which post them only after
+// their loads have completed.  x = A^{-1} f to one more correction.
+// 2 waves per SIMD: the halo and residual terms need more registers.
+template <int K, int W, typename TI>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(2))) void k_onepass_fix(
+    const FwdRec *fwd_, const BwdRec *bwd_, const SegRec *seg_, const double *__restrict__ diag,
+    int64_t n, int ngroups, const TI *F, int64_t ldf, double *X, int64_t ldx, int64_t batch,
+    unsigned int *ctr, unsigned int *fst, unsigned int *bst, double *ex, unsigned int *err)
+{
+    PENT_GROUP_LDS(W);
+    __shared__ unsigned int s_unit;
+    const CFwd fwd = (CFwd)fwd_;
+    const CBwd bwd = (CBwd)bwd_;
+    const CSeg seg = (CSeg)seg_;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+    const int lane = threadIdx.x & 63;
+    if (w == 0) s_unit = take_unit(ctr);  // every lane of wave 0 stores the same value
+    __syncthreads();
+    const unsigned int u = (unsigned int)__builtin_amdgcn_readfirstlane((int)s_unit);
+    const int t = (int)(u / (unsigned int)ngroups), g = (int)(u % (unsigned int)ngroups);
+    const int64_t j = (int64_t)t * 64 + lane;
+    const bool act = j < batch;
+    const int64_t jj = act ? j : 0;
+    const int64_t r0 = ((int64_t)g * W + w) * K;
+    const int64_t rem = n - r0;
+    const int L = (int)(rem < 0 ? 0 : rem < K ? rem : K);
+    double v[K];
+    // x of the block, and its halo rows (zero outside the matrix)
+    load_rows<K, double>(v, X + jj + (L > 0 ? r0 * ldx : 0), ldx, act ? L : 0);
+    // Every load below is unconditional, from a row clamped into the matrix
+    // (a load whose value is used under a per-lane condition gets sunk into
+    // that branch and waited for there).  No select is needed: a halo row
+    // outside the matrix meets a zero diagonal entry (the stored diagonals
+    // are zero there), rows past L are zeroed after the residual, and lanes
+    // past the batch store nothing.
+    auto xrow = [&](int64_t i) { return X[(i < 0 ? 0 : i >= n ? n - 1 : i) * ldx + jj]; };
+    const double hm2 = xrow(r0 - 2), hm1 = xrow(r0 - 1), hp0 = xrow(r0 + K), hp1 = xrow(r0 + K + 1);
+    // r over x, row by row, the two overwritten x values kept rolling; rows
+    // past the matrix (k >= L) give zero
+    fix_residual<K, TI>(v, diag, n, F + jj + (L > 0 ? r0 * ldf : 0), ldf, r0, L, hm2, hm1, hp0, hp1);
+    group_phases<K, W>(v, fwd, bwd, seg, r0, w, g, ngroups, u - (unsigned int)g, fst, bst, ex, err,
+                       sh, agg, mat);
+    if (!act || L == 0) return;
+    // x += d, 32 rows at a time: every load of a batch is issued before its
+    // stores (one round trip per batch; the compiler cannot tell the rows
+    // apart, so an interleaved read-modify-write would wait per row)
+    double *base = X + jj + r0 * ldx;
+#pragma unroll
+    for (int b = 0; b < K; b += 32) {
+        double xo[32];
+#pragma unroll
+        for (int q = 0; q < 32; q++) xo[q] = base[(b + q < L ? b + q : 0) * ldx];
+#pragma unroll
+        for (int q = 0; q < 32; q++)
+            if (b + q < L) base[(b + q) * ldx] = xo[q] + v[b + q];
+    }
+}
+
 __global__ void k_zero_words(unsigned int *p, int64_t count)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,6 +331,58 @@ hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *se
                     (void *)&fst, (void *)&bst, (void *)&ex, (void *)&err};
     e = hipLaunchKernel(fn, dim3((unsigned)units), dim3(64 * W), args, 0, s);
     return e;
+}
+
+// One fused refinement correction (k_onepass_fix): x += A^{-1}(f - A x).
+// diag: the 5n row-indexed diagonals; scratch and capacity as launch_onepass
+// (64-row segments, four per workgroup).
+constexpr int kFixK = 64, kFixW = 4;
+
+int onepass_fix_capacity()
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, (const void *)k_onepass_fix<kFixK, kFixW, double>, 64 * kFixW, 0) != hipSuccess)
+        return 0;
+    return cus * per_cu;
+}
+
+int64_t onepass_fix_groups(int64_t n) { return (n + kFixK * kFixW - 1) / (kFixK * kFixW); }
+
+size_t onepass_fix_scratch_bytes(int64_t n, int64_t batch)
+{
+    const int64_t units = (batch + 63) / 64 * onepass_fix_groups(n);
+    const size_t words = (size_t)(kTicketWords + 2 * units);
+    const size_t wbytes = (words * sizeof(unsigned int) + 255) / 256 * 256;
+    return wbytes + (size_t)units * kExRows * 64 * sizeof(double);
+}
+
+hipError_t launch_onepass_fix(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg64,
+                              const double *diag, int64_t n, const void *F, bool f32, int64_t ldf,
+                              double *X, int64_t ldx, int64_t batch, void *scratch,
+                              unsigned int *err, hipStream_t s)
+{
+    const int64_t ngroups = onepass_fix_groups(n);
+    const int64_t units = (batch + 63) / 64 * ngroups;
+    if (units > (int64_t)UINT32_MAX / 2 || kSegPad % kFixW != 0) return hipErrorInvalidValue;
+    const int64_t words = kTicketWords + 2 * units;
+    unsigned int *w = (unsigned int *)scratch;
+    unsigned int *ctr = w, *fst = w + kTicketWords, *bst = w + kTicketWords + units;
+    const size_t wbytes = ((size_t)words * sizeof(unsigned int) + 255) / 256 * 256;
+    double *ex = (double *)((char *)scratch + wbytes);
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, w, words);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const void *fn = f32 ? (const void *)k_onepass_fix<kFixK, kFixW, float>
+                         : (const void *)k_onepass_fix<kFixK, kFixW, double>;
+    int ng = (int)ngroups;
+    void *args[] = {(void *)&fwd, (void *)&bwd, (void *)&seg64, (void *)&diag, (void *)&n,
+                    (void *)&ng, (void *)&F, (void *)&ldf, (void *)&X, (void *)&ldx,
+                    (void *)&batch, (void *)&ctr, (void *)&fst, (void *)&bst, (void *)&ex,
+                    (void *)&err};
+    return hipLaunchKernel(fn, dim3((unsigned)units), dim3(64 * kFixW), args, 0, s);
 }
 
 // ---- group variant 6: 64-row segments, four per workgroup

@@ -64,6 +64,41 @@ def test_mixed_against_oracle(torch, sigma, refine):
     assert np.allclose(eta_dev, eta_ref, rtol=1e-6, atol=1e-30)
 
 
+@pytest.mark.parametrize("n,m", [(1, 3), (2, 70), (5, 64), (37, 5), (300, 130), (1000, 64),
+                                 (4133, 129)])
+@pytest.mark.parametrize("f_is_32", [True, False])
+def test_fused_correction_matches_three_kernel_path(torch, n, m, f_is_32):
+    """One and two corrections fused into single passes (schedule 4: the
+    residual formed as blocks load, x updated in place) against the same
+    corrections as residual, solve and update kernels (schedule 2): both
+    within the oracle's tolerance, and within twice it of each other; tiny n
+    puts every halo row outside the matrix."""
+    sigma = 1e3
+    print_case(test="fused_fix", n=n, m=m, f32=f_is_32)
+    f = f32_rhs(n, m, 7 * n + m)
+    if not f_is_32:
+        f = f.astype(np.float64) + np.random.Generator(np.random.PCG64(n)).uniform(-1e-9, 1e-9, (n, m))
+    dg = oracle.assemble_d4(n, sigma)
+    ref = oracle.solve(dg, f.astype(np.float64))
+    outs = []
+    with pb.Plan.factor_d4(n, sigma) as p:
+        for kind in (4, 2):
+            p.set_schedule(kind, 64)
+            for k in (1, 2):
+                F = torch.from_numpy(f).cuda()
+                X = torch.empty((n, m), dtype=torch.float64, device="cuda")
+                eta = torch.empty(m, dtype=torch.float64, device="cuda")
+                p.solve_mixed(F, X, refine_steps=k, eta=eta)
+                torch.cuda.synchronize()
+                p.check()
+                Xh = X.cpu().numpy()
+                assert np.all(colerr(Xh, ref) <= d4_tol(sigma)), (kind, k)
+                assert float(eta.max()) <= 1e-12
+                outs.append(Xh)
+    for a, b in zip(outs[:2], outs[2:]):
+        assert np.all(colerr(a, b) <= 2 * d4_tol(sigma))
+
+
 def test_backward_error_of_perturbed_solution(torch):
     """pent_backward_error sees a planted perturbation of x (the oracle's
     evaluator gives the same number)."""
