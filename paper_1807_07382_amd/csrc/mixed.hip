@@ -55,11 +55,13 @@ __device__ __forceinline__ void residual_block(const double *__restrict__ diag, 
 // pointer, so their scalar loads neither pile up at the start (out of scalar
 // registers) nor wait one row at a time.  r is formed over f (rv holds f on
 // entry).
-template <typename TI>
+// MAXES: also fold max |x| and max |f| over the block's rows into xm, fm.
+template <typename TI, bool MAXES = false>
 __device__ __forceinline__ void residual_interior(const double *__restrict__ diag, int64_t n,
                                                   const TI *f, int64_t ldf, const double *x,
                                                   int64_t ldx, int64_t j, int64_t i0,
-                                                  double (&fv)[kRB])
+                                                  double (&fv)[kRB], double *xm = nullptr,
+                                                  double *fm = nullptr)
 {
     double xw[kRB + 4];
     const double *xc = x + (i0 - 2) * ldx + j;
@@ -68,6 +70,13 @@ __device__ __forceinline__ void residual_interior(const double *__restrict__ dia
     for (int k = 0; k < kRB + 4; k++) xw[k] = __builtin_nontemporal_load(xc + k * ldx);
 #pragma unroll
     for (int k = 0; k < kRB; k++) fv[k] = (double)__builtin_nontemporal_load(fc + k * ldf);
+    if (MAXES) {
+#pragma unroll
+        for (int k = 0; k < kRB; k++) {
+            *xm = fmax(*xm, fabs(xw[k + 2]));
+            *fm = fmax(*fm, fabs(fv[k]));
+        }
+    }
     CDbl dg = (CDbl)diag;
 #pragma unroll
     for (int k = 0; k < kRB; k++) {
@@ -131,15 +140,26 @@ __global__ __launch_bounds__(64) void k_eta_partial(const double *__restrict__ d
 {
     const int64_t j = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (j >= batch) return;
-    const int64_t i0 = (int64_t)blockIdx.y * kRB;
-    double rv[kRB], fv[kRB], xw[kRB + 4];
-    residual_block<TI, false>(diag, n, f, ldf, x, ldx, j, i0, rv, fv, xw);
+    // row blocks blockIdx.y, blockIdx.y + gridDim.y, ...: maxima in
+    // registers, one set of atomics per lane
     double rm = 0.0, xm = 0.0, fm = 0.0;
+    const int64_t nblk = (n + kRB - 1) / kRB;
+    for (int64_t b = blockIdx.y; b < nblk; b += gridDim.y) {
+        const int64_t i0 = b * kRB;
+        double rv[kRB];
+        if (i0 >= 2 && i0 + kRB + 2 <= n) {
+            residual_interior<TI, true>(diag, n, f, ldf, x, ldx, j, i0, rv, &xm, &fm);
+        } else {
+            double fv[kRB], xw[kRB + 4];
+            residual_block<TI, false>(diag, n, f, ldf, x, ldx, j, i0, rv, fv, xw);
 #pragma unroll
-    for (int k = 0; k < kRB; k++) {
-        rm = fmax(rm, fabs(rv[k]));
-        xm = fmax(xm, fabs(xw[k + 2]));
-        fm = fmax(fm, fabs(fv[k]));
+            for (int k = 0; k < kRB; k++) {
+                xm = fmax(xm, fabs(xw[k + 2]));
+                fm = fmax(fm, fabs(fv[k]));
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kRB; k++) rm = fmax(rm, fabs(rv[k]));
     }
     atomicMax(acc + 3 * j + 0, (unsigned long long)__double_as_longlong(rm));
     atomicMax(acc + 3 * j + 1, (unsigned long long)__double_as_longlong(xm));
@@ -211,7 +231,8 @@ hipError_t launch_eta(const double *d_diag, const double *d_anorm, int64_t n, co
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, acc, cnt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const dim3 grid((unsigned)((batch + 63) / 64), (unsigned)((n + kRB - 1) / kRB));
+    const int64_t nblk = (n + kRB - 1) / kRB;
+    const dim3 grid((unsigned)((batch + 63) / 64), (unsigned)(nblk < 32 ? nblk : 32));
     if (f32)
         hipLaunchKernelGGL(k_eta_partial<float>, grid, dim3(64), 0, s, d_diag, n, (const float *)f,
                            ldf, x, ldx, batch, acc);
