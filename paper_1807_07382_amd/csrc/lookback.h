@@ -90,19 +90,6 @@ __device__ __forceinline__ void publish(unsigned int *p, unsigned int v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Status of a neighbour once it is non-zero (1 aggregate, 2 inclusive); on
-// timeout the error word is raised and 2 is returned so the wave finishes.
-__device__ __forceinline__ unsigned int wait_status(unsigned int *p, unsigned int *err)
-{
-    for (int i = 0; i < kSpin; i++) {
-        const unsigned int v = poll(p);
-        if (v != 0) return v;
-        __builtin_amdgcn_s_sleep(1);
-    }
-    atomicOr(err, 1u);
-    return 2;
-}
-
 template <int K, typename TI>
 __device__ __forceinline__ void load_rows(double (&v)[K], const TI *base, int64_t ld, int L)
 {
@@ -124,16 +111,19 @@ __device__ __forceinline__ void load_rows(double (&v)[K], const TI *base, int64_
 constexpr int kSchedRows = 8;
 
 // Forward recurrence over the segment from (p2, p1); STORE writes g over v.
-template <int K, bool STORE>
-__device__ __forceinline__ void forward(double (&v)[K], CFwd fwd, int64_t r0, double &p2, double &p1)
+// LREC: the block's records were staged in LDS (lf[k], row r0 + k) instead.
+template <int K, bool STORE, bool LREC = false>
+__device__ __forceinline__ void forward(double (&v)[K], CFwd fwd, int64_t r0, double &p2, double &p1,
+                                        const FwdRec *lf = nullptr)
 {
 #pragma unroll
     for (int k = 0; k < K; k++) {
-        if (k % kSchedRows == 0) {
+        if (!LREC && k % kSchedRows == 0) {
             __builtin_amdgcn_sched_barrier(0);
             fwd = fresh(fwd);
         }
-        const double ra = fwd[r0 + k].ra, ap = fwd[r0 + k].ap, bp = fwd[r0 + k].bp;
+        const double ra = LREC ? lf[k].ra : fwd[r0 + k].ra, ap = LREC ? lf[k].ap : fwd[r0 + k].ap,
+                     bp = LREC ? lf[k].bp : fwd[r0 + k].bp;
         const double g = fma(-bp, p1, fma(-ap, p2, ra * v[k]));
         if (STORE) v[k] = g;
         p2 = p1;
@@ -143,16 +133,17 @@ __device__ __forceinline__ void forward(double (&v)[K], CFwd fwd, int64_t r0, do
 
 // Back substitution over the segment from (q1, q2) = (x_{r0+K}, x_{r0+K+1});
 // on exit (q1, q2) = (x_{r0}, x_{r0+1}).  STORE writes x over v.
-template <int K, bool STORE>
-__device__ __forceinline__ void backward(double (&v)[K], CBwd bwd, int64_t r0, double &q1, double &q2)
+template <int K, bool STORE, bool LREC = false>
+__device__ __forceinline__ void backward(double (&v)[K], CBwd bwd, int64_t r0, double &q1, double &q2,
+                                         const BwdRec *lb = nullptr)
 {
 #pragma unroll
     for (int k = K - 1; k >= 0; k--) {
-        if ((k + 1) % kSchedRows == 0) {
+        if (!LREC && (k + 1) % kSchedRows == 0) {
             __builtin_amdgcn_sched_barrier(0);
             bwd = fresh(bwd);
         }
-        const double gm = bwd[r0 + k].gm, dl = bwd[r0 + k].dl;
+        const double gm = LREC ? lb[k].gm : bwd[r0 + k].gm, dl = LREC ? lb[k].dl : bwd[r0 + k].dl;
         const double x = fma(-gm, q1, fma(-dl, q2, v[k]));
         if (STORE) v[k] = x;
         q2 = q1;
@@ -184,179 +175,6 @@ __device__ __forceinline__ unsigned int lane_status(unsigned int *word, int64_t 
     const unsigned int v = in ? __hip_atomic_load(word + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
     return v;
-}
-
-// Forward phase of block s (rows r0.., unit u, tile's first unit u0): on
-// exit v holds g and the block's inclusive value is posted.
-// Look-back by windows of 64 segments (lane l looks at segment hi - l): the
-// nearest segment with an inclusive value is found once every segment in
-// between has posted its aggregate; the chain is then replayed from that
-// inclusive value through the aggregates, innermost first -- bit for bit the
-// serial recurrence y_{p+1} = e_p + Tf_p y_p whatever the timing.  Segment 0
-// only ever posts inclusive values, so every look-back ends.
-template <int K>
-__device__ __forceinline__ void forward_phase(double (&v)[K], CFwd fwd, CSeg seg, int64_t r0, int s,
-                                              int nseg, unsigned int u, unsigned int *fst,
-                                              double *ex, unsigned int *err)
-{
-    const int lane = threadIdx.x;
-    const unsigned int u0 = u - (unsigned int)s;
-    double *me = ex + (int64_t)u * (kExRows * 64) + lane;
-    double y0 = 0.0, y1 = 0.0;
-    if (s > 0) {
-        double e0 = 0.0, e1 = 0.0;
-        forward<K, false>(v, fwd, r0, e0, e1);
-        int hi = s - 1, pstar = s - 1;
-        bool posted = false;
-        for (int spin = 0;; spin++) {
-            const int p = hi - lane;
-            const unsigned int st = lane_status(fst, (int64_t)u0 + p, p >= 0);
-            const unsigned long long incl = __ballot(st == 2);
-            const unsigned long long none = __ballot(p >= 0 && st == 0);
-            if (incl != 0) {
-                const int l = __builtin_ctzll(incl);
-                if ((none & ((1ull << l) - 1)) == 0) {
-                    pstar = hi - l;
-                    break;
-                }
-            } else if (none == 0 && hi >= 64) {
-                hi -= 64;  // a full window of aggregates: look further back
-                continue;
-            }
-            if (!posted) {
-                xstore(&me[0], e0);
-                xstore(&me[64], e1);
-                publish(&fst[u], 1u);
-                posted = true;
-            }
-            if (spin >= kSpin) {
-                atomicOr(err, 1u);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        if (pstar < s - 1 && !posted) {
-            xstore(&me[0], e0);
-            xstore(&me[64], e1);
-            publish(&fst[u], 1u);
-        }
-        const double *nb = ex + (int64_t)(u0 + pstar) * (kExRows * 64) + lane;
-        y0 = xload(&nb[2 * 64]);
-        y1 = xload(&nb[3 * 64]);
-        for (int q0 = pstar + 1; q0 < s; q0 += 8) {
-            double w0[8], w1[8];
-#pragma unroll
-            for (int i = 0; i < 8; i++) {
-                const double *ag = ex + (int64_t)(u0 + q0 + i) * (kExRows * 64) + lane;
-                w0[i] = q0 + i < s ? xload(&ag[0]) : 0.0;
-                w1[i] = q0 + i < s ? xload(&ag[64]) : 0.0;
-            }
-#pragma unroll
-            for (int i = 0; i < 8; i++) {
-                const int q = q0 + i;
-                if (q < s) link(w0[i], w1[i], seg[q].tf[0], seg[q].tf[1], seg[q].tf[2], seg[q].tf[3], y0, y1);
-            }
-        }
-        if (s < nseg - 1) {
-            double o0 = y0, o1 = y1;
-            link(e0, e1, seg[s].tf[0], seg[s].tf[1], seg[s].tf[2], seg[s].tf[3], o0, o1);
-            xstore(&me[2 * 64], o0);
-            xstore(&me[3 * 64], o1);
-            publish(&fst[u], 2u);
-        }
-        forward<K, true>(v, fwd, r0, y0, y1);
-    } else {
-        forward<K, true>(v, fwd, r0, y0, y1);  // zero start is the true start
-        if (nseg > 1) {
-            xstore(&me[2 * 64], y0);
-            xstore(&me[3 * 64], y1);
-            publish(&fst[u], 2u);
-        }
-    }
-}
-
-// Backward phase, the mirror image (look-ahead by windows, lane l at segment
-// lo + l; the last segment only ever posts inclusive values): on exit v
-// holds x.
-template <int K>
-__device__ __forceinline__ void backward_phase(double (&v)[K], CBwd bwd, CSeg seg, int64_t r0, int s,
-                                               int nseg, unsigned int u, unsigned int *bst,
-                                               double *ex, unsigned int *err)
-{
-    const int lane = threadIdx.x;
-    const unsigned int u0 = u - (unsigned int)s;
-    double *me = ex + (int64_t)u * (kExRows * 64) + lane;
-    double z0 = 0.0, z1 = 0.0;
-    if (s < nseg - 1) {
-        double a0 = 0.0, a1 = 0.0;
-        backward<K, false>(v, bwd, r0, a0, a1);
-        int lo = s + 1, pstar = s + 1;
-        bool posted = false;
-        for (int spin = 0;; spin++) {
-            const int p = lo + lane;
-            const unsigned int st = lane_status(bst, (int64_t)u0 + p, p < nseg);
-            const unsigned long long incl = __ballot(st == 2);
-            const unsigned long long none = __ballot(p < nseg && st == 0);
-            if (incl != 0) {
-                const int l = __builtin_ctzll(incl);
-                if ((none & ((1ull << l) - 1)) == 0) {
-                    pstar = lo + l;
-                    break;
-                }
-            } else if (none == 0 && lo + 64 < nseg) {
-                lo += 64;
-                continue;
-            }
-            if (!posted) {
-                xstore(&me[4 * 64], a0);
-                xstore(&me[5 * 64], a1);
-                publish(&bst[u], 1u);
-                posted = true;
-            }
-            if (spin >= kSpin) {
-                atomicOr(err, 1u);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-        if (pstar > s + 1 && !posted) {
-            xstore(&me[4 * 64], a0);
-            xstore(&me[5 * 64], a1);
-            publish(&bst[u], 1u);
-        }
-        const double *nb = ex + (int64_t)(u0 + pstar) * (kExRows * 64) + lane;
-        z0 = xload(&nb[6 * 64]);
-        z1 = xload(&nb[7 * 64]);
-        for (int q0 = pstar - 1; q0 > s; q0 -= 8) {
-            double w0[8], w1[8];
-#pragma unroll
-            for (int i = 0; i < 8; i++) {
-                const double *ag = ex + (int64_t)(u0 + q0 - i) * (kExRows * 64) + lane;
-                w0[i] = q0 - i > s ? xload(&ag[4 * 64]) : 0.0;
-                w1[i] = q0 - i > s ? xload(&ag[5 * 64]) : 0.0;
-            }
-#pragma unroll
-            for (int i = 0; i < 8; i++) {
-                const int q = q0 - i;
-                if (q > s) link(w0[i], w1[i], seg[q].tb[0], seg[q].tb[1], seg[q].tb[2], seg[q].tb[3], z0, z1);
-            }
-        }
-        if (s > 0) {
-            double o0 = z0, o1 = z1;
-            link(a0, a1, seg[s].tb[0], seg[s].tb[1], seg[s].tb[2], seg[s].tb[3], o0, o1);
-            xstore(&me[6 * 64], o0);
-            xstore(&me[7 * 64], o1);
-            publish(&bst[u], 2u);
-        }
-        backward<K, true>(v, bwd, r0, z0, z1);
-    } else {
-        backward<K, true>(v, bwd, r0, z0, z1);  // nothing below the last segment
-        if (s > 0) {
-            xstore(&me[6 * 64], z0);
-            xstore(&me[7 * 64], z1);
-            publish(&bst[u], 2u);
-        }
-    }
 }
 
 // ---- grouped form: a workgroup of W waves takes W consecutive segments
@@ -529,22 +347,66 @@ __device__ __forceinline__ void group_carry(CSeg seg, int g, int ngroups, unsign
     }
 }
 
+// The records of rows r0 .. r0+K-1 into LDS (lf: K FwdRec, lb: K BwdRec) by
+// direct loads, to be issued before the block's own loads; rec_wait()
+// before the first sweep then waits for them alone while the block is still
+// arriving.  The sweeps then read their coefficients as LDS broadcasts
+// instead of a scalar-load round trip per batch of rows.  K is 32 or 64.
+template <int K>
+__device__ __forceinline__ void stage_records(const FwdRec *fwd, const BwdRec *bwd, int64_t r0,
+                                              FwdRec *lf, BwdRec *lb)
+{
+    const int lane = threadIdx.x & 63;
+    const char *fs = (const char *)(fwd + r0) + 16 * lane;
+    const uint32_t fl = (uint32_t)(uintptr_t)lf;
+#pragma unroll
+    for (int c = 0; c < K * (int)sizeof(FwdRec) / 1024; c++)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(fs + 1024 * c),
+                                         (__attribute__((address_space(3))) void *)(fl + 1024u * c), 16, 0, 0);
+    const char *bs = (const char *)(bwd + r0) + 16 * lane;
+    if (K * (int)sizeof(BwdRec) >= 1024 || lane < K * (int)sizeof(BwdRec) / 16)
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)bs,
+                                         (__attribute__((address_space(3))) void *)(uint32_t)(uintptr_t)lb,
+                                         16, 0, 0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// s_waitcnt immediate for vmcnt(vm) alone (vm <= 63; gfx9 encoding: low
+// four bits at 3:0, high two at 15:14, expcnt and lgkmcnt at their maxima).
+constexpr int vmcnt_imm(int vm) { return (vm & 15) | ((vm >> 4) << 14) | 0x0F70; }
+
+// Waits for the staged records.  full (wave-uniform): a full block's K loads
+// were issued after them, so at most K - 1 outstanding operations means
+// they have landed while most of the block is still arriving; else wait for
+// everything.
+template <int K>
+__device__ __forceinline__ void rec_wait(bool full)
+{
+    static_assert(K >= 1 && K <= 64, "vmcnt holds at most 63");
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    if (full) __builtin_amdgcn_s_waitcnt(vmcnt_imm(K - 1));
+    else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Both sweeps of the block held by wave w of group g (rows r0 .. r0+K-1):
 // on exit v holds x.
-template <int K, int W>
+template <int K, int W, bool LREC = false>
 __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd, CSeg seg,
                                              int64_t r0, int w, int g, int ngroups,
                                              unsigned int u0, unsigned int *fst,
                                              unsigned int *bst, double *ex, unsigned int *err,
                                              double (*sh)[2][64], double (*agg)[128],
-                                             double (*mat)[W][4])
+                                             double (*mat)[W][4], const FwdRec *lf = nullptr,
+                                             const BwdRec *lb = nullptr)
 {
     const int lane = threadIdx.x & 63;
     const int64_t s0 = (int64_t)g * W;
     // forward: zero-start aggregates of the waves, then the group's carry
     {
         double e0 = 0.0, e1 = 0.0;
-        forward<K, false>(v, fwd, r0, e0, e1);
+        forward<K, false, LREC>(v, fwd, r0, e0, e1, lf);
         sh[w][0][lane] = e0;
         sh[w][1][lane] = e1;
     }
@@ -575,13 +437,13 @@ __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd,
         for (int i = 0; i < w; i++)
             link(sh[i][0][lane], sh[i][1][lane], seg[s0 + i].tf[0], seg[s0 + i].tf[1],
                  seg[s0 + i].tf[2], seg[s0 + i].tf[3], y0, y1);
-        forward<K, true>(v, fwd, r0, y0, y1);
+        forward<K, true, LREC>(v, fwd, r0, y0, y1, lf);
     }
     __syncthreads();  // sh is reused below
     // backward: zero-start aggregates over the true g, then the group's carry
     {
         double a0 = 0.0, a1 = 0.0;
-        backward<K, false>(v, bwd, r0, a0, a1);
+        backward<K, false, LREC>(v, bwd, r0, a0, a1, lb);
         sh[w][0][lane] = a0;
         sh[w][1][lane] = a1;
     }
@@ -612,7 +474,7 @@ __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd,
         for (int i = W - 1; i > w; i--)
             link(sh[i][0][lane], sh[i][1][lane], seg[s0 + i].tb[0], seg[s0 + i].tb[1],
                  seg[s0 + i].tb[2], seg[s0 + i].tb[3], z0, z1);
-        backward<K, true>(v, bwd, r0, z0, z1);
+        backward<K, true, LREC>(v, bwd, r0, z0, z1, lb);
     }
     // x is complete here: keep the compiler from sinking the sweep into the
     // block that stores x (past a caller's waits, with every coefficient

@@ -93,9 +93,16 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     const int64_t rem = m.n - r0;
     const int L = (int)(rem < 0 ? 0 : rem < K ? rem : K);
     double v[K];
+    // the sweeps' records from LDS (measured faster here, where the many
+    // small matrices' record tables compete for the scalar cache; slower
+    // in k_onepass, where the extra registers cost spills)
+    __shared__ FwdRec lf[W][K];
+    __shared__ BwdRec lb[W][K];
+    stage_records<K>(m.fwd, m.bwd, r0, lf[w], lb[w]);
     load_rows<K, double>(v, m.F + jj + (L > 0 ? r0 * m.ld : 0), m.ld, act ? L : 0);
-    group_phases<K, W>(v, fwd, bwd, seg, r0, w, un.g, un.ngroups, (unsigned int)un.u0, fst, bst, ex,
-                       err, sh, agg, mat);
+    rec_wait<K>(L == K);
+    group_phases<K, W, true>(v, fwd, bwd, seg, r0, w, un.g, un.ngroups, (unsigned int)un.u0, fst, bst,
+                             ex, err, sh, agg, mat, lf[w], lb[w]);
     if (!act || L == 0) return;
     double *base = m.F + jj + r0 * m.ld;
     if (L == K) {
