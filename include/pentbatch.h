@@ -92,7 +92,11 @@ int pent_solve(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream
  * doubles at F + j*ld (element (i, j) at F[j*ld + i]), ld >= n.  This is the
  * layout of the second direction of an alternating-direction (ADI-style)
  * sweep over a 2-D grid (Sec. 4 names ADI as the route to 2-D and 3-D
- * problems). */
+ * problems).  Runs as the single pass (blocks of 64 systems transposed
+ * through LDS so that memory moves in contiguous runs of each system),
+ * allocating stream-ordered scratch on `stream`, when one tile of it fits on
+ * the device; else one lane per system.  A single-pass wait that runs out is
+ * reported by pent_check, as for pent_solve. */
 int pent_solve_strided(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream);
 
 /* ------------------------------------------------- precision extension --

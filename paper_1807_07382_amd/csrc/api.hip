@@ -74,6 +74,7 @@ pent_plan *new_plan(int64_t n, int *st)
     p->d_err = nullptr;
     p->onepass_cap[0] = p->onepass_cap[1] = 0;
     p->fix_cap = 0;
+    p->t_cap = 0;
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipMalloc(&p->d_diag, sizeof(double) * 5 * n);
     if (e == hipSuccess) e = hipMalloc(&p->d_fac, sizeof(double) * 4 * n);
@@ -1417,8 +1418,23 @@ int pent_solve_strided(pent_handle h, double *F, int64_t batch, int64_t ld, void
     if (!valid(h) || batch < 0 || ld < h->n) return ret(PENT_INVALID_VALUE);
     if (batch == 0) return ret(PENT_OK);
     if (!F) return ret(PENT_INVALID_VALUE);
-    return ret(hip_status(
-        launch_strided_sweep(h->d_fwd, h->d_bwd, h->n, F, batch, ld, (hipStream_t)stream)));
+    hipStream_t s = (hipStream_t)stream;
+    // the single pass (blocks transposed through LDS) where a tile of it
+    // fits on the device; else one lane per system
+    if (h->t_cap == 0) h->t_cap = onepass_t_capacity();
+    if (h->t_cap > 0 && onepass_t_groups(h->n) <= h->t_cap / 4 &&
+        (batch + 63) / 64 * onepass_t_groups(h->n) <= (int64_t)UINT32_MAX / 2) {
+        int st;
+        const SegRec *seg64 = seg_cache(h, 64, &st);
+        if (!seg64) return ret(st);
+        void *scratch = nullptr;
+        hipError_t e = hipMallocAsync(&scratch, onepass_t_scratch_bytes(h->n, batch), s);
+        if (e != hipSuccess) return ret(hip_status(e));
+        e = launch_onepass_t(h->d_fwd, h->d_bwd, seg64, h->n, F, batch, ld, scratch, h->d_err, s);
+        const hipError_t e2 = hipFreeAsync(scratch, s);
+        return ret(hip_status(e != hipSuccess ? e : e2));
+    }
+    return ret(hip_status(launch_strided_sweep(h->d_fwd, h->d_bwd, h->n, F, batch, ld, s)));
 }
 
 int pent_get_factors(pent_handle h, double *alpha, double *beta, double *gamma, double *delta)

@@ -163,6 +163,7 @@ struct pent_plan {
     unsigned int *d_err;     // 1 word: a single-pass wait ran out (cleared by pent_check)
     int onepass_cap[2];      // co-resident single-pass units (32, 64 rows), 0 = not yet queried
     int fix_cap;             // co-resident units of the fused correction, 0 = not yet queried
+    int t_cap;               // ... of the system-major single pass
     std::mutex mu;           // guards seg caches (lazy build)
     pent::SegCache seg[pent::kMaxSegCaches];
     pent::ScanRec *d_scan;   // resident-tile scan constants (64 records), lazily built
@@ -295,6 +296,12 @@ int64_t onepass_groups(int64_t n, int seg_rows);     // workgroups per 64-system
 int64_t onepass_units(int64_t n, int seg_rows, int64_t batch);
 size_t onepass_scratch_bytes(int64_t n, int seg_rows, int64_t batch);
 int onepass_capacity(int seg_rows);  // co-resident workgroups on the current device
+int onepass_t_capacity();
+int64_t onepass_t_groups(int64_t n);
+size_t onepass_t_scratch_bytes(int64_t n, int64_t batch);
+hipError_t launch_onepass_t(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg64, int64_t n,
+                            double *F, int64_t batch, int64_t ld, void *scratch, unsigned int *err,
+                            hipStream_t s);
 int onepass_fix_capacity();
 int64_t onepass_fix_groups(int64_t n);
 size_t onepass_fix_scratch_bytes(int64_t n, int64_t batch);

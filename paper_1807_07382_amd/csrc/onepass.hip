@@ -174,6 +174,103 @@ __device__ __forceinline__ void fix_residual(double (&v)[K], const double *diag,
     }
 }
 
+// System-major right-hand sides (element (row i, system s) at F[s*ld + i],
+// e.g. the x sweeps of a grid stored x-fastest), in place: the single pass
+// of k_onepass with each wave's K x 64 block transposed through LDS, 8 rows
+// at a time.  Loads and stores move whole 64-byte runs of each system (8
+// lanes per system, 8 systems per instruction); in registers every lane
+// holds one system's rows, as in k_onepass.  Positions past the matrix or
+// the batch load from clamped addresses (no load under a per-lane test) and
+// are zeroed or never stored.
+template <int K, int W>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_onepass_t(
+    const FwdRec *fwd_, const BwdRec *bwd_, const SegRec *seg_, int64_t n, int ngroups, double *F,
+    int64_t ld, int64_t batch, unsigned int *ctr, unsigned int *fst, unsigned int *bst, double *ex,
+    unsigned int *err)
+{
+    PENT_GROUP_LDS(W);
+    __shared__ double tb[W][8][66];  // row stride 66: the transposing writes hit distinct banks
+    __shared__ unsigned int s_unit;
+    const CFwd fwd = (CFwd)fwd_;
+    const CBwd bwd = (CBwd)bwd_;
+    const CSeg seg = (CSeg)seg_;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+    const int lane = threadIdx.x & 63;
+    if (w == 0) s_unit = take_unit(ctr);  // every lane of wave 0 stores the same value
+    __syncthreads();
+    const unsigned int u = (unsigned int)__builtin_amdgcn_readfirstlane((int)s_unit);
+    const int t = (int)(u / (unsigned int)ngroups), g = (int)(u % (unsigned int)ngroups);
+    const int64_t s0 = (int64_t)t * 64;
+    const int64_t r0 = ((int64_t)g * W + w) * K;
+    const int64_t rem = n - r0;
+    const int L = (int)(rem < 0 ? 0 : rem < K ? rem : K);
+    const int sub = lane & 7, grp = lane >> 3;  // row in a chunk, system in an 8-system slice
+    double v[K];
+    // raw loads: v[8c + q] = (row r0 + 8c + sub, system s0 + 8q + grp).  A
+    // full block (all rows in the matrix, all 64 systems in the batch) is one
+    // per-lane base plus uniform offsets; a ragged one clamps each address
+    const bool full = L == K && s0 + 64 <= batch;
+    if (full) {
+        const double *pl = F + (s0 + grp) * ld + r0 + sub;
+#pragma unroll
+        for (int c = 0; c < K / 8; c++)
+#pragma unroll
+            for (int q = 0; q < 8; q++) v[8 * c + q] = __builtin_nontemporal_load(pl + 8 * q * ld + 8 * c);
+    } else {
+#pragma unroll
+        for (int c = 0; c < K / 8; c++) {
+            int64_t row = r0 + 8 * c + sub;
+            row = row < n ? row : n - 1;
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                int64_t sys = s0 + 8 * q + grp;
+                sys = sys < batch ? sys : batch - 1;
+                v[8 * c + q] = F[sys * ld + row];
+            }
+            __builtin_amdgcn_sched_barrier(0);  // 8 loads at a time: few addresses live
+        }
+    }
+    // transpose in place: afterwards v[k] = (row r0 + k, system s0 + lane)
+    double(*tw)[66] = tb[w];
+#pragma unroll
+    for (int c = 0; c < K / 8; c++) {
+#pragma unroll
+        for (int q = 0; q < 8; q++) tw[sub][8 * q + grp] = v[8 * c + q];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const double x = tw[k][lane];
+            v[8 * c + k] = 8 * c + k < L ? x : 0.0;  // rows past the matrix
+        }
+    }
+    group_phases<K, W>(v, fwd, bwd, seg, r0, w, g, ngroups, u - (unsigned int)g, fst, bst, ex, err,
+                       sh, agg, mat);
+    // transpose back and store the positions inside the matrix and batch
+#pragma unroll
+    for (int c = 0; c < K / 8; c++) {
+#pragma unroll
+        for (int k = 0; k < 8; k++) tw[k][lane] = v[8 * c + k];
+#pragma unroll
+        for (int q = 0; q < 8; q++) v[8 * c + q] = tw[sub][8 * q + grp];
+    }
+    if (full) {
+        double *pl = F + (s0 + grp) * ld + r0 + sub;
+#pragma unroll
+        for (int c = 0; c < K / 8; c++)
+#pragma unroll
+            for (int q = 0; q < 8; q++) __builtin_nontemporal_store(v[8 * c + q], pl + 8 * q * ld + 8 * c);
+    } else {
+#pragma unroll
+        for (int c = 0; c < K / 8; c++) {
+            const int64_t row = r0 + 8 * c + sub;
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                const int64_t sys = s0 + 8 * q + grp;
+                if (row < n && sys < batch) F[sys * ld + row] = v[8 * c + q];
+            }
+        }
+    }
+}
+
 // One refinement correction in a single pass: each block forms the
 // residual r = f - A x of its rows from f and x (x with two halo rows each
 // side, zero outside the matrix; compensated, dot2_row), solves A d = r by
@@ -338,6 +435,54 @@ hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *se
                     (void *)&fst, (void *)&bst, (void *)&ex, (void *)&err};
     e = hipLaunchKernel(fn, dim3((unsigned)units), dim3(64 * W), args, 0, s);
     return e;
+}
+
+// The single pass over system-major right-hand sides (k_onepass_t): 64-row
+// segments, four per workgroup; scratch as launch_onepass.
+constexpr int kTK = 64, kTW = 4;
+
+int onepass_t_capacity()
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_onepass_t<kTK, kTW>,
+                                                     64 * kTW, 0) != hipSuccess)
+        return 0;
+    return cus * per_cu;
+}
+
+int64_t onepass_t_groups(int64_t n) { return (n + kTK * kTW - 1) / (kTK * kTW); }
+
+size_t onepass_t_scratch_bytes(int64_t n, int64_t batch)
+{
+    const int64_t units = (batch + 63) / 64 * onepass_t_groups(n);
+    const size_t words = (size_t)(kTicketWords + 2 * units);
+    const size_t wbytes = (words * sizeof(unsigned int) + 255) / 256 * 256;
+    return wbytes + (size_t)units * kExRows * 64 * sizeof(double);
+}
+
+hipError_t launch_onepass_t(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg64, int64_t n,
+                            double *F, int64_t batch, int64_t ld, void *scratch, unsigned int *err,
+                            hipStream_t s)
+{
+    const int64_t ngroups = onepass_t_groups(n);
+    const int64_t units = (batch + 63) / 64 * ngroups;
+    if (units > (int64_t)UINT32_MAX / 2 || kSegPad % kTW != 0) return hipErrorInvalidValue;
+    const int64_t words = kTicketWords + 2 * units;
+    unsigned int *w = (unsigned int *)scratch;
+    unsigned int *ctr = w, *fst = w + kTicketWords, *bst = w + kTicketWords + units;
+    const size_t wbytes = ((size_t)words * sizeof(unsigned int) + 255) / 256 * 256;
+    double *ex = (double *)((char *)scratch + wbytes);
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, w, words);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int ng = (int)ngroups;
+    void *args[] = {(void *)&fwd, (void *)&bwd, (void *)&seg64, (void *)&n, (void *)&ng, (void *)&F,
+                    (void *)&ld, (void *)&batch, (void *)&ctr, (void *)&fst, (void *)&bst,
+                    (void *)&ex, (void *)&err};
+    return hipLaunchKernel((const void *)k_onepass_t<kTK, kTW>, dim3((unsigned)units), dim3(64 * kTW),
+                           args, 0, s);
 }
 
 // One fused refinement correction (k_onepass_fix): x += A^{-1}(f - A x).

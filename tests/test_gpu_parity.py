@@ -193,6 +193,31 @@ def test_strided_layout(torch, n, m, pad):
     assert np.array_equal(out[:, n:], buf[:, n:])
 
 
+@pytest.mark.parametrize("n,m,pad", [(4133, 1000, 5), (1024, 4100, 0)])
+def test_strided_single_pass_deterministic(torch, n, m, pad):
+    """System-major solves by the single pass (blocks transposed through
+    LDS): the same bits on every run, oracle parity, padding untouched, no
+    timed-out wait; a ragged last tile of systems and a ragged last group of
+    rows."""
+    print_case(test="strided_det", n=n, m=m, pad=pad)
+    sigma = 50.0
+    buf = np.random.Generator(np.random.PCG64(n * m)).uniform(-1, 1, (m, n + pad))
+    ref = oracle.solve(oracle.assemble_d4(n, sigma), np.ascontiguousarray(buf[:, :n].T))
+    outs = []
+    with pb.Plan.factor_d4(n, sigma) as p:
+        for _ in range(3):
+            T = torch.from_numpy(buf.copy()).cuda()
+            p.solve_strided_(T[:, :n])
+            outs.append(T)
+        torch.cuda.synchronize()
+        p.check()
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    out = outs[0].cpu().numpy()
+    assert np.all(colerr(np.ascontiguousarray(out[:, :n].T), ref) <= d4_tol(sigma))
+    assert np.array_equal(out[:, n:], buf[:, n:])
+
+
 def test_hyperdiff_full_size_sampled(torch):
     """The hyperdiffusion workload at full size (N=4096, 65536 systems, the
     automatic schedule the benchmark uses), two backward-Euler steps; 256
