@@ -343,7 +343,9 @@ def run_cahn2d(args, torch):
                 scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
                 config=dict(workload="cahn2d", grid=[n, n], instances=ninst, sigma=sigma),
                 roofline=dict(bound="hbm", achieved=gbs, peak=PEAK_HBM_GBS, unit="GB/s",
-                              frac=gbs / PEAK_HBM_GBS, traffic=None),
+                              frac=gbs / PEAK_HBM_GBS,
+                              traffic=traffic_for("ch2d", "cahn2d",
+                                                  ("onepass.hip", "lookback.h", "ch2d.hip"))),
                 parity=dict(instance=0, max_rel_err_vs_oracle=err))
 
 

@@ -32,6 +32,33 @@ __global__ __launch_bounds__(256) void k_ch2d_rhs(const double *__restrict__ C,
     const int64_t sy = ninst * nx;
     const double dtk = dt[k];
     int64_t i = y0 * sy + k * nx + x;
+    if (y0 + kRows < ny && y0 >= 1) {
+        // interior run: every load of the run issued up front (one round
+        // trip instead of one per row)
+        // (x-neighbours load unconditionally, from the column itself at the
+        // grid's edge, and are masked by a multiply: a load under a per-lane
+        // test would be waited for inside its branch)
+        double cc[kRows + 2], ce[kRows], cw[kRows];
+        const double *col = C + i - sy;
+        const int de = x + 1 < nx ? 1 : 0, dw = x >= 1 ? 1 : 0;
+        const double me = de, mw = dw;
+#pragma unroll
+        for (int r = 0; r < kRows + 2; r++) cc[r] = col[r * sy];
+#pragma unroll
+        for (int r = 0; r < kRows; r++) {
+            ce[r] = col[(r + 1) * sy + de];
+            cw[r] = col[(r + 1) * sy - dw];
+        }
+#pragma unroll
+        for (int r = 0; r < kRows; r++) {
+            const double w = wterm(cc[r + 1]);
+            const double we = me * wterm(ce[r]);
+            const double ww = mw * wterm(cw[r]);
+            const double lap = (we + ww + wterm(cc[r + 2]) + wterm(cc[r]) - 4.0 * w) * inv_h2;
+            R[i + r * sy] = cc[r + 1] + dtk * lap;
+        }
+        return;
+    }
     double ws = y0 >= 1 ? wterm(C[i - sy]) : 0.0;
     double c = C[i];
     double w = wterm(c);
