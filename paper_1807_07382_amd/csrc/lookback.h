@@ -1,6 +1,7 @@
 // lookback.h -- device pieces of the single-pass sweeps (onepass.hip,
-// cyclic.hip): ticketing, status words, the interface link, and the forward
-// and backward phases of one (tile, segment) block held in registers.
+// cyclic.hip): ticketing, status words, the interface link, the sweeps of a
+// block held in registers, and the phases of a workgroup of W such blocks
+// (group_phases) with its look-back and look-ahead (group_carry).
 //
 // By linearity (Sec. 2.4's recurrences are affine in the carried pair), a
 // segment's outgoing forward state is

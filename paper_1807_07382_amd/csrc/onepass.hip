@@ -2,10 +2,13 @@
 // written once.
 //
 // The rows are cut into segments of K rows and the systems into tiles of 64
-// (one lane per system); a unit = (tile, segment) is one one-wave workgroup
-// that holds its K x 64 block of the right-hand side in registers from load
-// to store, and exchanges the two-value segment interface states with the
-// other units of its tile by decoupled look-back (lookback.h).
+// (one lane per system); a unit = (tile, group of W consecutive segments) is
+// one workgroup of W waves, each holding one K x 64 block of the right-hand
+// side in registers from load to store; the waves pass their segment
+// interface states through LDS, and the groups of a tile exchange theirs by
+// decoupled look-back (lookback.h).  Variants: many matrices in one launch
+// (k_group_onepass), system-major storage (k_onepass_t), and one fused
+// refinement correction (k_onepass_fix).
 //
 // Units take tickets from a counter in ticket order (tile-major), so a unit
 // only ever waits on units that already hold a slot (look-back) or on later
