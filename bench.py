@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -48,10 +49,14 @@ SCHEDULE_SOURCES = {"lane": ("sweep.hip",), "partitioned": ("sweep.hip",), "tile
 
 
 def kernel_source_hash(names) -> str:
+    """Hash of the kernel sources with comments and blank lines removed, so
+    that a comment-only edit keeps the counters taken on the same code."""
     h = hashlib.sha256()
     for name in (names,) if isinstance(names, str) else names:
-        with open(os.path.join(ROOT, "paper_1807_07382_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1807_07382_amd", "csrc", name)) as fh:
+            text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+        lines = (re.sub(r"//.*", "", line).rstrip() for line in text.splitlines())
+        h.update("\n".join(line for line in lines if line).encode())
     return h.hexdigest()[:16]
 
 
