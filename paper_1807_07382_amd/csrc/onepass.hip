@@ -180,9 +180,9 @@ __device__ __forceinline__ void fix_residual(double (&v)[K], const double *diag,
 // System-major right-hand sides (element (row i, system s) at F[s*ld + i],
 // e.g. the x sweeps of a grid stored x-fastest), in place: the single pass
 // of k_onepass with each wave's K x 64 block transposed through LDS, 8 rows
-// at a time.  Loads and stores move whole 64-byte runs of each system (8
-// lanes per system, 8 systems per instruction); in registers every lane
-// holds one system's rows, as in k_onepass.  Positions past the matrix or
+// at a time.  Loads and stores move whole 128-byte runs of each system (8
+// lanes per system, 16 bytes each, 8 systems per instruction); in registers
+// every lane holds one system's rows, as in k_onepass.  Positions past the matrix or
 // the batch load from clamped addresses (no load under a per-lane test) and
 // are zeroed or never stored.
 template <int K, int W>
@@ -209,68 +209,92 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     const int L = (int)(rem < 0 ? 0 : rem < K ? rem : K);
     const int sub = lane & 7, grp = lane >> 3;  // row in a chunk, system in an 8-system slice
     double v[K];
-    // raw loads: v[8c + q] = (row r0 + 8c + sub, system s0 + 8q + grp).  A
-    // full block (all rows in the matrix, all 64 systems in the batch) is one
-    // per-lane base plus uniform offsets; a ragged one clamps each address
-    const bool full = L == K && s0 + 64 <= batch;
+    // raw loads in 16-row chunks c: lane (sub, grp) takes rows 2 sub, 2 sub + 1
+    // of the chunk of system s0 + 8q + grp (8 lanes cover a whole 128-byte
+    // run of each system), into v[16c + 2q + e], e the row parity.  A full
+    // block (all rows in the matrix, all 64 systems in the batch) is one
+    // per-lane base plus uniform offsets; a ragged one clamps each address.
+    // (the 16-byte accesses also need every system's run 16-byte aligned:
+    // an even ld and F itself aligned)
+    typedef double Dbl2 __attribute__((ext_vector_type(2)));
+    const bool full = L == K && s0 + 64 <= batch && ld % 2 == 0 && (uintptr_t)F % 16 == 0;
     if (full) {
-        const double *pl = F + (s0 + grp) * ld + r0 + sub;
+        const double *pl = F + (s0 + grp) * ld + r0 + 2 * sub;
 #pragma unroll
-        for (int c = 0; c < K / 8; c++)
+        for (int c = 0; c < K / 16; c++)
 #pragma unroll
-            for (int q = 0; q < 8; q++) v[8 * c + q] = __builtin_nontemporal_load(pl + 8 * q * ld + 8 * c);
+            for (int q = 0; q < 8; q++) {
+                const Dbl2 p = __builtin_nontemporal_load((const Dbl2 *)(pl + 8 * q * ld + 16 * c));
+                v[16 * c + 2 * q] = p.x;
+                v[16 * c + 2 * q + 1] = p.y;
+            }
     } else {
 #pragma unroll
-        for (int c = 0; c < K / 8; c++) {
-            int64_t row = r0 + 8 * c + sub;
-            row = row < n ? row : n - 1;
+        for (int c = 0; c < K / 16; c++) {
 #pragma unroll
             for (int q = 0; q < 8; q++) {
                 int64_t sys = s0 + 8 * q + grp;
                 sys = sys < batch ? sys : batch - 1;
-                v[8 * c + q] = F[sys * ld + row];
+#pragma unroll
+                for (int e = 0; e < 2; e++) {
+                    int64_t row = r0 + 16 * c + 2 * sub + e;
+                    row = row < n ? row : n - 1;
+                    v[16 * c + 2 * q + e] = F[sys * ld + row];
+                }
             }
-            __builtin_amdgcn_sched_barrier(0);  // 8 loads at a time: few addresses live
+            __builtin_amdgcn_sched_barrier(0);  // 16 loads at a time: few addresses live
         }
     }
-    // transpose in place: afterwards v[k] = (row r0 + k, system s0 + lane)
+    // transpose in place, one row parity at a time (8 rows through the 8-row
+    // buffer): afterwards v[k] = (row r0 + k, system s0 + lane)
     double(*tw)[66] = tb[w];
 #pragma unroll
-    for (int c = 0; c < K / 8; c++) {
+    for (int c = 0; c < K / 16; c++) {
 #pragma unroll
-        for (int q = 0; q < 8; q++) tw[sub][8 * q + grp] = v[8 * c + q];
+        for (int e = 0; e < 2; e++) {
 #pragma unroll
-        for (int k = 0; k < 8; k++) {
-            const double x = tw[k][lane];
-            v[8 * c + k] = 8 * c + k < L ? x : 0.0;  // rows past the matrix
+            for (int q = 0; q < 8; q++) tw[sub][8 * q + grp] = v[16 * c + 2 * q + e];
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const int row = 16 * c + 2 * k + e;
+                const double x = tw[k][lane];
+                v[row] = row < L ? x : 0.0;  // rows past the matrix
+            }
         }
     }
     group_phases<K, W>(v, fwd, bwd, seg, r0, w, g, ngroups, u - (unsigned int)g, fst, bst, ex, err,
                        sh, agg, mat);
-    // transpose back and store the positions inside the matrix and batch
+    // transpose back (per row parity) and store whole 128-byte runs
 #pragma unroll
-    for (int c = 0; c < K / 8; c++) {
+    for (int c = 0; c < K / 16; c++) {
 #pragma unroll
-        for (int k = 0; k < 8; k++) tw[k][lane] = v[8 * c + k];
+        for (int e = 0; e < 2; e++) {
 #pragma unroll
-        for (int q = 0; q < 8; q++) v[8 * c + q] = tw[sub][8 * q + grp];
+            for (int k = 0; k < 8; k++) tw[k][lane] = v[16 * c + 2 * k + e];
+#pragma unroll
+            for (int q = 0; q < 8; q++) v[16 * c + 2 * q + e] = tw[sub][8 * q + grp];
+        }
     }
     if (full) {
-        double *pl = F + (s0 + grp) * ld + r0 + sub;
+        double *pl = F + (s0 + grp) * ld + r0 + 2 * sub;
 #pragma unroll
-        for (int c = 0; c < K / 8; c++)
+        for (int c = 0; c < K / 16; c++)
 #pragma unroll
-            for (int q = 0; q < 8; q++) __builtin_nontemporal_store(v[8 * c + q], pl + 8 * q * ld + 8 * c);
+            for (int q = 0; q < 8; q++)
+                __builtin_nontemporal_store(Dbl2{v[16 * c + 2 * q], v[16 * c + 2 * q + 1]},
+                                            (Dbl2 *)(pl + 8 * q * ld + 16 * c));
     } else {
 #pragma unroll
-        for (int c = 0; c < K / 8; c++) {
-            const int64_t row = r0 + 8 * c + sub;
+        for (int c = 0; c < K / 16; c++)
 #pragma unroll
             for (int q = 0; q < 8; q++) {
                 const int64_t sys = s0 + 8 * q + grp;
-                if (row < n && sys < batch) F[sys * ld + row] = v[8 * c + q];
+#pragma unroll
+                for (int e = 0; e < 2; e++) {
+                    const int64_t row = r0 + 16 * c + 2 * sub + e;
+                    if (row < n && sys < batch) F[sys * ld + row] = v[16 * c + 2 * q + e];
+                }
             }
-        }
     }
 }
 
