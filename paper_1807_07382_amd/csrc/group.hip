@@ -14,7 +14,7 @@
 // to the item's slice of the workspace, wave 0 runs the interface recurrence
 // over the segments, pass 2 repeats the sweeps from the true incoming states
 // and writes x in place.  No workgroup ever waits for another.
-#include "internal.h"
+#include "lookback.h"
 
 namespace pent {
 namespace {
@@ -181,15 +181,36 @@ __device__ __forceinline__ unsigned int wave_fetch_add(unsigned int *p, unsigned
 }
 
 // Every lane polls the flag (one address); true once it reads non-zero.
+// The flag and the summaries move with relaxed agent-scope accesses, ordered
+// by waiting for the writer's own stores before its flag (as the single
+// pass does): acquire / release operations would invalidate or write back a
+// whole XCD L2 per poll.
 __device__ __forceinline__ bool wait_flag(unsigned int *flag)
 {
     for (int spins = 0; spins < kSpinLimit; spins++) {
-        const unsigned int v = __hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned int v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
         if (__builtin_amdgcn_readlane((int)v, 0) != 0) return true;
         __builtin_amdgcn_s_sleep(2);
     }
     return false;
 }
+
+// Device-coherent element access for interface_chain over the summaries,
+// which waves on other XCDs wrote.
+struct CohRef {
+    double *p;
+    __device__ operator double() const { return lb::xload(p); }
+    __device__ CohRef &operator=(double v)
+    {
+        lb::xstore(p, v);
+        return *this;
+    }
+};
+struct CohPtr {
+    double *p;
+    __device__ CohRef operator[](int64_t i) const { return CohRef{p + i}; }
+};
 
 template <int kGK>
 __global__ __launch_bounds__(64) void k_group_tasks(const GroupMat *__restrict__ mats,
@@ -229,24 +250,27 @@ __global__ __launch_bounds__(64) void k_group_tasks(const GroupMat *__restrict__
             double p2 = 0.0, p1 = 0.0, q1 = 0.0, q2 = 0.0;
             fwd_seg(v, fwd, r0, p2, p1);
             bwd_seg(v, bwd, r0, q1, q2);
-            o[0] = p2;
-            o[64] = p1;
-            o[128] = q1;
-            o[192] = q2;
-            __threadfence();  // summaries visible before the count
+            double *oc = (double *)o;
+            lb::xstore(oc, p2);
+            lb::xstore(oc + 64, p1);
+            lb::xstore(oc + 128, q1);
+            lb::xstore(oc + 192, q2);
+            lb::store_fence();  // summaries complete before the count
             const int c = (int)wave_fetch_add(&cnt[ii], 1u);
             if (c == nseg - 1) {  // last segment of this item: resolve its interfaces
-                __threadfence();
-                interface_chain(S + lane, (int64_t)256, (int64_t)64, segr, (int64_t)nseg);
-                __threadfence();
-                __hip_atomic_store(&ready[ii], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                // every other segment counted after storing its summaries
+                interface_chain(CohPtr{(double *)(S + lane)}, (int64_t)256, (int64_t)64, segr,
+                                (int64_t)nseg);
+                lb::store_fence();
+                __hip_atomic_store(&ready[ii], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         } else if (!wait_flag(&ready[ii])) {
             atomicExch(&ctr[2], 1u);
         } else {
-            __threadfence();
             load_seg(v, base, m.ld, act ? L : 0);
-            double p2 = o[0], p1 = o[64], q1 = o[128], q2 = o[192];
+            const double *oc = (const double *)o;
+            double p2 = lb::xload(oc), p1 = lb::xload(oc + 64), q1 = lb::xload(oc + 128),
+                   q2 = lb::xload(oc + 192);
             fwd_seg(v, fwd, r0, p2, p1);
             bwd_seg(v, bwd, r0, q1, q2);
             if (act) {
