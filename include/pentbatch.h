@@ -217,12 +217,16 @@ int pent_graph_destroy(pent_graph gr); /* NULL is a no-op */
  * (y*ninst + k)*nx + x); dt: DEVICE, ninst time steps; h: grid spacing.
  * pent_ch2d_rhs:  R = C + dt_k * Lap_h(C^3 - C) (5-point Laplacian, zero
  *                 values outside the grid); C and R must not overlap.
- * pent_ch2d_step: R = the right-hand side above, then the x sweeps
- *                 (I + sigma D4_x) R* = R in place (hx: n = nx, system-major),
- *                 then the y sweeps (I + sigma D4_y) C = R* (hy: n = ny,
- *                 batch-fastest over ninst*nx systems), so C holds the next
- *                 state and R is scratch.  May allocate stream-ordered
- *                 scratch.  Limits: ny, ninst <= 65535. */
+ * pent_ch2d_step: the x sweeps (I + sigma D4_x) R* = RHS (hx: n = nx,
+ *                 system-major) with RHS the right-hand side above, formed
+ *                 inside the sweep kernel from C (it never goes to memory;
+ *                 where one tile of that kernel would not fit on the device,
+ *                 pent_ch2d_rhs writes it to R first and R is swept in
+ *                 place), then the y sweeps (I + sigma D4_y) C = R* (hy:
+ *                 n = ny, batch-fastest over ninst*nx systems), so C holds
+ *                 the next state and R is scratch.  R* is the same, bit for
+ *                 bit, either way.  May allocate stream-ordered scratch.
+ *                 Limits: ny, ninst <= 65535. */
 int pent_ch2d_rhs(const double *C, double *R, int64_t ny, int64_t ninst, int64_t nx,
                   const double *dt, double h, void *stream);
 int pent_ch2d_step(pent_handle hx, pent_handle hy, double *C, double *R, int64_t ny,

@@ -75,6 +75,7 @@ pent_plan *new_plan(int64_t n, int *st)
     p->onepass_cap[0] = p->onepass_cap[1] = 0;
     p->fix_cap = 0;
     p->t_cap = 0;
+    p->tst_cap = 0;
     hipError_t e = hipGetDevice(&p->device);
     if (e == hipSuccess) e = hipMalloc(&p->d_diag, sizeof(double) * 5 * n);
     if (e == hipSuccess) e = hipMalloc(&p->d_fac, sizeof(double) * 4 * n);
@@ -1237,11 +1238,33 @@ int pent_ch2d_step(pent_handle hx, pent_handle hy, double *C, double *R, int64_t
                    int64_t ninst, int64_t nx, const double *dt, double h, void *stream)
 {
     if (!valid(hx) || !valid(hy) || hx->n != nx || hy->n != ny) return ret(PENT_INVALID_VALUE);
-    int st = pent_ch2d_rhs(C, R, ny, ninst, nx, dt, h, stream);
-    if (st != PENT_OK) return st;
-    // x sweeps: system (y, k) is nx contiguous values
-    st = pent_solve_strided(hx, R, ny * ninst, nx, stream);
-    if (st != PENT_OK) return st;
+    if (!C || !R || !dt || ny < 1 || ninst < 1 || nx < 1 || !(h > 0.0) || ny > 65535 ||
+        ninst > 65535 || C == R)
+        return ret(PENT_INVALID_VALUE);
+    hipStream_t s = (hipStream_t)stream;
+    // x sweeps, system (y, k) being nx contiguous values: the single pass
+    // forms the explicit right-hand side from C itself where a tile of it
+    // fits on the device; else the stencil pass writes it to R first
+    const int64_t batch = ny * ninst;
+    if (hx->tst_cap == 0) hx->tst_cap = onepass_t_capacity(true);
+    if (hx->tst_cap > 0 && onepass_t_groups(nx) <= hx->tst_cap / 4 &&
+        (batch + 63) / 64 * onepass_t_groups(nx) <= (int64_t)UINT32_MAX / 2) {
+        int st;
+        const SegRec *seg64 = seg_cache(hx, 64, &st);
+        if (!seg64) return ret(st);
+        void *scratch = nullptr;
+        hipError_t e = hipMallocAsync(&scratch, onepass_t_scratch_bytes(nx, batch), s);
+        if (e != hipSuccess) return ret(hip_status(e));
+        e = launch_onepass_t_ch2d(hx->d_fwd, hx->d_bwd, seg64, nx, C, R, ny, ninst, dt, h, scratch,
+                                  hx->d_err, s);
+        const hipError_t e2 = hipFreeAsync(scratch, s);
+        if (e != hipSuccess || e2 != hipSuccess) return ret(hip_status(e != hipSuccess ? e : e2));
+    } else {
+        int st = pent_ch2d_rhs(C, R, ny, ninst, nx, dt, h, stream);
+        if (st != PENT_OK) return st;
+        st = pent_solve_strided(hx, R, batch, nx, stream);
+        if (st != PENT_OK) return st;
+    }
     // y sweeps: batch-fastest over (k, x), read from R, written into C
     return ret(solve_io_scratch(hy, R, ninst * nx, C, ninst * nx, ninst * nx, (hipStream_t)stream));
 }

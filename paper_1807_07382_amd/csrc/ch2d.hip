@@ -3,7 +3,9 @@
 // Semi-implicit Cahn-Hilliard (Sec. 2.1): the nonlinear term D*Lap(C^3 - C)
 // is taken explicitly, the fourth-order term implicitly.  On a 2-D grid the
 // implicit part is split into an x sweep and a y sweep of (I + sigma*D4)
-// solves; this kernel forms the right-hand side of the x sweep:
+// solves; this kernel forms the right-hand side of the x sweep (the step
+// itself forms it inside the x-sweep kernel; this pass serves pent_ch2d_rhs
+// and the step where that kernel cannot run):
 //     R = C + dt_k * Lap_h(C^3 - C),
 // Lap_h the 5-point Laplacian with zero values outside the grid (matching the
 // truncated D4 rows), one dt per instance.  Layout [y][inst][x], contiguous:
@@ -12,8 +14,6 @@
 
 namespace pent {
 namespace {
-
-__device__ __forceinline__ double wterm(double c) { return c * c * c - c; }
 
 // One thread per (x, instance) walks kRows consecutive y rows, keeping the
 // y-neighbours' C^3 - C in registers, so each element of C comes from memory
@@ -41,7 +41,6 @@ __global__ __launch_bounds__(256) void k_ch2d_rhs(const double *__restrict__ C,
         double cc[kRows + 2], ce[kRows], cw[kRows];
         const double *col = C + i - sy;
         const int de = x + 1 < nx ? 1 : 0, dw = x >= 1 ? 1 : 0;
-        const double me = de, mw = dw;
 #pragma unroll
         for (int r = 0; r < kRows + 2; r++) cc[r] = col[r * sy];
 #pragma unroll
@@ -51,25 +50,23 @@ __global__ __launch_bounds__(256) void k_ch2d_rhs(const double *__restrict__ C,
         }
 #pragma unroll
         for (int r = 0; r < kRows; r++) {
-            const double w = wterm(cc[r + 1]);
-            const double we = me * wterm(ce[r]);
-            const double ww = mw * wterm(cw[r]);
-            const double lap = (we + ww + wterm(cc[r + 2]) + wterm(cc[r]) - 4.0 * w) * inv_h2;
-            R[i + r * sy] = cc[r + 1] + dtk * lap;
+            const double we = de ? ch_wterm(ce[r]) : 0.0;
+            const double ww = dw ? ch_wterm(cw[r]) : 0.0;
+            R[i + r * sy] = ch_point(cc[r + 1], ch_wterm(cc[r + 1]), we, ww, ch_wterm(cc[r + 2]),
+                                     ch_wterm(cc[r]), dtk, inv_h2);
         }
         return;
     }
-    double ws = y0 >= 1 ? wterm(C[i - sy]) : 0.0;
+    double ws = y0 >= 1 ? ch_wterm(C[i - sy]) : 0.0;
     double c = C[i];
-    double w = wterm(c);
+    double w = ch_wterm(c);
     const int64_t y1 = y0 + kRows < ny ? y0 + kRows : ny;
     for (int64_t y = y0; y < y1; y++) {
         const double cn = y + 1 < ny ? C[i + sy] : 0.0;
-        const double wn = y + 1 < ny ? wterm(cn) : 0.0;
-        const double we = (x + 1 < nx) ? wterm(C[i + 1]) : 0.0;
-        const double ww = (x >= 1) ? wterm(C[i - 1]) : 0.0;
-        const double lap = (we + ww + wn + ws - 4.0 * w) * inv_h2;
-        R[i] = c + dtk * lap;
+        const double wn = y + 1 < ny ? ch_wterm(cn) : 0.0;
+        const double we = (x + 1 < nx) ? ch_wterm(C[i + 1]) : 0.0;
+        const double ww = (x >= 1) ? ch_wterm(C[i - 1]) : 0.0;
+        R[i] = ch_point(c, w, we, ww, wn, ws, dtk, inv_h2);
         ws = w;
         w = wn;
         c = cn;

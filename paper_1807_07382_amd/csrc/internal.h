@@ -164,6 +164,7 @@ struct pent_plan {
     int onepass_cap[2];      // co-resident single-pass units (32, 64 rows), 0 = not yet queried
     int fix_cap;             // co-resident units of the fused correction, 0 = not yet queried
     int t_cap;               // ... of the system-major single pass
+    int tst_cap;             // ... of its form with the 2-D Cahn-Hilliard stencil
     std::mutex mu;           // guards seg caches (lazy build)
     pent::SegCache seg[pent::kMaxSegCaches];
     pent::ScanRec *d_scan;   // resident-tile scan constants (64 records), lazily built
@@ -284,7 +285,18 @@ hipError_t launch_eta(const double *d_diag, const double *d_anorm, int64_t n, co
                       unsigned long long *acc, double *eta, hipStream_t s);
 hipError_t launch_anorm(const double *d_diag, int64_t n, double *d_anorm, hipStream_t s);
 
-// ---- 2-D Cahn-Hilliard explicit term (ch2d.hip) ----
+// ---- 2-D Cahn-Hilliard explicit term (ch2d.hip, and fused into k_onepass_t) ----
+// R = C + dt_k * Lap_h(C^3 - C) at one point, from the point's C and the
+// C^3 - C of itself and its four neighbours (zero outside the grid).  Both
+// kernels that form it go through these two functions, so they agree bit
+// for bit.
+__device__ __forceinline__ double ch_wterm(double c) { return c * c * c - c; }
+__device__ __forceinline__ double ch_point(double c, double w, double we, double ww, double wn,
+                                           double ws, double dtk, double inv_h2)
+{
+    const double lap = (we + ww + wn + ws - 4.0 * w) * inv_h2;
+    return c + dtk * lap;
+}
 hipError_t launch_ch2d_rhs(const double *C, double *R, int64_t ny, int64_t ninst, int64_t nx,
                            const double *dt, double h, hipStream_t s);
 
@@ -296,12 +308,19 @@ int64_t onepass_groups(int64_t n, int seg_rows);     // workgroups per 64-system
 int64_t onepass_units(int64_t n, int seg_rows, int64_t batch);
 size_t onepass_scratch_bytes(int64_t n, int seg_rows, int64_t batch);
 int onepass_capacity(int seg_rows);  // co-resident workgroups on the current device
-int onepass_t_capacity();
+int onepass_t_capacity(bool stencil = false);
 int64_t onepass_t_groups(int64_t n);
 size_t onepass_t_scratch_bytes(int64_t n, int64_t batch);
 hipError_t launch_onepass_t(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg64, int64_t n,
                             double *F, int64_t batch, int64_t ld, void *scratch, unsigned int *err,
                             hipStream_t s);
+// The x sweeps of a 2-D Cahn-Hilliard step with its explicit right-hand side
+// formed on the fly: grid C[y][k][x] (ny x ninst x nx, contiguous) in, the
+// swept R (same layout) out; systems (y, k), nx rows each (n == nx).
+hipError_t launch_onepass_t_ch2d(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg64,
+                                 int64_t n, const double *C, double *R, int64_t ny, int64_t ninst,
+                                 const double *dt, double h, void *scratch, unsigned int *err,
+                                 hipStream_t s);
 int onepass_fix_capacity();
 int64_t onepass_fix_groups(int64_t n);
 size_t onepass_fix_scratch_bytes(int64_t n, int64_t batch);

@@ -7,7 +7,8 @@
 // side in registers from load to store; the waves pass their segment
 // interface states through LDS, and the groups of a tile exchange theirs by
 // decoupled look-back (lookback.h).  Variants: many matrices in one launch
-// (k_group_onepass), system-major storage (k_onepass_t), and one fused
+// (k_group_onepass), system-major storage (k_onepass_t, also with the 2-D
+// Cahn-Hilliard explicit term formed in the kernel), and one fused
 // refinement correction (k_onepass_fix).
 //
 // Units take tickets from a counter in ticket order (tile-major), so a unit
@@ -185,14 +186,29 @@ __device__ __forceinline__ void fix_residual(double (&v)[K], const double *diag,
 // every lane holds one system's rows, as in k_onepass.  Positions past the matrix or
 // the batch load from clamped addresses (no load under a per-lane test) and
 // are zeroed or never stored.
-template <int K, int W>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_onepass_t(
+//
+// ST: the x sweeps of a 2-D Cahn-Hilliard step (Sec. 2.1's semi-implicit
+// scheme, split over x and y) with the explicit right-hand side formed here
+// instead of in a pass of its own: C[y][k][x] is read, R = C + dt_k *
+// Lap_h(C^3 - C) is formed in registers and swept, and the result is stored
+// to F (same layout).  Systems are numbered instance-major, s = k * ny + y,
+// so the 64 systems of a tile are consecutive y of one instance (where the
+// tile does not straddle two): a system's y neighbours are the adjacent
+// lanes, read back through the transpose buffer, plus one halo system above
+// and below the tile (one row per lane); its x neighbours are the adjacent
+// rows in registers, plus one value past each end of the block.
+template <int K, int W, bool ST>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(ST ? 2 : 3))) void k_onepass_t(
     const FwdRec *fwd_, const BwdRec *bwd_, const SegRec *seg_, int64_t n, int ngroups, double *F,
     int64_t ld, int64_t batch, unsigned int *ctr, unsigned int *fst, unsigned int *bst, double *ex,
-    unsigned int *err)
+    unsigned int *err, const double *Cin, int64_t ny, int64_t ninst, const double *dt,
+    double inv_h2)
 {
+    static_assert(!ST || K == 64, "the halo rows are held one per lane");
     PENT_GROUP_LDS(W);
     __shared__ double tb[W][8][66];  // row stride 66: the transposing writes hit distinct banks
+    __shared__ double hw[ST ? W : 1][2][64];  // ST: the halo systems' C^3 - C, by row
+    __shared__ double xe[ST ? W : 1][2][64];  // ST: each block's first and last row of C
     __shared__ unsigned int s_unit;
     const CFwd fwd = (CFwd)fwd_;
     const CBwd bwd = (CBwd)bwd_;
@@ -208,23 +224,36 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     const int64_t rem = n - r0;
     const int L = (int)(rem < 0 ? 0 : rem < K ? rem : K);
     const int sub = lane & 7, grp = lane >> 3;  // row in a chunk, system in an 8-system slice
+    // first element of system s, and the distance between consecutive
+    // systems of one run (ST: instance k's systems at y * ninst * ld + k * ld)
+    auto sbase = [&](int64_t s) -> int64_t {
+        if constexpr (ST) {
+            const int64_t k = s / ny;
+            return ((s - k * ny) * ninst + k) * ld;
+        } else {
+            return s * ld;
+        }
+    };
+    const int64_t sst = ST ? ninst * ld : ld;
+    const double *src = ST ? Cin : F;
     double v[K];
     // raw loads in 16-row chunks c: lane (sub, grp) takes rows 2 sub, 2 sub + 1
     // of the chunk of system s0 + 8q + grp (8 lanes cover a whole 128-byte
     // run of each system), into v[16c + 2q + e], e the row parity.  A full
-    // block (all rows in the matrix, all 64 systems in the batch) is one
-    // per-lane base plus uniform offsets; a ragged one clamps each address.
-    // (the 16-byte accesses also need every system's run 16-byte aligned:
-    // an even ld and F itself aligned)
+    // block (all rows in the matrix, all 64 systems in the batch, and for ST
+    // in one instance) is one per-lane base plus uniform offsets; a ragged
+    // one clamps each address.  (the 16-byte accesses also need every
+    // system's run 16-byte aligned: an even ld and F itself aligned)
     typedef double Dbl2 __attribute__((ext_vector_type(2)));
-    const bool full = L == K && s0 + 64 <= batch && ld % 2 == 0 && (uintptr_t)F % 16 == 0;
+    bool full = L == K && s0 + 64 <= batch && ld % 2 == 0 && (uintptr_t)F % 16 == 0;
+    if constexpr (ST) full = full && s0 % ny + 64 <= ny && (uintptr_t)Cin % 16 == 0;
     if (full) {
-        const double *pl = F + (s0 + grp) * ld + r0 + 2 * sub;
+        const double *pl = src + sbase(s0) + grp * sst + r0 + 2 * sub;
 #pragma unroll
         for (int c = 0; c < K / 16; c++)
 #pragma unroll
             for (int q = 0; q < 8; q++) {
-                const Dbl2 p = __builtin_nontemporal_load((const Dbl2 *)(pl + 8 * q * ld + 16 * c));
+                const Dbl2 p = __builtin_nontemporal_load((const Dbl2 *)(pl + 8 * q * sst + 16 * c));
                 v[16 * c + 2 * q] = p.x;
                 v[16 * c + 2 * q + 1] = p.y;
             }
@@ -235,15 +264,41 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
             for (int q = 0; q < 8; q++) {
                 int64_t sys = s0 + 8 * q + grp;
                 sys = sys < batch ? sys : batch - 1;
+                const int64_t sb = sbase(sys);
 #pragma unroll
                 for (int e = 0; e < 2; e++) {
                     int64_t row = r0 + 16 * c + 2 * sub + e;
                     row = row < n ? row : n - 1;
-                    v[16 * c + 2 * q + e] = F[sys * ld + row];
+                    v[16 * c + 2 * q + e] = src[sb + row];
                 }
             }
             __builtin_amdgcn_sched_barrier(0);  // 16 loads at a time: few addresses live
         }
+    }
+    // ST: the values around the block, loaded now to arrive with it
+    double xl = 0.0, xr = 0.0, h0 = 0.0, h1 = 0.0, dtk = 0.0;
+    bool up = false, dn = false;
+    if constexpr (ST) {
+        const int64_t sl = s0 + lane < batch ? s0 + lane : batch - 1;  // this lane's system
+        const int64_t kl = sl / ny, yl = sl - kl * ny;
+        const int64_t bl = (yl * ninst + kl) * ld;
+        up = yl >= 1;
+        dn = yl + 1 < ny;
+        // the rows just past the block: inside the workgroup they are its
+        // neighbour waves' (exchanged below); only the group's first and
+        // last wave load them (a block wholly past the matrix, r0 >= n,
+        // clamps both to row n - 1)
+        if (w == 0) xl = Cin[bl + (r0 < 1 ? 0 : r0 - 1 < n ? r0 - 1 : n - 1)];
+        if (w == W - 1) xr = Cin[bl + (r0 + K < n ? r0 + K : n - 1)];
+        dtk = dt[kl];
+        // halo systems: s0 - 1 above lane 0, s0 + 64 below lane 63 (each used
+        // only where that lane's own mask allows: same instance, inside the
+        // grid), row r0 + lane of each
+        const int64_t hrow = r0 + lane < n ? r0 + lane : n - 1;
+        const int64_t sa = s0 >= 1 ? s0 - 1 : 0;
+        const int64_t sb = s0 + 64 < batch ? s0 + 64 : batch - 1;
+        h0 = Cin[sbase(sa) + hrow];
+        h1 = Cin[sbase(sb) + hrow];
     }
     // transpose in place, one row parity at a time (8 rows through the 8-row
     // buffer): afterwards v[k] = (row r0 + k, system s0 + lane)
@@ -262,6 +317,50 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
             }
         }
     }
+    if constexpr (ST) {
+        // right-hand side in place, 8 rows at a time: the rows' C^3 - C go
+        // through the buffer (column 1 + lane) so each lane reads its y
+        // neighbours'; lanes 0 and 63 read the halo systems' (hw, by row)
+        // instead.  Every lane reads (from a selected address) and masks
+        // the value: a read under a per-lane test would become a branch per
+        // row.  x neighbours roll along the rows.
+        const bool west = r0 >= 1, east = r0 + K < n;
+        hw[w][0][lane] = ch_wterm(h0);
+        hw[w][1][lane] = ch_wterm(h1);
+        xe[w][0][lane] = v[0];
+        xe[w][1][lane] = v[K - 1];
+        __syncthreads();
+        if (w > 0) xl = xe[w - 1][1][lane];
+        if (w < W - 1) xr = xe[w + 1][0][lane];
+        double wprev = west ? ch_wterm(xl) : 0.0;
+        double wcur = ch_wterm(v[0]);
+#pragma unroll
+        for (int b = 0; b < K / 8; b++) {
+#pragma unroll
+            for (int k = 0; k < 8; k++) tw[k][lane + 1] = ch_wterm(v[8 * b + k]);
+            // other lanes' writes are read below, and this batch's reads
+            // precede the next batch's writes: to one lane the addresses
+            // never coincide, so without these fences the compiler may
+            // reorder them (the wave's LDS accesses then run in order)
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const int row = 8 * b + k;
+                const double tn = *(lane == 63 ? &hw[w][1][row] : &tw[k][lane + 2]);
+                const double ts = *(lane == 0 ? &hw[w][0][row] : &tw[k][lane]);
+                const double wn = dn ? tn : 0.0;
+                const double ws = up ? ts : 0.0;
+                const double wnext = ch_wterm(row + 1 < K ? v[row + 1] : xr);
+                const double we = (row + 1 < K ? r0 + row + 1 < n : east) ? wnext : 0.0;
+                const double r = ch_point(v[row], wcur, we, wprev, wn, ws, dtk, inv_h2);
+                wprev = wcur;
+                wcur = wnext;
+                v[row] = row < L ? r : 0.0;
+            }
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_sched_barrier(0);  // one batch at a time
+        }
+    }
     group_phases<K, W>(v, fwd, bwd, seg, r0, w, g, ngroups, u - (unsigned int)g, fst, bst, ex, err,
                        sh, agg, mat);
     // transpose back (per row parity) and store whole 128-byte runs
@@ -276,23 +375,24 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
         }
     }
     if (full) {
-        double *pl = F + (s0 + grp) * ld + r0 + 2 * sub;
+        double *pl = F + sbase(s0) + grp * sst + r0 + 2 * sub;
 #pragma unroll
         for (int c = 0; c < K / 16; c++)
 #pragma unroll
             for (int q = 0; q < 8; q++)
                 __builtin_nontemporal_store(Dbl2{v[16 * c + 2 * q], v[16 * c + 2 * q + 1]},
-                                            (Dbl2 *)(pl + 8 * q * ld + 16 * c));
+                                            (Dbl2 *)(pl + 8 * q * sst + 16 * c));
     } else {
 #pragma unroll
         for (int c = 0; c < K / 16; c++)
 #pragma unroll
             for (int q = 0; q < 8; q++) {
                 const int64_t sys = s0 + 8 * q + grp;
+                const int64_t sb = sbase(sys < batch ? sys : batch - 1);
 #pragma unroll
                 for (int e = 0; e < 2; e++) {
                     const int64_t row = r0 + 16 * c + 2 * sub + e;
-                    if (row < n && sys < batch) F[sys * ld + row] = v[16 * c + 2 * q + e];
+                    if (row < n && sys < batch) F[sb + row] = v[16 * c + 2 * q + e];
                 }
             }
     }
@@ -468,14 +568,14 @@ hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *se
 // segments, four per workgroup; scratch as launch_onepass.
 constexpr int kTK = 64, kTW = 4;
 
-int onepass_t_capacity()
+int onepass_t_capacity(bool stencil)
 {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_onepass_t<kTK, kTW>,
-                                                     64 * kTW, 0) != hipSuccess)
-        return 0;
+    const void *fn = stencil ? (const void *)k_onepass_t<kTK, kTW, true>
+                             : (const void *)k_onepass_t<kTK, kTW, false>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * kTW, 0) != hipSuccess) return 0;
     return cus * per_cu;
 }
 
@@ -489,9 +589,12 @@ size_t onepass_t_scratch_bytes(int64_t n, int64_t batch)
     return wbytes + (size_t)units * kExRows * 64 * sizeof(double);
 }
 
-hipError_t launch_onepass_t(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg64, int64_t n,
-                            double *F, int64_t batch, int64_t ld, void *scratch, unsigned int *err,
-                            hipStream_t s)
+namespace {
+
+hipError_t launch_t(bool stencil, const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg64,
+                    int64_t n, double *F, int64_t batch, int64_t ld, void *scratch,
+                    unsigned int *err, const double *Cin, int64_t ny, int64_t ninst,
+                    const double *dt, double inv_h2, hipStream_t s)
 {
     const int64_t ngroups = onepass_t_groups(n);
     const int64_t units = (batch + 63) / 64 * ngroups;
@@ -505,11 +608,31 @@ hipError_t launch_onepass_t(const FwdRec *fwd, const BwdRec *bwd, const SegRec *
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int ng = (int)ngroups;
-    void *args[] = {(void *)&fwd, (void *)&bwd, (void *)&seg64, (void *)&n, (void *)&ng, (void *)&F,
-                    (void *)&ld, (void *)&batch, (void *)&ctr, (void *)&fst, (void *)&bst,
-                    (void *)&ex, (void *)&err};
-    return hipLaunchKernel((const void *)k_onepass_t<kTK, kTW>, dim3((unsigned)units), dim3(64 * kTW),
-                           args, 0, s);
+    void *args[] = {(void *)&fwd, (void *)&bwd, (void *)&seg64, (void *)&n,   (void *)&ng,
+                    (void *)&F,   (void *)&ld,  (void *)&batch, (void *)&ctr, (void *)&fst,
+                    (void *)&bst, (void *)&ex,  (void *)&err,   (void *)&Cin, (void *)&ny,
+                    (void *)&ninst, (void *)&dt, (void *)&inv_h2};
+    const void *fn = stencil ? (const void *)k_onepass_t<kTK, kTW, true>
+                             : (const void *)k_onepass_t<kTK, kTW, false>;
+    return hipLaunchKernel(fn, dim3((unsigned)units), dim3(64 * kTW), args, 0, s);
+}
+
+}  // namespace
+
+hipError_t launch_onepass_t(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg64, int64_t n,
+                            double *F, int64_t batch, int64_t ld, void *scratch, unsigned int *err,
+                            hipStream_t s)
+{
+    return launch_t(false, fwd, bwd, seg64, n, F, batch, ld, scratch, err, F, batch, 1, nullptr, 0.0, s);
+}
+
+hipError_t launch_onepass_t_ch2d(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg64,
+                                 int64_t n, const double *C, double *R, int64_t ny, int64_t ninst,
+                                 const double *dt, double h, void *scratch, unsigned int *err,
+                                 hipStream_t s)
+{
+    return launch_t(true, fwd, bwd, seg64, n, R, ny * ninst, n, scratch, err, C, ny, ninst, dt,
+                    1.0 / (h * h), s);
 }
 
 // One fused refinement correction (k_onepass_fix): x += A^{-1}(f - A x).

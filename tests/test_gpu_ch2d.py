@@ -75,3 +75,29 @@ def test_full_grid_sampled_instances(torch):
         got = C[:, k:k + 1, :].cpu().numpy()
         err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
         assert err <= 2 * steps * d4_tol(sigma), (k, err)
+
+
+@pytest.mark.parametrize("ny,ninst,nx", [(96, 3, 96), (70, 2, 130), (37, 3, 45), (5, 1, 300),
+                                         (64, 2, 1024), (130, 5, 640), (1024, 32, 1024)])
+def test_fused_step_matches_separate_passes(torch, ny, ninst, nx):
+    """The step forms the x sweeps' right-hand side inside the sweep kernel;
+    it must equal the stencil pass followed by the system-major sweeps bit
+    for bit (same point formula, same canonical sweep arithmetic), over
+    ragged blocks, tiles that straddle two instances, odd row lengths (no
+    16-byte path) and the full grid."""
+    print_case(test="ch2d_fused", ny=ny, ninst=ninst, nx=nx)
+    g = np.random.Generator(np.random.PCG64(ny * 7919 + nx))
+    sigma = 200.0
+    C0 = g.uniform(-0.1, 0.1, (ny, ninst, nx))
+    h = 1.0 / nx
+    dt = torch.from_numpy(sigma * h ** 4 / g.uniform(1e-3, 1e-1, ninst)).cuda()
+    C = torch.from_numpy(C0).cuda()
+    R = torch.empty_like(C)
+    R2 = torch.empty_like(C)
+    with pb.Plan.factor_d4(nx, sigma) as px, pb.Plan.factor_d4(ny, sigma) as py:
+        pb.ch2d_rhs(C, R2, dt, h)
+        px.solve_strided_(R2.view(ny * ninst, nx))
+        pb.ch2d_step(px, py, C, R, dt, h)
+        torch.cuda.synchronize()
+        px.check()
+    assert torch.equal(R, R2)
