@@ -603,12 +603,21 @@ int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64
         for (int64_t sg = 0; sg < (n + 31) / 32; sg++) t32.push_back(make_int2((int)i, (int)sg));
     }
     if (t32.size() > (size_t)INT32_MAX / 2) return PENT_NOT_SUPPORTED;
-    // unit table of the single pass: every item's row groups, consecutive,
-    // items in work-list order (longest first)
+    // unit table of the single pass: every item's row groups, consecutive;
+    // items with the longest chains of groups (largest n) first, then the
+    // widest (measured ~1% faster than the work-list order, whose per-item
+    // balance is not what bounds the single pass)
+    std::vector<size_t> uorder(items.size());
+    for (size_t i = 0; i < items.size(); i++) uorder[i] = i;
+    std::stable_sort(uorder.begin(), uorder.end(), [&](size_t a, size_t b) {
+        const int64_t na = mats[items[a].mat].n, nb = mats[items[b].mat].n;
+        if (na != nb) return na > nb;
+        return items[a].ncols > items[b].ncols;
+    });
     std::vector<GroupUnit> units;
     int64_t max_groups = 0;
     const int64_t orows = group_onepass_rows();
-    for (size_t i = 0; i < items.size(); i++) {
+    for (size_t i : uorder) {
         const int64_t ng = (mats[items[i].mat].n + orows - 1) / orows;
         max_groups = std::max(max_groups, ng);
         const int64_t u0 = (int64_t)units.size();
