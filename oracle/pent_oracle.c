@@ -210,14 +210,17 @@ int orc_residual(int64_t n, const double *a, const double *b, const double *c,
             }
             double r = s + comp;
             double ar = fabs(r), ax = fabs(X[i * ldx + j]), af = fabs(Fo[i * ldf + j]);
-            if (ar > rmax) rmax = ar;
-            if (ax > xmax) xmax = ax;
-            if (af > fmax) fmax = af;
+            /* maxima that keep a NaN: a non-finite x has no finite backward error */
+            if (ar > rmax || ar != ar) rmax = ar;
+            if (ax > xmax || ax != ax) xmax = ax;
+            if (af > fmax || af != af) fmax = af;
             r2 += r * r;
             f2 += Fo[i * ldf + j] * Fo[i * ldf + j];
         }
         double den = anorm * xmax + fmax;
-        if (eta) eta[j] = den > 0.0 ? rmax / den : 0.0;
+        /* den == 0 only for x = 0 and f = 0, where r = 0 too; a NaN in either
+         * maximum reaches eta */
+        if (eta) eta[j] = (den > 0.0 || den != den) ? rmax / den : rmax;
         if (rho) rho[j] = f2 > 0.0 ? sqrt(r2) / sqrt(f2) : sqrt(r2);
     }
     return ORC_OK;

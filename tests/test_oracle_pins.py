@@ -353,3 +353,20 @@ def test_backward_error_of_oracle_solution_is_small(sigma):
     X = oracle.solve(dg, F)
     eta, rho = oracle.residual(dg, X, F)
     assert np.all(eta <= 1e-15)
+
+
+@pytest.mark.parametrize("bad", [np.nan, np.inf, -np.inf])
+def test_backward_error_of_non_finite_solution_is_not_finite(bad):
+    """A solution with a NaN or an infinite entry has no finite backward
+    error: eta must come out non-finite, never 0 (a max that skipped the NaN
+    would report a clean column)."""
+    n = 12
+    dg = oracle.assemble_d4(n, 2.0)
+    F = np.random.Generator(np.random.PCG64(11)).uniform(-1, 1, (n, 3))
+    X = oracle.solve(dg, F)
+    X[5, 1] = bad
+    X[:, 2] = bad
+    eta, _ = oracle.residual(dg, X, F)
+    assert np.isfinite(eta[0]) and eta[0] <= 1e-15
+    assert not np.isfinite(eta[1])
+    assert not np.isfinite(eta[2])
