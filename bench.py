@@ -212,7 +212,7 @@ def precision_compare(torch, sigma, reps=10, seed=4):
         # correction solve + x += d (24)
         refine1 = solve32 + (28 if one else 20 + solve64 + 24)
         out["schedule"] = "single pass" if one else "partitioned"
-        nbytes = pb.lib().pent_mixed_workspace_size(plan.handle, m, 1, 1)
+        nbytes = plan.mixed_workspace_size(m, 1, True)
         work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
 
         def rel_err(T):
@@ -274,7 +274,7 @@ def run_group(args, torch):
         p.autotune(F.shape[1])
     s = torch.cuda.Stream()
     res = {}
-    for mode in (0, 1):
+    for mode in (pb.GROUP_FP64, pb.GROUP_PER_MATRIX):
         for T, I in zip(Ts, init):
             T.copy_(I)
         torch.cuda.synchronize()
@@ -296,9 +296,9 @@ def run_group(args, torch):
         graph.close()
         res[mode] = dict(ms=ms, max_rel_err_vs_oracle=max(errs))
     g.close()
-    ms_step = res[0]["ms"] / steps
+    ms_step = res[pb.GROUP_FP64]["ms"] / steps
     gbs = BYTES_PER_UNKNOWN_FP64 * unknowns / (ms_step / 1e3) / 1e9
-    return dict(metric=METRIC, value=systems * steps / (res[0]["ms"] / 1e3), unit="RHS-solves/s",
+    return dict(metric=METRIC, value=systems * steps / (res[pb.GROUP_FP64]["ms"] / 1e3), unit="RHS-solves/s",
                 n_gpus=1, steps=steps, warmup=1, ms_per_step=ms_step, higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
                 config=dict(workload="group", matrices=len(mats), unknowns_per_step=unknowns,
@@ -307,10 +307,11 @@ def run_group(args, torch):
                               frac=gbs / PEAK_HBM_GBS,
                               traffic=traffic_for("group_onepass64", "group",
                                                   ("onepass.hip", "lookback.h"))
-                              if variant == 6 else None),
-                persistent=res[0],
-                per_matrix=dict(res[1], ms_per_step=res[1]["ms"] / steps,
-                                speedup_of_persistent=res[1]["ms"] / res[0]["ms"]))
+                              if variant == 1 else None),
+                persistent=res[pb.GROUP_FP64],
+                per_matrix=dict(res[pb.GROUP_PER_MATRIX],
+                                ms_per_step=res[pb.GROUP_PER_MATRIX]["ms"] / steps,
+                                speedup_of_persistent=res[pb.GROUP_PER_MATRIX]["ms"] / res[pb.GROUP_FP64]["ms"]))
 
 
 def run_cahn2d(args, torch):

@@ -122,17 +122,36 @@ int pent_solve_strided(pent_handle h, double *F, int64_t batch, int64_t ld, void
  *             kernels (residual, solve, update).
  *   eta_out : optional DEVICE array of batch doubles; receives each system's
  *             backward error ||f - A x||_inf / (||A||_inf ||x||_inf +
- *             ||f||_inf) with the residual evaluated compensated.
+ *             ||f||_inf) with the residual evaluated compensated (NaN or Inf
+ *             when x has a non-finite entry).
  *   work    : DEVICE scratch of at least
- *             pent_mixed_workspace_size(h, batch, refine_steps, eta_out != NULL)
- *             bytes, caller-owned (NULL allowed when that size is 0).
- * Asynchronous on `stream`; allocates nothing.  Returns PENT_INVALID_VALUE
- * for bad arguments, PENT_SIZE_MISMATCH for a workspace that is too small,
- * PENT_NOT_SUPPORTED for n > 2097120. */
+ *             pent_mixed_workspace_size_ex(h, batch, refine_steps, eta_out != NULL)
+ *             bytes (pent_mixed_workspace_size(h, batch) covers every
+ *             refine_steps and eta_out), caller-owned (NULL allowed when
+ *             that size is 0).
+ * With a tolerance set (pent_set_refine_tolerance) the backward error is
+ * evaluated after the corrections even when eta_out is NULL, and a system
+ * whose eta exceeds the tolerance (or is not finite) makes the next
+ * pent_check return PENT_NOT_CONVERGED; nothing waits on the host.
+ * Asynchronous on `stream`; allocates nothing once the handle's per-schedule
+ * tables exist (pent_factor builds those of the automatic schedule; a
+ * schedule forced later builds its own on first use, blocking once).
+ * Returns PENT_INVALID_VALUE for bad arguments, PENT_SIZE_MISMATCH for a
+ * workspace that is too small, PENT_NOT_SUPPORTED for n > 2097120. */
 int pent_solve_mixed(pent_handle h, const void *f, int f_dtype, int64_t ld_f, double *x,
                      int64_t ld_x, int64_t batch, int refine_steps, double *eta_out, void *work,
                      size_t work_bytes, void *stream);
-size_t pent_mixed_workspace_size(pent_handle h, int64_t batch, int refine_steps, int want_eta);
+/* Workspace of pent_solve_mixed for `batch` systems, enough for any
+ * refine_steps (0..16) with eta_out and a tolerance; 0 on a bad argument. */
+size_t pent_mixed_workspace_size(pent_handle h, int64_t batch);
+/* Workspace for one configuration: refine_steps corrections, want_eta != 0
+ * when eta_out will be passed (a tolerance set on h counts as want_eta). */
+size_t pent_mixed_workspace_size_ex(pent_handle h, int64_t batch, int refine_steps, int want_eta);
+
+/* Backward-error tolerance of h's refined solves (pent_solve_mixed): tol > 0
+ * turns the check on, 0 (the default) off.  PENT_INVALID_VALUE for a
+ * negative or non-finite tol.  Host-only. */
+int pent_set_refine_tolerance(pent_handle h, double tol);
 
 /* Per-system backward error of a computed solution x (same definition and
  * layouts as eta_out above).  work: DEVICE scratch of at least
@@ -155,59 +174,75 @@ pent_group pent_group_create(const pent_handle *hs, int64_t count);
  * batch[count]); 0 on error. */
 size_t pent_group_workspace_size(pent_group g, const int64_t *batch);
 
+/* Group solve modes. */
+#define PENT_GROUP_FP64 0      /* one launch for all matrices, FP64 streams */
+#define PENT_GROUP_MIXED 1     /* FP32 streams: not supported, see below */
+#define PENT_GROUP_PER_MATRIX 2 /* one solve per matrix, the baseline */
+
 /* Solve every matrix k on its own block: F[k] (DEVICE pointer, FP64,
  * batch-fastest, element (i, j) at F[k][i*ld[k] + j]) is overwritten with
  * A_k^{-1} F[k].  F, batch and ld are HOST arrays of `count` entries.
- * mode 0: one persistent launch for all matrices, work items of (matrix,
- *         64 consecutive systems) taken longest first from a device counter;
- * mode 1: one solve per matrix (the library's single-matrix schedules, one
- *         after the other on `stream`), the baseline the persistent launch
- *         is compared with.
+ * mode PENT_GROUP_FP64: one launch for all matrices (the kernel variant set
+ *         by pent_group_set_variant or pent_group_autotune);
+ * mode PENT_GROUP_MIXED: returns PENT_NOT_SUPPORTED after the argument
+ *         checks.  In a time-stepping group the right-hand side of a step is
+ *         the FP64 solution of the previous one, so there is no FP32 stream
+ *         whose bytes could be saved; pent_solve_mixed covers right-hand
+ *         sides that arrive in FP32;
+ * mode PENT_GROUP_PER_MATRIX: one solve per matrix (the library's
+ *         single-matrix schedules, one after the other on `stream`), the
+ *         baseline the single launch is compared with.
  * work: DEVICE scratch of at least pent_group_workspace_size() bytes.
  * The buffer table is uploaded (blocking) only when F/batch/ld differ from
  * the previous call, so repeated calls with the same buffers only enqueue
  * kernels and may be captured into a graph.  Calls on one group must not
- * overlap in time (they share the group's work counter). */
+ * overlap in time (they share the group's work counter).  The handles must
+ * outlive the group and every graph captured from it. */
 int pent_group_solve(pent_group g, double *const *F, const int64_t *batch, const int64_t *ld,
                      int mode, void *work, size_t work_bytes, void *stream);
-int pent_group_destroy(pent_group g); /* NULL is a no-op */
+int pent_group_destroy(pent_group g); /* NULL is a no-op; graphs captured from g stay valid */
 
-/* Autotune the persistent group kernel for these right-hand-side counts
- * (HOST array batch[count]): every kernel variant (64 or 32 rows per segment,
- * 8 or 4 waves per workgroup) is timed on scratch blocks of the same shapes
- * (the caller's data is not touched) and the fastest is kept for later mode-0
- * solves.  Blocking; allocates scratch for the duration of the call.
- * variant_out / ms_out (HOST, optional) receive the choice and its time. */
+/* Autotune the group kernel for these right-hand-side counts (HOST array
+ * batch[count]): every variant that can run is timed on scratch blocks of
+ * the same shapes (the caller's data and binding are not touched) and the
+ * fastest is kept for later PENT_GROUP_FP64 solves.  Blocking; allocates
+ * scratch for the duration of the call.  variant_out / ms_out (HOST,
+ * optional) receive the choice and its time. */
 int pent_group_autotune(pent_group g, const int64_t *batch, int *variant_out, double *ms_out,
                         void *stream);
 
-/* Force the persistent kernel variant for later mode-0 solves (tests and
- * manual tuning).  0..3: one workgroup per work item, 64/32/64/32 rows per
- * segment with 8/8/4/4 waves; 4, 5: one-wave tasks (item, segment) drawn
- * independently, 64/32 rows per segment, pass-2 tasks waiting (bounded) on
- * a per-item flag the last pass-1 task sets; 6: the single pass over all
- * matrices (pent_set_schedule kind 4 with 64-row segments, four per
- * workgroup, units of every matrix in one launch; f read once, x written
- * once), which falls back to variant 0 when the deepest 64-system tile
- * would not fit on the device at once.  PENT_INVALID_VALUE for an unknown
- * variant. */
+/* Force the kernel variant of later PENT_GROUP_FP64 solves:
+ *   0: persistent: resident workgroups take work items (matrix, 64
+ *      consecutive systems) longest first from a device counter and solve
+ *      each alone with the partitioned sweep (f read twice, x written once);
+ *      runs at any size;
+ *   1 (default): the single pass over all matrices (pent_set_schedule kind
+ *      4 with 64-row segments, four per workgroup, the units of every matrix
+ *      in one launch; f read once, x written once); falls back to variant 0
+ *      when the deepest 64-system tile would not fit on the device at once.
+ * PENT_INVALID_VALUE for an unknown variant. */
 int pent_group_set_variant(pent_group g, int variant);
 
 /* Blocking check of the group's device status after its solves: PENT_OK, or
- * PENT_TIMEOUT if a bounded wait of variants 4, 5 or 6 ran out (then results
- * of that launch are incomplete). */
+ * PENT_TIMEOUT if a bounded wait of the single pass ran out since the last
+ * check (the flag is then cleared; the values of that launch that depend on
+ * the missed carry are NaN). */
 int pent_group_check(pent_group g);
 
 /* Capture `steps` consecutive group solves (mode as above) on `stream` into
  * an executable HIP graph (one graph launch = `steps` implicit time steps).
  * `stream` must be a created stream (not the null stream).  The buffers are
- * bound first, outside the capture.  NULL on error. */
+ * bound first, outside the capture.  The graph keeps its own reference to
+ * the group's device tables of that binding, so a later rebinding, autotune
+ * or pent_group_destroy leaves it valid; F and work are the caller's and
+ * must stay alive (and keep their shapes) while the graph may launch.
+ * NULL on error. */
 typedef struct pent_graph_s *pent_graph;
 pent_graph pent_group_capture(pent_group g, double *const *F, const int64_t *batch,
                               const int64_t *ld, int mode, int steps, void *work,
                               size_t work_bytes, void *stream);
 int pent_graph_launch(pent_graph gr, void *stream);
-int pent_graph_destroy(pent_graph gr); /* NULL is a no-op */
+int pent_graph_destroy(pent_graph gr); /* NULL is a no-op; no launch of gr may still run */
 
 /* ------------------------------------------ 2-D Cahn-Hilliard workload --
  * Split-implicit step of the 2-D Cahn-Hilliard equation on ninst independent
@@ -328,7 +363,9 @@ int64_t pent_size(pent_handle h); /* n, or -1 for a bad handle */
  *           64 rows) for n >= 1024 when a tile of its blocks fits on the
  *           device, else the partitioned form (kind 2);
  *   kind 1: one lane per system, both sweeps in one kernel (the paper's
- *           one-thread-per-system schedule, Sec. 2.4 last paragraph);
+ *           one-thread-per-system schedule, Sec. 2.4 last paragraph), rows
+ *           prefetched seg_rows at a time (the prefetch depth: 8, 16 or 32;
+ *           0 means 16);
  *   kind 2: partitioned: seg_rows consecutive rows per lane, several lanes
  *           per system, with a reduced interface recurrence between the
  *           segments (seg_rows in {16, 32, 64});
@@ -350,26 +387,43 @@ int64_t pent_size(pent_handle h); /* n, or -1 for a bad handle */
  * Returns PENT_INVALID_VALUE for an unknown kind or seg_rows. */
 int pent_set_schedule(pent_handle h, int kind, int seg_rows);
 
-/* Blocking check of the handle's error word: PENT_TIMEOUT if a single-pass
- * solve (kind 4) on this handle gave up a wait since the last check (the
- * word is then cleared), else PENT_OK. */
+/* Blocking check of the handle's status word since the last check (then
+ * cleared): PENT_TIMEOUT if a single-pass solve on this handle gave up a
+ * wait (the values that depend on the missed carry are NaN), else
+ * PENT_NOT_CONVERGED if a refined solve missed the tolerance set by
+ * pent_set_refine_tolerance, else PENT_OK. */
 int pent_check(pent_handle h);
 
 /* Autotune the schedule of this handle for `batch` systems: one lane per
- * system, partitioned with 16/32/64 rows per lane, and (n <= 4096) the
- * resident tile are timed on a scratch buffer of n x batch (allocated and
- * freed here) and the fastest is set as the handle's schedule (for every
- * later batch size).  Results are kept per process for (n, batch) and
- * appended to the text file named by the environment variable
- * PENT_TUNE_CACHE, which later processes read back.  Blocking.  kind_out,
- * seg_rows_out, ms_out (HOST, optional) receive the choice and its time. */
+ * system at prefetch depths 8/16/32, partitioned with 16/32/64 rows per
+ * lane, (n <= 4096) the resident tile, and the single pass with 32/64-row
+ * segments are timed on a scratch buffer of n x batch (allocated and freed
+ * here) and the fastest is set as the handle's schedule (for every later
+ * batch size).  Results are kept per process, keyed by (device
+ * architecture, n, batch, element type), and appended to the text file named
+ * by the environment variable PENT_TUNE_CACHE, which later processes read
+ * back (a line measured on another architecture is never used).  Blocking.
+ * kind_out, seg_rows_out, ms_out (HOST, optional) receive the choice and its
+ * time. */
 int pent_autotune(pent_handle h, int64_t batch, int *kind_out, int *seg_rows_out, double *ms_out,
                   void *stream);
 
 /* The schedule pent_solve would use for `batch` systems on this handle
- * (kind as above, seg_rows 0 unless kind is 2 or 4).  Host-only, no HIP
- * call. */
+ * (kind as above; seg_rows is the segment height for kinds 2 and 4, the
+ * prefetch depth for kind 1, 0 for kind 3).  Host-only, no HIP call. */
 int pent_query_schedule(pent_handle h, int64_t batch, int *kind, int *seg_rows);
+
+/* ---------------------------------------------------------- measurement --
+ * The copy ceiling of the batch-fastest single pass: dst = src for an
+ * (n x batch) block (DEVICE FP64, element (i, j) at src[i*ld_src + j] and
+ * dst[i*ld_dst + j]; src == dst with equal ld is an in-place copy), moved
+ * exactly as the single pass moves its right-hand sides (64 systems x 64
+ * rows per wave, one 512-byte row segment per load, four waves down the
+ * rows per workgroup) with no arithmetic and no exchange.  Its bandwidth is
+ * what a solve on that layout can at best reach (Sec. 2.6 layout; the
+ * measurement behind the roofline fractions).  Asynchronous on `stream`. */
+int pent_stream_copy(const double *src, int64_t ld_src, double *dst, int64_t ld_dst, int64_t n,
+                     int64_t batch, void *stream);
 
 /* --------------------------------------------------------------- status -- */
 int pent_last_status(void);

@@ -26,7 +26,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pent_oracle.c")
-_LIB_PATH = os.path.join(_HERE, "_pent_oracle.so")
+# PENT_ORACLE_LIB names another build of the same source (the sanitizer job's)
+_LIB_PATH = os.environ.get("PENT_ORACLE_LIB") or os.path.join(_HERE, "_pent_oracle.so")
 _lib = None
 
 OK, INVALID, ZERO_PIVOT = 0, 1, 2

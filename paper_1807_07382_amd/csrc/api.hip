@@ -6,7 +6,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <new>
+#include <string>
 #include <tuple>
 
 #include "internal.h"
@@ -68,6 +70,7 @@ pent_plan *new_plan(int64_t n, int *st)
     p->d_bwd = nullptr;
     p->sched_kind = 0;
     p->sched_seg = 0;
+    p->refine_tol = 0.0;
     p->d_scan = nullptr;
     p->d_trec = nullptr;
     p->scan_rows = 0;
@@ -100,19 +103,39 @@ void query_onepass_cap(pent_plan *p, int seg_rows)
     if (cap == 0) cap = onepass_capacity(seg_rows);
 }
 
-// Factor the diagonals already in p->d_diag; blocks.  Consumes p on error.
+const SegRec *seg_cache_locked(pent_plan *p, int seg_rows, int *st, bool sync);
+bool tile_cache(pent_plan *p, int rows, const ScanRec **scan, const double **trec, int *st,
+                bool sync);
+
+// Factor the diagonals already in p->d_diag and build the per-schedule
+// tables of the automatic schedule (segment constants for 64- and 32-row
+// segments, and the resident tile's tables where n allows it), all on the
+// null stream, then synchronise once to read the pivot check.  Later solves
+// with the automatic schedule then allocate nothing for these tables.
+// Consumes p on error.
 pent_handle finish_factor(pent_plan *p)
 {
     int64_t *d_bad = nullptr;
     int64_t bad = -1;
+    int st = PENT_OK;
     hipError_t e = hipMalloc(&d_bad, sizeof(int64_t));
     if (e == hipSuccess) e = launch_factor(p->d_diag, p->n, p->npad, p->d_fac, p->d_fwd, p->d_bwd, d_bad, 0);
     if (e == hipSuccess) e = launch_anorm(p->d_diag, p->n, p->d_anorm, 0);
+    if (e == hipSuccess) {
+        std::lock_guard<std::mutex> lk(p->mu);
+        if (!seg_cache_locked(p, 64, &st, false) || !seg_cache_locked(p, 32, &st, false))
+            e = hipErrorUnknown;
+    }
+    if (e == hipSuccess && tile_rows_for(p->n) > 0) {
+        const ScanRec *sc;
+        const double *tr;
+        if (!tile_cache(p, tile_rows_for(p->n), &sc, &tr, &st, false)) e = hipErrorUnknown;
+    }
     if (e == hipSuccess) e = hipMemcpy(&bad, d_bad, sizeof(int64_t), hipMemcpyDeviceToHost);
     if (d_bad) (void)hipFree(d_bad);
     if (e != hipSuccess) {
         free_plan(p);
-        ret(hip_status(e));
+        ret(st != PENT_OK ? st : hip_status(e));
         return nullptr;
     }
     if (bad >= 0) {
@@ -130,7 +153,7 @@ pent_handle finish_factor(pent_plan *p)
 // Per-segment constants for seg_rows, built once per handle on first use.
 // The build runs on the null stream and synchronises it, so later solves on
 // any stream see the finished constants.
-const SegRec *seg_cache_locked(pent_plan *p, int seg_rows, int *st)
+const SegRec *seg_cache_locked(pent_plan *p, int seg_rows, int *st, bool sync = true)
 {
     int slot = seg_rows == 16 ? 0 : seg_rows == 32 ? 1 : 2;
     SegCache &c = p->seg[slot];
@@ -146,7 +169,7 @@ const SegRec *seg_cache_locked(pent_plan *p, int seg_rows, int *st)
     hipError_t e = hipMalloc(&d, sizeof(SegRec) * nalloc);
     if (e == hipSuccess) e = hipMemset(d, 0, sizeof(SegRec) * nalloc);
     if (e == hipSuccess) e = launch_seg_prep(p->d_fwd, p->d_bwd, p->n, seg_rows, d, 0);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e == hipSuccess && sync) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         if (d) (void)hipFree(d);
         *st = hip_status(e);
@@ -167,11 +190,12 @@ const SegRec *seg_cache(pent_plan *p, int seg_rows, int *st)
 
 // Interface-scan constants and record image of the resident-tile schedule
 // (built once per handle).
-bool tile_cache(pent_plan *p, int rows, const ScanRec **scan, const double **trec, int *st)
+bool tile_cache(pent_plan *p, int rows, const ScanRec **scan, const double **trec, int *st,
+                bool sync = true)
 {
     std::lock_guard<std::mutex> lk(p->mu);
     if (!(p->d_scan && p->scan_rows == rows)) {
-        const SegRec *seg = seg_cache_locked(p, rows, st);
+        const SegRec *seg = seg_cache_locked(p, rows, st, sync);
         if (!seg) return false;
         ScanRec *d = nullptr;
         double *t = nullptr;
@@ -179,7 +203,7 @@ bool tile_cache(pent_plan *p, int rows, const ScanRec **scan, const double **tre
         if (e == hipSuccess) e = hipMalloc(&t, sizeof(double) * tile_recs_doubles(rows));
         if (e == hipSuccess) e = launch_scan_prep(seg, (p->n + rows - 1) / rows, d, 0);
         if (e == hipSuccess) e = launch_tile_recs(p->d_fwd, p->d_bwd, rows, t, 0);
-        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e == hipSuccess && sync) e = hipDeviceSynchronize();
         if (e != hipSuccess) {
             if (d) (void)hipFree(d);
             if (t) (void)hipFree(t);
@@ -252,7 +276,11 @@ void io_schedule(const pent_plan *p, int64_t batch, bool inplace64, int *kind, i
             onepass_units(p->n, *seg_rows, batch) > (int64_t)UINT32_MAX / 2)
             *kind = 2;
     }
-    if (*kind == 2 && (p->n + *seg_rows - 1) / *seg_rows > 65535) *kind = 1;
+    if (*kind == 2 && (p->n + *seg_rows - 1) / *seg_rows > 65535) {
+        *kind = 1;
+        *seg_rows = 16;
+    }
+    if (*kind == 1 && *seg_rows != 8 && *seg_rows != 32) *seg_rows = 16;  // prefetch depth
     if (*kind == 1 && !inplace64) {
         *kind = 2;
         *seg_rows = 64;
@@ -267,7 +295,8 @@ int solve_io(pent_plan *h, const void *f, bool f32, int64_t ldf, double *x, int6
     const bool inplace64 = !f32 && (const void *)x == f && ldx == ldf;
     int kind, seg_rows, st;
     io_schedule(h, batch, inplace64, &kind, &seg_rows);
-    if (kind == 1) return hip_status(launch_lane_sweep(h->d_fwd, h->d_bwd, h->n, x, batch, ldx, s));
+    if (kind == 1)
+        return hip_status(launch_lane_sweep(h->d_fwd, h->d_bwd, h->n, x, batch, ldx, seg_rows, s));
     if (kind == 3) {
         const int rows = tile_rows_for(h->n);
         const ScanRec *scan;
@@ -307,6 +336,72 @@ int solve_io_scratch(pent_plan *h, const double *f, int64_t ldf, double *x, int6
 
 constexpr int kMaxRefine = 16;
 
+// Workspace of pent_solve_mixed: single-pass / partitioned scratch, the
+// correction buffer r (three-kernel corrections only) and the backward-error
+// accumulators (when eta is asked for or a tolerance is set).
+struct MixedLayout {
+    size_t summ = 0, r = 0, acc = 0;
+    bool fused = false;  // corrections run as the fused single pass
+    size_t total() const { return summ + r + acc; }
+};
+
+MixedLayout mixed_layout(pent_plan *h, int64_t batch, bool inplace64, int refine_steps, bool want_eta)
+{
+    MixedLayout L;
+    int kind, seg_rows;
+    io_schedule(h, batch, inplace64, &kind, &seg_rows);
+    L.summ = summ_bytes(h, kind, seg_rows, batch);
+    if (refine_steps > 0) {
+        if (kind == 4) {
+            if (h->fix_cap == 0) h->fix_cap = onepass_fix_capacity();
+            L.fused = h->fix_cap > 0 && onepass_fix_groups(h->n) <= h->fix_cap / 4 &&
+                      onepass_fix_scratch_bytes(h->n, batch) <= L.summ;
+        }
+        if (!L.fused) L.r = align256(sizeof(double) * (size_t)h->n * batch);
+    }
+    if (want_eta || h->refine_tol > 0.0) L.acc = align256(sizeof(unsigned long long) * 3 * (size_t)batch);
+    return L;
+}
+
+}  // namespace
+
+namespace {
+
+// Device tables of one binding of a group: the buffer table, the work list
+// of the persistent kernel and the unit table of the single pass.  Shared by
+// the group and by every graph captured from that binding and freed when
+// the last of them lets go, so rebinding or destroying the group never
+// pulls them from under a graph that still launches kernels reading them.
+struct GroupTables {
+    GroupMat *d_mats = nullptr;
+    GroupItem *d_items = nullptr;
+    GroupUnit *d_units = nullptr;
+    int nitems = 0;
+    int64_t nunits = 0;
+    int64_t max_groups = 0;    // deepest tile of the single pass, in units
+    GroupTables() = default;
+    GroupTables(const GroupTables &) = delete;
+    GroupTables &operator=(const GroupTables &) = delete;
+    ~GroupTables()
+    {
+        for (void *q : {(void *)d_mats, (void *)d_items, (void *)d_units})
+            if (q) (void)hipFree(q);
+    }
+};
+
+// The group's device words [next item, workgroups done, wait timed out],
+// shared the same way (the kernels of a captured graph use them).
+struct GroupCounters {
+    unsigned int *d_ctr = nullptr;
+    GroupCounters() = default;
+    GroupCounters(const GroupCounters &) = delete;
+    GroupCounters &operator=(const GroupCounters &) = delete;
+    ~GroupCounters()
+    {
+        if (d_ctr) (void)hipFree(d_ctr);
+    }
+};
+
 }  // namespace
 
 struct pent_group_s {
@@ -317,26 +412,17 @@ struct pent_group_s {
     bool bound = false;
     std::vector<double *> F;
     std::vector<int64_t> batch, ld;
-    GroupMat *d_mats = nullptr;
-    GroupItem *d_items = nullptr;
-    int nitems = 0;
-    int64_t summ_doubles = 0;
-    unsigned int *d_ctr = nullptr;  // [next item/task, workgroups done, wait timed out]
-    int2 *d_tasks64 = nullptr;      // (item, segment) task lists of the decoupled variants
-    int2 *d_tasks32 = nullptr;
-    int ntasks64 = 0, ntasks32 = 0;
-    unsigned int *d_cnt = nullptr;  // per-item pass-1 completion count
-    unsigned int *d_ready = nullptr;  // per-item interface-ready flag
-    GroupUnit *d_units = nullptr;   // single-pass unit table (variant 6)
-    int64_t nunits = 0;
-    int64_t max_groups = 0;         // deepest tile of the single pass, in units
-    int onepass_cap = 0;            // co-resident single-pass workgroups (0: unknown)
-    int variant = 0;                // group kernel variant (autotuned)
+    std::shared_ptr<GroupTables> tabs;
+    std::shared_ptr<GroupCounters> ctr;
+    int onepass_cap = 0;  // co-resident single-pass workgroups (0: not yet queried)
+    int variant = 1;      // group kernel variant (pent_group_set_variant / autotune)
 };
 
 struct pent_graph_s {
     uint64_t magic = 0;
     hipGraphExec_t exec = nullptr;
+    std::shared_ptr<GroupTables> tabs;  // kept alive while the graph exists
+    std::shared_ptr<GroupCounters> ctr;
 };
 
 struct pent_cyclic_s {
@@ -496,20 +582,14 @@ int cyc_run_single(pent_cyclic c, bool cn, const double *F, int64_t ldf, double 
 void free_group(pent_group g)
 {
     if (!g) return;
-    if (g->d_mats) (void)hipFree(g->d_mats);
-    if (g->d_items) (void)hipFree(g->d_items);
-    if (g->d_ctr) (void)hipFree(g->d_ctr);
-    if (g->d_tasks64) (void)hipFree(g->d_tasks64);
-    if (g->d_tasks32) (void)hipFree(g->d_tasks32);
-    if (g->d_cnt) (void)hipFree(g->d_cnt);
-    if (g->d_ready) (void)hipFree(g->d_ready);
-    if (g->d_units) (void)hipFree(g->d_units);
+    g->tabs.reset();  // graphs captured from the group keep their own references
+    g->ctr.reset();
     g->magic = 0;
     delete g;
 }
 
 // Workspace of the persistent solve for these counts (doubles of segment
-// summaries, counted for 64-row segments; the 32-row variants use twice that).
+// summaries, 64-row segments).
 int64_t group_summ_doubles(const pent_group g, const int64_t *batch)
 {
     int64_t tot = 0;
@@ -517,11 +597,15 @@ int64_t group_summ_doubles(const pent_group g, const int64_t *batch)
         const int64_t nseg = (g->plans[k]->n + 63) / 64;
         tot += (batch[k] + 63) / 64 * nseg * 256;
     }
-    return 2 * tot;
+    return tot;
 }
 
-constexpr int kGroupOnepassVariant = 6;  // the single pass over all matrices
-int group_variant_count() { return group_variants() + 1; }
+// Group kernel variants: 0 the persistent kernel (group.hip), 1 the single
+// pass over all matrices (onepass.hip).
+constexpr int kGroupPersistent = 0, kGroupOnepass = 1, kGroupVariants = 2;
+
+// Group solve modes (pent_group_solve).
+constexpr int kModeFP64 = 0, kModeMixed = 1, kModePerMatrix = 2;
 
 int64_t group_onepass_units(const pent_group g, const int64_t *batch)
 {
@@ -537,8 +621,8 @@ int64_t group_onepass_units(const pent_group g, const int64_t *batch)
 bool group_onepass_ok(pent_group g)
 {
     if (g->onepass_cap == 0) g->onepass_cap = group_onepass_capacity();
-    return g->onepass_cap > 0 && g->max_groups <= g->onepass_cap / 4 &&
-           g->nunits <= (int64_t)UINT32_MAX / 2;
+    return g->tabs && g->onepass_cap > 0 && g->tabs->max_groups <= g->onepass_cap / 4 &&
+           g->tabs->nunits <= (int64_t)UINT32_MAX / 2;
 }
 
 size_t group_ws_bytes(const pent_group g, const int64_t *batch)
@@ -555,7 +639,8 @@ size_t group_ws_bytes(const pent_group g, const int64_t *batch)
 
 // Upload the buffer table and the sorted work list if anything changed.
 // Blocking; also builds every per-matrix cache a later solve could need, so
-// the solves themselves never synchronise (graph capture).
+// the solves themselves never synchronise (graph capture).  The new tables
+// replace the group's; graphs captured earlier keep the old ones.
 int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64_t *ld)
 {
     const size_t cnt = g->plans.size();
@@ -570,17 +655,15 @@ int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64
         pent_plan *p = g->plans[k];
         const SegRec *seg64 = seg_cache(p, 64, &st);
         if (!seg64) return st;
-        const SegRec *seg32 = seg_cache(p, 32, &st);
-        if (!seg32) return st;
         int kind, seg_rows;
         io_schedule(p, batch[k], true, &kind, &seg_rows);
-        if (kind == 2 && !seg_cache(p, seg_rows, &st)) return st;
+        if ((kind == 2 || kind == 4) && !seg_cache(p, seg_rows, &st)) return st;
         if (kind == 3) {
             const ScanRec *sc;
             const double *tr;
             if (!tile_cache(p, tile_rows_for(p->n), &sc, &tr, &st)) return st;
         }
-        mats[k] = GroupMat{p->d_fwd, p->d_bwd, seg64, seg32, F[k], p->n, p->npad, ld[k], batch[k]};
+        mats[k] = GroupMat{p->d_fwd, p->d_bwd, seg64, F[k], p->n, p->npad, ld[k], batch[k]};
     }
     for (size_t k = 0; k < cnt; k++)
         for (int64_t c0 = 0; c0 < batch[k]; c0 += 64)
@@ -595,14 +678,6 @@ int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64
         off += (mats[it.mat].n + 63) / 64 * 256;
     }
     if (items.size() > (size_t)INT32_MAX / 2) return PENT_NOT_SUPPORTED;
-    // task lists of the decoupled variants, items in work-list order
-    std::vector<int2> t64, t32;
-    for (size_t i = 0; i < items.size(); i++) {
-        const int64_t n = mats[items[i].mat].n;
-        for (int64_t sg = 0; sg < (n + 63) / 64; sg++) t64.push_back(make_int2((int)i, (int)sg));
-        for (int64_t sg = 0; sg < (n + 31) / 32; sg++) t32.push_back(make_int2((int)i, (int)sg));
-    }
-    if (t32.size() > (size_t)INT32_MAX / 2) return PENT_NOT_SUPPORTED;
     // unit table of the single pass: every item's row groups, consecutive;
     // items with the longest chains of groups (largest n) first, then the
     // widest (measured ~1% faster than the work-list order, whose per-item
@@ -624,54 +699,22 @@ int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64
         for (int64_t q = 0; q < ng; q++)
             units.push_back(GroupUnit{items[i].mat, (int)q, (int)ng, 0, items[i].col0, u0});
     }
-    GroupMat *dm = nullptr;
-    GroupItem *di = nullptr;
-    int2 *d64 = nullptr, *d32 = nullptr;
-    unsigned int *dc = nullptr, *dr = nullptr;
-    GroupUnit *du = nullptr;
-    const size_t ni = std::max<size_t>(items.size(), 1);
-    hipError_t e = hipMalloc(&dm, sizeof(GroupMat) * std::max<size_t>(cnt, 1));
-    if (e == hipSuccess) e = hipMalloc(&di, sizeof(GroupItem) * ni);
-    if (e == hipSuccess) e = hipMalloc(&d64, sizeof(int2) * std::max<size_t>(t64.size(), 1));
-    if (e == hipSuccess) e = hipMalloc(&d32, sizeof(int2) * std::max<size_t>(t32.size(), 1));
-    if (e == hipSuccess) e = hipMalloc(&dc, sizeof(unsigned int) * ni);
-    if (e == hipSuccess) e = hipMalloc(&dr, sizeof(unsigned int) * ni);
-    if (e == hipSuccess) e = hipMalloc(&du, sizeof(GroupUnit) * std::max<size_t>(units.size(), 1));
+    auto t = std::make_shared<GroupTables>();
+    hipError_t e = hipMalloc(&t->d_mats, sizeof(GroupMat) * std::max<size_t>(cnt, 1));
+    if (e == hipSuccess) e = hipMalloc(&t->d_items, sizeof(GroupItem) * std::max<size_t>(items.size(), 1));
+    if (e == hipSuccess) e = hipMalloc(&t->d_units, sizeof(GroupUnit) * std::max<size_t>(units.size(), 1));
     if (e == hipSuccess && !units.empty())
-        e = hipMemcpy(du, units.data(), sizeof(GroupUnit) * units.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess && cnt) e = hipMemcpy(dm, mats.data(), sizeof(GroupMat) * cnt, hipMemcpyHostToDevice);
+        e = hipMemcpy(t->d_units, units.data(), sizeof(GroupUnit) * units.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && cnt)
+        e = hipMemcpy(t->d_mats, mats.data(), sizeof(GroupMat) * cnt, hipMemcpyHostToDevice);
     if (e == hipSuccess && !items.empty())
-        e = hipMemcpy(di, items.data(), sizeof(GroupItem) * items.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !t64.empty())
-        e = hipMemcpy(d64, t64.data(), sizeof(int2) * t64.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess && !t32.empty())
-        e = hipMemcpy(d32, t32.data(), sizeof(int2) * t32.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_zero_u32(dc, (int)ni, 0);
-    if (e == hipSuccess) e = launch_zero_u32(dr, (int)ni, 0);
+        e = hipMemcpy(t->d_items, items.data(), sizeof(GroupItem) * items.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e != hipSuccess) {
-        for (void *q : {(void *)dm, (void *)di, (void *)d64, (void *)d32, (void *)dc, (void *)dr,
-                        (void *)du})
-            if (q) (void)hipFree(q);
-        return hip_status(e);
-    }
-    for (void *q : {(void *)g->d_mats, (void *)g->d_items, (void *)g->d_tasks64,
-                    (void *)g->d_tasks32, (void *)g->d_cnt, (void *)g->d_ready,
-                    (void *)g->d_units})
-        if (q) (void)hipFree(q);
-    g->d_units = du;
-    g->nunits = (int64_t)units.size();
-    g->max_groups = max_groups;
-    g->d_mats = dm;
-    g->d_items = di;
-    g->d_tasks64 = d64;
-    g->d_tasks32 = d32;
-    g->ntasks64 = (int)t64.size();
-    g->ntasks32 = (int)t32.size();
-    g->d_cnt = dc;
-    g->d_ready = dr;
-    g->nitems = (int)items.size();
-    g->summ_doubles = 2 * off;
+    if (e != hipSuccess) return hip_status(e);  // t frees what it holds
+    t->nitems = (int)items.size();
+    t->nunits = (int64_t)units.size();
+    t->max_groups = max_groups;
+    g->tabs = std::move(t);
     g->F.assign(F, F + cnt);
     g->batch.assign(batch, batch + cnt);
     g->ld.assign(ld, ld + cnt);
@@ -682,23 +725,16 @@ int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64
 // Enqueue one group solve of the bound buffers (no synchronisation).
 int group_enqueue(pent_group g, int mode, void *work, hipStream_t s)
 {
-    if (mode == 0) {
-        if (g->nitems == 0) return PENT_OK;
-        int v = g->variant;
-        if (v == kGroupOnepassVariant) {
-            if (group_onepass_ok(g))
-                return hip_status(launch_group_onepass(g->d_mats, g->d_units, g->nunits, work,
-                                                       &g->d_ctr[2], s));
-            v = 0;  // a tile too deep for the device: the persistent kernel
-        }
-        const bool tasks = group_variant_is_tasks(v);
-        const bool k64 = group_variant_seg_rows(v) == 64;
-        const int ntasks = k64 ? g->ntasks64 : g->ntasks32;
-        const int units = tasks ? 2 * ntasks : g->nitems;
-        const int nblocks = std::max(1, std::min(units, group_max_blocks(v)));
-        return hip_status(launch_group(v, g->d_mats, g->d_items, g->nitems,
-                                       k64 ? g->d_tasks64 : g->d_tasks32, ntasks, (double *)work,
-                                       g->d_ctr, g->d_cnt, g->d_ready, nblocks, s));
+    if (mode == kModeFP64) {
+        const GroupTables &t = *g->tabs;
+        if (t.nitems == 0) return PENT_OK;
+        if (g->variant == kGroupOnepass && group_onepass_ok(g))
+            return hip_status(launch_group_onepass(t.d_mats, t.d_units, t.nunits, work,
+                                                   &g->ctr->d_ctr[2], s));
+        // the persistent kernel (chosen, or a tile too deep for the single pass)
+        const int nblocks = std::max(1, std::min(t.nitems, group_max_blocks()));
+        return hip_status(launch_group(t.d_mats, t.d_items, t.nitems, (double *)work, g->ctr->d_ctr,
+                                       nblocks, s));
     }
     for (size_t k = 0; k < g->plans.size(); k++) {
         if (g->batch[k] == 0) continue;
@@ -710,11 +746,23 @@ int group_enqueue(pent_group g, int mode, void *work, hipStream_t s)
 }
 
 // ---- autotuning ----
-// Results are kept per process, keyed by (n, batch), and optionally in a text
-// file named by PENT_TUNE_CACHE ("n batch kind seg_rows ms" per line).
+// Results are kept per process, keyed by (device architecture, n, batch,
+// element type of the solve), and optionally in a text file named by
+// PENT_TUNE_CACHE ("arch n batch dtype kind seg_rows ms" per line), so a
+// choice measured on one device or element type is never applied to another.
+using TuneKey = std::tuple<std::string, int64_t, int64_t, int>;
 std::mutex g_tune_mu;
-std::map<std::pair<int64_t, int64_t>, std::tuple<int, int, double>> g_tune;
+std::map<TuneKey, std::tuple<int, int, double>> g_tune;
 bool g_tune_loaded = false;
+
+std::string device_arch(int dev)
+{
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a(prop.gcnArchName);
+    const size_t colon = a.find(':');  // drop feature suffixes (":sramecc+:xnack-")
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
 
 void tune_load_locked()
 {
@@ -724,22 +772,27 @@ void tune_load_locked()
     if (!path) return;
     FILE *f = std::fopen(path, "r");
     if (!f) return;
+    char line[512], arch[128];
     long long n, b;
-    int kind, seg;
+    int dt, kind, seg;
     double ms;
-    while (std::fscanf(f, "%lld %lld %d %d %lf", &n, &b, &kind, &seg, &ms) == 5)
-        g_tune[{n, b}] = std::make_tuple(kind, seg, ms);
+    while (std::fgets(line, sizeof(line), f)) {
+        if (std::sscanf(line, "%127s %lld %lld %d %d %d %lf", arch, &n, &b, &dt, &kind, &seg, &ms) == 7)
+            g_tune[TuneKey{arch, n, b, dt}] = std::make_tuple(kind, seg, ms);
+    }
     std::fclose(f);
 }
 
-void tune_store_locked(int64_t n, int64_t b, int kind, int seg, double ms)
+void tune_store_locked(const TuneKey &key, int kind, int seg, double ms)
 {
-    g_tune[{n, b}] = std::make_tuple(kind, seg, ms);
+    g_tune[key] = std::make_tuple(kind, seg, ms);
     const char *path = std::getenv("PENT_TUNE_CACHE");
     if (!path) return;
     FILE *f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%lld %lld %d %d %.6f\n", (long long)n, (long long)b, kind, seg, ms);
+    std::fprintf(f, "%s %lld %lld %d %d %d %.6f\n", std::get<0>(key).c_str(),
+                 (long long)std::get<1>(key), (long long)std::get<2>(key), std::get<3>(key), kind,
+                 seg, ms);
     std::fclose(f);
 }
 
@@ -781,11 +834,15 @@ int time_ms(Fn fn, hipStream_t s, int reps, double *ms)
 int group_check_args(pent_group g, double *const *F, const int64_t *batch, const int64_t *ld,
                      int mode)
 {
-    if (!gvalid(g) || !batch || !ld || (mode != 0 && mode != 1)) return PENT_INVALID_VALUE;
+    if (!gvalid(g) || !batch || !ld || mode < kModeFP64 || mode > kModePerMatrix)
+        return PENT_INVALID_VALUE;
     for (size_t k = 0; k < g->plans.size(); k++) {
         if (!valid(g->plans[k]) || batch[k] < 0 || ld[k] < batch[k]) return PENT_INVALID_VALUE;
         if (batch[k] > 0 && (!F || !F[k])) return PENT_INVALID_VALUE;
     }
+    // the mixed group solve: a time-stepping state is the FP64 solution of
+    // the previous step, so there is no FP32 stream to save bytes on
+    if (mode == kModeMixed) return PENT_NOT_SUPPORTED;
     return PENT_OK;
 }
 
@@ -869,19 +926,20 @@ int pent_solve(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream
     return ret(solve_io_scratch(h, F, ld, F, ld, batch, (hipStream_t)stream));
 }
 
-size_t pent_mixed_workspace_size(pent_handle h, int64_t batch, int refine_steps, int want_eta)
+size_t pent_mixed_workspace_size_ex(pent_handle h, int64_t batch, int refine_steps, int want_eta)
 {
     if (!valid(h) || batch < 0 || refine_steps < 0 || refine_steps > kMaxRefine) {
         ret(PENT_INVALID_VALUE);
         return 0;
     }
-    int kind, seg_rows;
-    io_schedule(h, batch, false, &kind, &seg_rows);
-    size_t b = summ_bytes(h, kind, seg_rows, batch);
-    if (refine_steps > 0) b += align256(sizeof(double) * (size_t)h->n * batch);
-    if (want_eta) b += align256(sizeof(unsigned long long) * 3 * (size_t)batch);
+    const MixedLayout L = mixed_layout(h, batch, false, refine_steps, want_eta != 0);
     ret(PENT_OK);
-    return b;
+    return L.total();
+}
+
+size_t pent_mixed_workspace_size(pent_handle h, int64_t batch)
+{
+    return pent_mixed_workspace_size_ex(h, batch, kMaxRefine, 1);
 }
 
 int pent_solve_mixed(pent_handle h, const void *f, int f_dtype, int64_t ld_f, double *x,
@@ -897,50 +955,44 @@ int pent_solve_mixed(pent_handle h, const void *f, int f_dtype, int64_t ld_f, do
     const bool alias = (const void *)x == f;
     if (alias && (f32 || ld_x != ld_f || refine_steps > 0)) return ret(PENT_INVALID_VALUE);
     if (h->n > (int64_t)65535 * 32) return ret(PENT_NOT_SUPPORTED);
-    int kind, seg_rows;
-    io_schedule(h, batch, alias, &kind, &seg_rows);
-    const size_t b_summ = summ_bytes(h, kind, seg_rows, batch);
-    const size_t b_r = refine_steps > 0 ? align256(sizeof(double) * (size_t)h->n * batch) : 0;
-    const size_t b_acc = eta_out ? align256(sizeof(unsigned long long) * 3 * (size_t)batch) : 0;
-    const size_t need = b_summ + b_r + b_acc;
-    if (need > 0 && (!work || work_bytes < need)) return ret(need > 0 && work ? PENT_SIZE_MISMATCH : PENT_INVALID_VALUE);
+    const MixedLayout L = mixed_layout(h, batch, alias, refine_steps, eta_out != nullptr);
+    const size_t need = L.total();
+    if (need > 0 && (!work || work_bytes < need)) return ret(work ? PENT_SIZE_MISMATCH : PENT_INVALID_VALUE);
     char *w = (char *)work;
     void *summ = w;
-    double *r = (double *)(w + b_summ);
-    unsigned long long *acc = (unsigned long long *)(w + b_summ + b_r);
+    double *r = (double *)(w + L.summ);
+    unsigned long long *acc = (unsigned long long *)(w + L.summ + L.r);
     hipStream_t s = (hipStream_t)stream;
 
     int st = solve_io(h, f, f32, ld_f, x, ld_x, batch, summ, s);
     if (st != PENT_OK) return ret(st);
-    // Corrections: where the solve ran as a single pass, each correction is
-    // one fused pass too (residual, solve and update of x in one kernel),
-    // if a tile of it fits on the device and the scratch is large enough;
-    // else residual, solve, x += d.
-    if (refine_steps > 0 && kind == 4) {
-        if (h->fix_cap == 0) h->fix_cap = onepass_fix_capacity();
-        const SegRec *seg64 = nullptr;
-        if (h->fix_cap > 0 && onepass_fix_groups(h->n) <= h->fix_cap / 4 &&
-            onepass_fix_scratch_bytes(h->n, batch) <= b_summ + b_r &&
-            (seg64 = seg_cache(h, 64, &st)) != nullptr) {
-            for (int it = 0; it < refine_steps; it++) {
-                hipError_t e = launch_onepass_fix(h->d_fwd, h->d_bwd, seg64, h->d_diag, h->n, f, f32,
-                                                  ld_f, x, ld_x, batch, summ, h->d_err, s);
-                if (e != hipSuccess) return ret(hip_status(e));
-            }
-            refine_steps = 0;
+    // Corrections: where the solve ran as a single pass and a tile of the
+    // fused correction fits on the device, each correction is one fused pass
+    // too (residual, solve and update of x in one kernel); else residual,
+    // solve, x += d.
+    if (refine_steps > 0 && L.fused) {
+        const SegRec *seg64 = seg_cache(h, 64, &st);
+        if (!seg64) return ret(st);
+        for (int it = 0; it < refine_steps; it++) {
+            hipError_t e = launch_onepass_fix(h->d_fwd, h->d_bwd, seg64, h->d_diag, h->n, f, f32, ld_f,
+                                              x, ld_x, batch, summ, h->d_err, s);
+            if (e != hipSuccess) return ret(hip_status(e));
+        }
+    } else {
+        for (int it = 0; it < refine_steps; it++) {
+            hipError_t e = launch_residual(h->d_diag, h->n, f, f32, ld_f, x, ld_x, r, batch, batch, s);
+            if (e != hipSuccess) return ret(hip_status(e));
+            st = solve_io(h, r, false, batch, r, batch, batch, summ, s);
+            if (st != PENT_OK) return ret(st);
+            e = launch_axpy(x, ld_x, r, batch, h->n, batch, s);
+            if (e != hipSuccess) return ret(hip_status(e));
         }
     }
-    for (int it = 0; it < refine_steps; it++) {
-        hipError_t e = launch_residual(h->d_diag, h->n, f, f32, ld_f, x, ld_x, r, batch, batch, s);
-        if (e != hipSuccess) return ret(hip_status(e));
-        st = solve_io(h, r, false, batch, r, batch, batch, summ, s);
-        if (st != PENT_OK) return ret(st);
-        e = launch_axpy(x, ld_x, r, batch, h->n, batch, s);
-        if (e != hipSuccess) return ret(hip_status(e));
-    }
-    if (eta_out) {
+    // the backward error, when asked for or when a tolerance is set (a miss
+    // sets the handle's status, reported by pent_check)
+    if (L.acc) {
         hipError_t e = launch_eta(h->d_diag, h->d_anorm, h->n, f, f32, ld_f, x, ld_x, batch, acc,
-                                  eta_out, s);
+                                  eta_out, h->refine_tol, h->d_err, s);
         if (e != hipSuccess) return ret(hip_status(e));
     }
     return ret(PENT_OK);
@@ -959,7 +1011,7 @@ int pent_backward_error(pent_handle h, const void *f, int f_dtype, int64_t ld_f,
     if (h->n > (int64_t)65535 * 32) return ret(PENT_NOT_SUPPORTED);
     return ret(hip_status(launch_eta(h->d_diag, h->d_anorm, h->n, f, f_dtype == PENT_DTYPE_FP32,
                                      ld_f, x, ld_x, batch, (unsigned long long *)work, eta_out,
-                                     (hipStream_t)stream)));
+                                     0.0, nullptr, (hipStream_t)stream)));
 }
 
 pent_group pent_group_create(const pent_handle *hs, int64_t count)
@@ -980,8 +1032,16 @@ pent_group pent_group_create(const pent_handle *hs, int64_t count)
     }
     g->plans.assign(hs, hs + count);
     hipError_t e = hipGetDevice(&g->device);
-    if (e == hipSuccess) e = hipMalloc(&g->d_ctr, 3 * sizeof(unsigned int));
-    if (e == hipSuccess) e = launch_group_init(g->d_ctr, 0);
+    try {
+        g->ctr = std::make_shared<GroupCounters>();
+        g->tabs = std::make_shared<GroupTables>();
+    } catch (const std::bad_alloc &) {
+        free_group(g);
+        ret(PENT_OUT_OF_MEMORY);
+        return nullptr;
+    }
+    if (e == hipSuccess) e = hipMalloc(&g->ctr->d_ctr, 3 * sizeof(unsigned int));
+    if (e == hipSuccess) e = launch_group_init(g->ctr->d_ctr, 0);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         free_group(g);
@@ -1026,25 +1086,31 @@ int pent_autotune(pent_handle h, int64_t batch, int *kind_out, int *seg_rows_out
 {
     if (!valid(h) || batch < 1) return ret(PENT_INVALID_VALUE);
     hipStream_t s = (hipStream_t)stream;
+    const TuneKey key{device_arch(h->device), h->n, batch, PENT_DTYPE_FP64};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_load_locked();
-        auto it = g_tune.find({h->n, batch});
+        auto it = g_tune.find(key);
         if (it != g_tune.end()) {
             h->sched_kind = std::get<0>(it->second);
             h->sched_seg = std::get<1>(it->second);
+            if (h->sched_kind == 4) query_onepass_cap(h, h->sched_seg);
             if (kind_out) *kind_out = h->sched_kind;
             if (seg_rows_out) *seg_rows_out = h->sched_seg;
             if (ms_out) *ms_out = std::get<2>(it->second);
             return ret(PENT_OK);
         }
     }
-    const int cands[7][2] = {{1, 0}, {2, 16}, {2, 32}, {2, 64}, {3, 0}, {4, 32}, {4, 64}};
+    // (kind, seg_rows): one lane per system at three prefetch depths, the
+    // partitioned sweep at three segment heights, the resident tile, the
+    // single pass at two segment heights
+    const int cands[9][2] = {{1, 8}, {1, 16}, {1, 32}, {2, 16}, {2, 32}, {2, 64}, {3, 0}, {4, 32}, {4, 64}};
     double *F = nullptr;
     void *work = nullptr;
     const size_t nF = (size_t)h->n * batch;
     size_t wbytes = 0;
-    for (const auto &c : cands) wbytes = std::max(wbytes, summ_bytes(h, c[0], c[1] ? c[1] : 64, batch));
+    for (const auto &c : cands)
+        if (c[0] != 1) wbytes = std::max(wbytes, summ_bytes(h, c[0], c[1] ? c[1] : 64, batch));
     hipError_t e = hipMalloc(&F, sizeof(double) * nF);
     if (e == hipSuccess && wbytes) e = hipMalloc(&work, wbytes);
     if (e == hipSuccess) e = fill_const(F, (int64_t)nF, 1.0, s);
@@ -1070,6 +1136,7 @@ int pent_autotune(pent_handle h, int64_t batch, int *kind_out, int *seg_rows_out
             best_seg = c[1];
         }
     }
+    (void)hipStreamSynchronize(s);
     if (F) (void)hipFree(F);
     if (work) (void)hipFree(work);
     if (st != PENT_OK) {
@@ -1081,7 +1148,7 @@ int pent_autotune(pent_handle h, int64_t batch, int *kind_out, int *seg_rows_out
     h->sched_seg = best_seg;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_store_locked(h->n, batch, best_kind, best_seg, best);
+        tune_store_locked(key, best_kind, best_seg, best);
     }
     if (kind_out) *kind_out = best_kind;
     if (seg_rows_out) *seg_rows_out = best_seg;
@@ -1110,28 +1177,37 @@ int pent_group_autotune(pent_group g, const int64_t *batch, int *variant_out, do
     const size_t wbytes = group_ws_bytes(g, batch);
     if (e == hipSuccess && wbytes) e = hipMalloc(&work, wbytes);
     int st = hip_status(e);
-    // keep the caller's binding to restore afterwards
+    // keep the caller's binding (its tables stay alive through the shared
+    // pointer) to restore afterwards
     const bool had = g->bound;
     std::vector<double *> oF = g->F;
     std::vector<int64_t> ob = g->batch, ol = g->ld;
-    if (st == PENT_OK) st = group_bind(g, F.data(), batch, ld.data());
+    std::shared_ptr<GroupTables> otabs = g->tabs;
+    if (st == PENT_OK) {
+        g->bound = false;
+        st = group_bind(g, F.data(), batch, ld.data());
+    }
     const int saved = g->variant;
     int best_v = saved;
     double best = 1e300;
-    for (int v = 0; st == PENT_OK && v < group_variant_count(); v++) {
-        if (v == kGroupOnepassVariant && !group_onepass_ok(g)) continue;
+    for (int v = 0; st == PENT_OK && v < kGroupVariants; v++) {
+        if (v == kGroupOnepass && !group_onepass_ok(g)) continue;
         g->variant = v;
         double ms = 0.0;
-        st = time_ms([&] { return group_enqueue(g, 0, work, s); }, s, 3, &ms);
+        st = time_ms([&] { return group_enqueue(g, kModeFP64, work, s); }, s, 3, &ms);
         if (st == PENT_OK && ms < best) {
             best = ms;
             best_v = v;
         }
     }
     g->variant = st == PENT_OK ? best_v : saved;
-    if (st == PENT_OK) (void)hipStreamSynchronize(s);
-    g->bound = false;  // next solve re-binds (to the caller's buffers)
-    if (had && st == PENT_OK) st = group_bind(g, oF.data(), ob.data(), ol.data());
+    (void)hipStreamSynchronize(s);
+    // back to the caller's binding, without re-uploading it
+    g->tabs = otabs;
+    g->F = oF;
+    g->batch = ob;
+    g->ld = ol;
+    g->bound = had;
     for (auto p : F)
         if (p) (void)hipFree(p);
     if (work) (void)hipFree(work);
@@ -1143,7 +1219,7 @@ int pent_group_autotune(pent_group g, const int64_t *batch, int *variant_out, do
 
 int pent_group_set_variant(pent_group g, int variant)
 {
-    if (!gvalid(g) || variant < 0 || variant >= group_variant_count()) return ret(PENT_INVALID_VALUE);
+    if (!gvalid(g) || variant < 0 || variant >= kGroupVariants) return ret(PENT_INVALID_VALUE);
     g->variant = variant;
     return ret(PENT_OK);
 }
@@ -1151,10 +1227,11 @@ int pent_group_set_variant(pent_group g, int variant)
 int pent_group_check(pent_group g)
 {
     if (!gvalid(g)) return ret(PENT_INVALID_VALUE);
-    unsigned int flags[3] = {0, 0, 0};
-    hipError_t e = hipMemcpy(flags, g->d_ctr, sizeof(flags), hipMemcpyDeviceToHost);
+    unsigned int flag = 0;
+    hipError_t e = hipMemcpy(&flag, &g->ctr->d_ctr[2], sizeof(flag), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && flag) e = hipMemset(&g->ctr->d_ctr[2], 0, sizeof(flag));
     if (e != hipSuccess) return ret(hip_status(e));
-    return ret(flags[2] ? PENT_TIMEOUT : PENT_OK);
+    return ret(flag ? PENT_TIMEOUT : PENT_OK);
 }
 
 int pent_group_destroy(pent_group g)
@@ -1185,9 +1262,17 @@ pent_graph pent_group_capture(pent_group g, double *const *F, const int64_t *bat
         ret(st);
         return nullptr;
     }
+    pent_graph gr = new (std::nothrow) pent_graph_s();
+    if (!gr) {
+        ret(PENT_OUT_OF_MEMORY);
+        return nullptr;
+    }
+    gr->tabs = g->tabs;
+    gr->ctr = g->ctr;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
+        delete gr;
         ret(hip_status(e));
         return nullptr;
     }
@@ -1203,13 +1288,8 @@ pent_graph pent_group_capture(pent_group g, double *const *F, const int64_t *bat
     if (graph) (void)hipGraphDestroy(graph);
     if (st != PENT_OK) {
         if (exec) (void)hipGraphExecDestroy(exec);
+        delete gr;
         ret(st);
-        return nullptr;
-    }
-    pent_graph gr = new (std::nothrow) pent_graph_s();
-    if (!gr) {
-        (void)hipGraphExecDestroy(exec);
-        ret(PENT_OUT_OF_MEMORY);
         return nullptr;
     }
     gr->exec = exec;
@@ -1230,7 +1310,7 @@ int pent_graph_destroy(pent_graph gr)
     if (gr->magic != kGraphMagic) return ret(PENT_INVALID_VALUE);
     (void)hipGraphExecDestroy(gr->exec);
     gr->magic = 0;
-    delete gr;
+    delete gr;  // drops its references to the tables it was captured with
     return ret(PENT_OK);
 }
 
@@ -1506,9 +1586,14 @@ int64_t pent_size(pent_handle h)
 int pent_set_schedule(pent_handle h, int kind, int seg_rows)
 {
     if (!valid(h)) return ret(PENT_INVALID_VALUE);
-    if (kind == 0 || kind == 1 || kind == 3) {
+    if (kind == 0 || kind == 3) {
         h->sched_kind = kind;
         h->sched_seg = 0;
+        return ret(PENT_OK);
+    }
+    if (kind == 1 && (seg_rows == 0 || seg_rows == 8 || seg_rows == 16 || seg_rows == 32)) {
+        h->sched_kind = 1;
+        h->sched_seg = seg_rows == 0 ? 16 : seg_rows;  // prefetch depth
         return ret(PENT_OK);
     }
     if (kind == 2 && (seg_rows == 16 || seg_rows == 32 || seg_rows == 64)) {
@@ -1532,15 +1617,33 @@ int pent_check(pent_handle h)
     hipError_t e = hipMemcpy(&w, h->d_err, sizeof(w), hipMemcpyDeviceToHost);
     if (e == hipSuccess && w) e = hipMemset(h->d_err, 0, sizeof(w));
     if (e != hipSuccess) return ret(hip_status(e));
-    return ret(w ? PENT_TIMEOUT : PENT_OK);
+    if (w & 1u) return ret(PENT_TIMEOUT);
+    if (w & 2u) return ret(PENT_NOT_CONVERGED);
+    return ret(PENT_OK);
+}
+
+int pent_set_refine_tolerance(pent_handle h, double tol)
+{
+    if (!valid(h) || !(tol >= 0.0) || !std::isfinite(tol)) return ret(PENT_INVALID_VALUE);
+    h->refine_tol = tol;
+    return ret(PENT_OK);
 }
 
 int pent_query_schedule(pent_handle h, int64_t batch, int *kind, int *seg_rows)
 {
     if (!valid(h) || batch < 0 || !kind || !seg_rows) return ret(PENT_INVALID_VALUE);
     io_schedule(h, batch, true, kind, seg_rows);  // what an in-place pent_solve runs
-    if (*kind != 2 && *kind != 4) *seg_rows = 0;
+    if (*kind == 3) *seg_rows = 0;
     return ret(PENT_OK);
+}
+
+int pent_stream_copy(const double *src, int64_t ld_src, double *dst, int64_t ld_dst, int64_t n,
+                     int64_t batch, void *stream)
+{
+    if (n < 1 || batch < 0 || ld_src < batch || ld_dst < batch) return ret(PENT_INVALID_VALUE);
+    if (batch == 0) return ret(PENT_OK);
+    if (!src || !dst) return ret(PENT_INVALID_VALUE);
+    return ret(hip_status(launch_block_copy(src, dst, n, batch, ld_src, ld_dst, (hipStream_t)stream)));
 }
 
 int pent_last_status(void) { return g_status; }

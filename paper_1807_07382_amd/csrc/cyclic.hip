@@ -240,16 +240,16 @@ __device__ __forceinline__ int64_t wrap(int64_t r, int64_t n)
     return r;
 }
 
-__device__ __forceinline__ unsigned int wait_nonzero(unsigned int *p, unsigned int want,
-                                                     unsigned int *err)
+// Waits until *p >= want; false (and *err raised) if the wait ran out.
+__device__ __forceinline__ bool wait_nonzero(unsigned int *p, unsigned int want, unsigned int *err)
 {
     for (int i = 0; i < kSpin; i++) {
         const unsigned int v = poll(p);
-        if (v >= want) return v;
+        if (v >= want) return true;
         __builtin_amdgcn_s_sleep(1);
     }
     atomicOr(err, 1u);
-    return want;
+    return false;
 }
 
 template <int K, int W, bool CN>
@@ -394,6 +394,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     if (last) {
         // every group's partial products, in group order (windows of 64)
         const unsigned int u0 = u - (unsigned int)g;
+        bool timed_out = false;
         for (int b0 = 0; b0 < ngroups; b0 += 64) {
             for (int spin = 0;; spin++) {
                 const bool in = b0 + lane < ngroups;
@@ -401,6 +402,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
                 if (__ballot(in && st == 0) == 0) break;
                 if (spin >= kSpin) {
                     atomicOr(err, 1u);
+                    timed_out = true;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(1);
@@ -423,6 +425,10 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
                 }
             }
         }
+        if (timed_out) {  // partial products never seen: poison the tail
+            d0 = __builtin_nan("");
+            d1 = __builtin_nan("");
+        }
         const double r0v = sft[0][lane] - d0, r1v = sft[1][lane] - d1;
         xt0 = fma(aux->minv[1], r1v, aux->minv[0] * r0v);
         xt1 = fma(aux->minv[3], r1v, aux->minv[2] * r0v);
@@ -434,9 +440,13 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
             X[jj + (m + 1) * ldx] = xt1;
         }
     } else {
-        wait_nonzero(&tst[t], 1u, err);
+        const bool seen = wait_nonzero(&tst[t], 1u, err);
         xt0 = xload(&tx[0]);
         xt1 = xload(&tx[64]);
+        if (!seen) {  // the tail never arrived: NaN instead of stale values
+            xt0 = __builtin_nan("");
+            xt1 = __builtin_nan("");
+        }
     }
     if (!act || L == 0) return;
     CDbl Zf = Z;  // loaded here, not hoisted over the waits above

@@ -21,53 +21,116 @@ __global__ void k_assemble_d4(double *__restrict__ diag, int64_t n, double sigma
     diag[4 * n + i] = (i + 2 < n) ? sigma : 0.0;
 }
 
-// A = L R (Sec. 2.4).  The recurrence is serial in the row index, so one
-// lane runs it; it touches 9 doubles per row and runs once per matrix.  The
-// paper's first and last rows are the general step with zero padding:
+// A = L R (Sec. 2.4).  The recurrence is serial in the row index:
 //   beta_i  = b_i - a_i gamma_{i-2}
 //   alpha_i = c_i - a_i delta_{i-2} - beta_i gamma_{i-1}
 //   gamma_i = (d_i - beta_i delta_{i-1}) / alpha_i
 //   delta_i = e_i / alpha_i
+// (the paper's first and last rows are the general step with zero padding).
 // Operations are rounded one by one in the written order (no contraction,
 // IEEE division), so the factors are the correctly rounded values of that
-// sequence.  *bad receives the first row with a zero or non-finite pivot,
-// or -1.
-__global__ void k_factor_serial(const double *__restrict__ diag, int64_t n,
-                                double *__restrict__ fac, int64_t *__restrict__ bad)
+// sequence.  One workgroup: its threads bring the diagonals into LDS a chunk
+// of kFC rows at a time (the next chunk while the current one is worked on)
+// and write the factors out coalesced; one lane runs the recurrence from
+// LDS, kFU rows per batch with the batch's diagonal entries read ahead of
+// its arithmetic, so a row costs the latency of its dependent arithmetic
+// (one product, one difference, one division) and no memory round trip.
+// The loop has no branch on the pivot: the first row with a zero or
+// non-finite pivot is recorded and the rows from it on are overwritten
+// afterwards.  *bad receives that row, or -1.
+constexpr int kFC = 512;  // rows per chunk
+constexpr int kFU = 8;    // rows per batch of the serial lane
+
+__global__ __launch_bounds__(256) void k_factor_serial(const double *__restrict__ diag, int64_t n,
+                                                       double *__restrict__ fac,
+                                                       int64_t *__restrict__ bad)
 {
 #pragma clang fp contract(off)
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
-    const double *a = diag, *b = diag + n, *c = diag + 2 * n, *d = diag + 3 * n,
-                 *e = diag + 4 * n;
+    __shared__ double din[2][5][kFC];  // diagonals a..e of the chunk (zero outside the matrix)
+    __shared__ double dout[4][kFC];    // alpha, beta, gamma, delta of the chunk
+    __shared__ long long s_bad;
+    const int tid = threadIdx.x;
     double *alpha = fac, *beta = fac + n, *gamma = fac + 2 * n, *delta = fac + 3 * n;
-    double gam2 = 0.0, del2 = 0.0, gam1 = 0.0, del1 = 0.0;
-    int64_t badrow = -1;
-    for (int64_t i = 0; i < n; i++) {
-        const double ai = (i >= 2) ? a[i] : 0.0;
-        const double bi = (i >= 1) ? b[i] : 0.0;
-        const double di = (i + 1 < n) ? d[i] : 0.0;
-        const double ei = (i + 2 < n) ? e[i] : 0.0;
-        const double be = bi - ai * gam2;
-        const double al = c[i] - ai * del2 - be * gam1;
-        beta[i] = be;
-        alpha[i] = al;
-        if (!(al != 0.0) || !__builtin_isfinite(al)) {
-            badrow = i;
-            for (int64_t k = i; k < n; k++) {  // leave defined values behind
-                gamma[k] = 0.0;
-                delta[k] = 0.0;
-                if (k > i) { alpha[k] = 1.0; beta[k] = 0.0; }
+    const int64_t nch = (n + kFC - 1) / kFC;
+    // threads [t0, t0 + nt) fetch chunk c into din[buf]
+    auto load_chunk = [&](int64_t c, int buf, int t0, int nt) {
+        for (int k = tid - t0; k < 5 * kFC; k += nt) {
+            const int q = k / kFC, r = k % kFC;
+            const int64_t i = c * kFC + r;
+            double v = 0.0;
+            if (i < n) {
+                // entries that fall outside the matrix are zero
+                const bool in = q == 0 ? i >= 2 : q == 1 ? i >= 1 : q == 3 ? i + 1 < n : q == 4 ? i + 2 < n : true;
+                if (in) v = diag[(int64_t)q * n + i];
             }
-            break;
+            din[buf][q][r] = v;
         }
-        const double ga = (di - be * del1) / al;
-        const double de = ei / al;
-        gamma[i] = ga;
-        delta[i] = de;
-        gam2 = gam1; del2 = del1;
-        gam1 = ga;   del1 = de;
+    };
+    if (tid == 0) s_bad = -1;
+    load_chunk(0, 0, 0, 256);
+    __syncthreads();
+    double gam2 = 0.0, del2 = 0.0, gam1 = 0.0, del1 = 0.0;
+    long long badrow = -1;
+    for (int64_t c = 0; c < nch; c++) {
+        const int buf = (int)(c & 1);
+        if (tid >= 64) {
+            if (c + 1 < nch) load_chunk(c + 1, buf ^ 1, 64, 192);  // waves 1..3 fetch ahead
+        } else if (tid == 0) {
+            const double(*dg)[kFC] = din[buf];
+            for (int r0 = 0; r0 < kFC; r0 += kFU) {
+                double a[kFU], b[kFU], cc[kFU], d[kFU], e[kFU];
+#pragma unroll
+                for (int k = 0; k < kFU; k++) {
+                    a[k] = dg[0][r0 + k];
+                    b[k] = dg[1][r0 + k];
+                    cc[k] = dg[2][r0 + k];
+                    d[k] = dg[3][r0 + k];
+                    e[k] = dg[4][r0 + k];
+                }
+#pragma unroll
+                for (int k = 0; k < kFU; k++) {
+                    const double be = b[k] - a[k] * gam2;
+                    const double al = cc[k] - a[k] * del2 - be * gam1;
+                    const double ga = (d[k] - be * del1) / al;
+                    const double de = e[k] / al;
+                    const int64_t i = c * kFC + r0 + k;
+                    const bool pivot_bad = !(al != 0.0) || !__builtin_isfinite(al);
+                    badrow = (badrow < 0 && pivot_bad && i < n) ? (long long)i : badrow;
+                    dout[0][r0 + k] = al;
+                    dout[1][r0 + k] = be;
+                    dout[2][r0 + k] = ga;
+                    dout[3][r0 + k] = de;
+                    gam2 = gam1;
+                    del2 = del1;
+                    gam1 = ga;
+                    del1 = de;
+                }
+            }
+        }
+        __syncthreads();
+        for (int k = tid; k < 4 * kFC; k += 256) {
+            const int q = k / kFC, r = k % kFC;
+            const int64_t i = c * kFC + r;
+            if (i < n) fac[(int64_t)q * n + i] = dout[q][r];
+        }
+        __syncthreads();  // dout and the next chunk's buffer are reused
     }
-    *bad = badrow;
+    if (tid == 0) s_bad = badrow;
+    __syncthreads();
+    const long long b0 = s_bad;
+    if (b0 >= 0) {
+        // leave defined values behind: gamma, delta zero from the bad row on,
+        // alpha 1 and beta 0 past it (as if the factorisation had stopped)
+        for (int64_t i = b0 + tid; i < n; i += 256) {
+            gamma[i] = 0.0;
+            delta[i] = 0.0;
+            if (i > b0) {
+                alpha[i] = 1.0;
+                beta[i] = 0.0;
+            }
+        }
+    }
+    if (tid == 0) *bad = b0;
 }
 
 // Sweep records from the factors (row-parallel).
@@ -175,7 +238,7 @@ hipError_t launch_assemble_d4(double *d_diag, int64_t n, double sigma, hipStream
 hipError_t launch_factor(const double *d_diag, int64_t n, int64_t npad, double *d_fac,
                          FwdRec *d_fwd, BwdRec *d_bwd, int64_t *d_bad, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_factor_serial, dim3(1), dim3(64), 0, s, d_diag, n, d_fac, d_bad);
+    hipLaunchKernelGGL(k_factor_serial, dim3(1), dim3(256), 0, s, d_diag, n, d_fac, d_bad);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
     const int bs = 256;

@@ -13,7 +13,9 @@
 // wave takes whole segments of 64 rows; pass 1 writes the segment summaries
 // to the item's slice of the workspace, wave 0 runs the interface recurrence
 // over the segments, pass 2 repeats the sweeps from the true incoming states
-// and writes x in place.  No workgroup ever waits for another.
+// and writes x in place.  No workgroup ever waits for another, so this
+// kernel runs at any size; the single pass over all matrices (onepass.hip)
+// is faster where its tiles fit on the device.
 #include "lookback.h"
 
 namespace pent {
@@ -90,7 +92,8 @@ __global__ __launch_bounds__(64 * kGroupWaves) void k_group(const GroupMat *__re
         const GroupMat m = mats[item.mat];
         const CFwd fwd = (CFwd)m.fwd;
         const CBwd bwd = (CBwd)m.bwd;
-        const CSeg segr = (CSeg)(kGK == 64 ? m.seg64 : m.seg32);
+        static_assert(kGK == 64, "segment records are the 64-row ones");
+        const CSeg segr = (CSeg)m.seg64;
         const int64_t n = m.n;
         const int nseg = (int)((n + kGK - 1) / kGK);
         const bool act = lane < item.ncols;
@@ -157,150 +160,6 @@ __global__ __launch_bounds__(64 * kGroupWaves) void k_group(const GroupMat *__re
     }
 }
 
-// Decoupled variant: one-wave workgroups, each pulling (item, segment)
-// tasks from one counter.  Tasks [0, T) are pass 1 of every segment of every
-// item (items longest first), tasks [T, 2T) pass 2 in the same order.  The
-// wave that completes the last pass-1 task of an item runs the item's
-// interface recurrence and then publishes ready[item]; a pass-2 task waits
-// for that flag.  Every pass-2 task is handed out only after all pass-1
-// tasks have been handed to running waves, and those never wait on
-// anything, so every flag is eventually published; the wait is bounded
-// anyway and a timeout is reported through ctr[2] instead of hanging.
-//
-// No branch in this kernel depends on the lane index alone: the atomics are
-// executed by every lane (lanes other than 0 add zero, stores repeat the same
-// value) and lane 0's result is read back with readlane.  With a lane-0-only
-// fetch the compiler may thread the loop's back edge round the fetch for
-// the other lanes, which then re-run the previous task.
-constexpr int kSpinLimit = 1 << 24;
-
-__device__ __forceinline__ unsigned int wave_fetch_add(unsigned int *p, unsigned int v)
-{
-    const unsigned int r = atomicAdd(p, threadIdx.x == 0 ? v : 0u);
-    return (unsigned int)__builtin_amdgcn_readlane((int)r, 0);
-}
-
-// Every lane polls the flag (one address); true once it reads non-zero.
-// The flag and the summaries move with relaxed agent-scope accesses, ordered
-// by waiting for the writer's own stores before its flag (as the single
-// pass does): acquire / release operations would invalidate or write back a
-// whole XCD L2 per poll.
-__device__ __forceinline__ bool wait_flag(unsigned int *flag)
-{
-    for (int spins = 0; spins < kSpinLimit; spins++) {
-        const unsigned int v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __atomic_signal_fence(__ATOMIC_SEQ_CST);
-        if (__builtin_amdgcn_readlane((int)v, 0) != 0) return true;
-        __builtin_amdgcn_s_sleep(2);
-    }
-    return false;
-}
-
-// Device-coherent element access for interface_chain over the summaries,
-// which waves on other XCDs wrote.
-struct CohRef {
-    double *p;
-    __device__ operator double() const { return lb::xload(p); }
-    __device__ CohRef &operator=(double v)
-    {
-        lb::xstore(p, v);
-        return *this;
-    }
-};
-struct CohPtr {
-    double *p;
-    __device__ CohRef operator[](int64_t i) const { return CohRef{p + i}; }
-};
-
-template <int kGK>
-__global__ __launch_bounds__(64) void k_group_tasks(const GroupMat *__restrict__ mats,
-                                                    const GroupItem *__restrict__ items,
-                                                    const int2 *__restrict__ tasks, int ntasks,
-                                                    int nitems, double *__restrict__ summ,
-                                                    unsigned int *__restrict__ ctr,
-                                                    unsigned int *__restrict__ cnt,
-                                                    unsigned int *__restrict__ ready)
-{
-    const int lane = threadIdx.x;
-    for (;;) {
-        const int t = (int)wave_fetch_add(&ctr[0], 1u);
-        if (t >= 2 * ntasks) break;
-        const bool pass1 = t < ntasks;
-        const int2 task = tasks[pass1 ? t : t - ntasks];
-        const int ii = __builtin_amdgcn_readfirstlane(task.x);
-        const int sg = __builtin_amdgcn_readfirstlane(task.y);
-        const GroupItem item = items[ii];
-        const GroupMat m = mats[item.mat];
-        const CFwd fwd = (CFwd)m.fwd;
-        const CBwd bwd = (CBwd)m.bwd;
-        const CSeg segr = (CSeg)(kGK == 64 ? m.seg64 : m.seg32);
-        const int64_t n = m.n;
-        const int nseg = (int)((n + kGK - 1) / kGK);
-        const bool act = lane < item.ncols;
-        const int64_t j = item.col0 + (act ? lane : 0);
-        GDbl col = (GDbl)m.F + j;
-        GDbl S = (GDbl)summ + item.summ_off * (64 / kGK);
-        const int64_t r0 = (int64_t)sg * kGK;
-        const int L = (int)((n - r0) < kGK ? (n - r0) : kGK);
-        GDbl base = col + r0 * m.ld;
-        GDbl o = S + (int64_t)sg * 256 + lane;
-        double v[kGK];
-        if (pass1) {
-            load_seg(v, base, m.ld, act ? L : 0);
-            double p2 = 0.0, p1 = 0.0, q1 = 0.0, q2 = 0.0;
-            fwd_seg(v, fwd, r0, p2, p1);
-            bwd_seg(v, bwd, r0, q1, q2);
-            double *oc = (double *)o;
-            lb::xstore(oc, p2);
-            lb::xstore(oc + 64, p1);
-            lb::xstore(oc + 128, q1);
-            lb::xstore(oc + 192, q2);
-            lb::store_fence();  // summaries complete before the count
-            const int c = (int)wave_fetch_add(&cnt[ii], 1u);
-            if (c == nseg - 1) {  // last segment of this item: resolve its interfaces
-                // every other segment counted after storing its summaries
-                interface_chain(CohPtr{(double *)(S + lane)}, (int64_t)256, (int64_t)64, segr,
-                                (int64_t)nseg);
-                lb::store_fence();
-                __hip_atomic_store(&ready[ii], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        } else if (!wait_flag(&ready[ii])) {
-            atomicExch(&ctr[2], 1u);
-        } else {
-            load_seg(v, base, m.ld, act ? L : 0);
-            const double *oc = (const double *)o;
-            double p2 = lb::xload(oc), p1 = lb::xload(oc + 64), q1 = lb::xload(oc + 128),
-                   q2 = lb::xload(oc + 192);
-            fwd_seg(v, fwd, r0, p2, p1);
-            bwd_seg(v, bwd, r0, q1, q2);
-            if (act) {
-                if (L == kGK) {
-#pragma unroll
-                    for (int k = 0; k < kGK; k++) __builtin_nontemporal_store(v[k], base + k * m.ld);
-                } else {
-#pragma unroll
-                    for (int k = 0; k < kGK; k++)
-                        if (k < L) base[k * m.ld] = v[k];
-                }
-            }
-        }
-    }
-    // last wave out resets the counters and flags for the next launch
-    __threadfence();
-    const unsigned int d = wave_fetch_add(&ctr[1], 1u);
-    if (d == gridDim.x - 1) {
-        __threadfence();
-        for (int i = lane; i < nitems; i += 64) {
-            cnt[i] = 0u;
-            ready[i] = 0u;
-        }
-        __threadfence();
-        atomicExch(&ctr[0], 0u);
-        atomicExch(&ctr[1], 0u);
-        __threadfence();
-    }
-}
-
 __global__ void k_zero_u32(unsigned int *p, int count)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -309,49 +168,17 @@ __global__ void k_zero_u32(unsigned int *p, int count)
 
 }  // namespace
 
-// variants 0..3: one workgroup per item (64/32 rows, 8/4 waves);
-// variants 4, 5: decoupled one-wave tasks (64/32 rows).
-int group_variants() { return 6; }
+// The persistent kernel: 64-row segments, eight waves per workgroup (the
+// shape that measured fastest of 64/32 rows x 8/4 waves).
+constexpr int kPK = 64, kPW = 8;
 
-static void variant_shape(int v, int *K, int *W)
+int group_max_blocks()
 {
-    if (v >= 4) {
-        *K = v == 4 ? 64 : 32;
-        *W = 1;
-        return;
-    }
-    *K = (v & 1) ? 32 : 64;
-    *W = (v & 2) ? 4 : 8;
-}
-
-bool group_variant_is_tasks(int v) { return v >= 4; }
-
-int group_variant_seg_rows(int v)
-{
-    int K, W;
-    variant_shape(v, &K, &W);
-    return K;
-}
-
-static const void *variant_fn(int v)
-{
-    switch (v) {
-    case 0: return (const void *)k_group<64, 8>;
-    case 1: return (const void *)k_group<32, 8>;
-    case 2: return (const void *)k_group<64, 4>;
-    case 3: return (const void *)k_group<32, 4>;
-    case 4: return (const void *)k_group_tasks<64>;
-    default: return (const void *)k_group_tasks<32>;
-    }
-}
-
-int group_max_blocks(int v)
-{
-    int dev = 0, cus = 0, per_cu = 0, K, W;
-    variant_shape(v, &K, &W);
+    int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, variant_fn(v), 64 * W, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_group<kPK, kPW>, 64 * kPW,
+                                                     0) != hipSuccess)
         return 0;
     return cus * (per_cu > 0 ? per_cu : 1);
 }
@@ -362,34 +189,11 @@ hipError_t launch_group_init(unsigned int *ctr, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_zero_u32(unsigned int *p, int count, hipStream_t s)
+hipError_t launch_group(const GroupMat *mats, const GroupItem *items, int nitems, double *summ,
+                        unsigned int *ctr, int nblocks, hipStream_t s)
 {
-    if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero_u32, dim3((count + 255) / 256), dim3(256), 0, s, p, count);
-    return hipGetLastError();
-}
-
-hipError_t launch_group(int v, const GroupMat *mats, const GroupItem *items, int nitems,
-                        const int2 *tasks, int ntasks, double *summ, unsigned int *ctr,
-                        unsigned int *cnt, unsigned int *ready, int nblocks, hipStream_t s)
-{
-    int K, W;
-    variant_shape(v, &K, &W);
-    const dim3 grid((unsigned)nblocks), block(64 * W);
-    switch (v) {
-    case 0: hipLaunchKernelGGL((k_group<64, 8>), grid, block, 0, s, mats, items, nitems, summ, ctr); break;
-    case 1: hipLaunchKernelGGL((k_group<32, 8>), grid, block, 0, s, mats, items, nitems, summ, ctr); break;
-    case 2: hipLaunchKernelGGL((k_group<64, 4>), grid, block, 0, s, mats, items, nitems, summ, ctr); break;
-    case 3: hipLaunchKernelGGL((k_group<32, 4>), grid, block, 0, s, mats, items, nitems, summ, ctr); break;
-    case 4:
-        hipLaunchKernelGGL((k_group_tasks<64>), grid, block, 0, s, mats, items, tasks, ntasks, nitems,
-                           summ, ctr, cnt, ready);
-        break;
-    default:
-        hipLaunchKernelGGL((k_group_tasks<32>), grid, block, 0, s, mats, items, tasks, ntasks, nitems,
-                           summ, ctr, cnt, ready);
-        break;
-    }
+    hipLaunchKernelGGL((k_group<kPK, kPW>), dim3((unsigned)nblocks), dim3(64 * kPW), 0, s, mats, items,
+                       nitems, summ, ctr);
     return hipGetLastError();
 }
 

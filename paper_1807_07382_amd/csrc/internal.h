@@ -28,6 +28,10 @@ __device__ __forceinline__ P fresh(P p)
     return (P)a;
 }
 
+// max(m, v) that keeps a NaN once seen (fmax drops it): the maxima of the
+// backward error must let a non-finite solution through.
+__device__ __forceinline__ double nan_max(double m, double v) { return (v > m || v != v) ? v : m; }
+
 // r_i of one row: f_i - sum_k coef_k * x_k, every product and partial sum
 // carried with its rounding error (TwoProduct by fused multiply-add, TwoSum;
 // the "Dot2" scheme of Ogita, Rump and Oishi, SIAM J. Sci. Comput. 26, 2005).
@@ -100,7 +104,6 @@ struct GroupMat {
     const FwdRec *fwd;
     const BwdRec *bwd;
     const SegRec *seg64;  // transfer matrices for 64-row segments
-    const SegRec *seg32;  // ... and for 32-row segments
     double *F;          // right-hand sides, batch-fastest, overwritten in place
     int64_t n, npad, ld, batch;
 };
@@ -159,8 +162,10 @@ struct pent_plan {
     pent::FwdRec *d_fwd;     // npad
     pent::BwdRec *d_bwd;     // npad
     int sched_kind;          // 0 auto, 1 lane, 2 partitioned, 3 resident tile, 4 single pass
-    int sched_seg;           // seg_rows for kinds 2 and 4
-    unsigned int *d_err;     // 1 word: a single-pass wait ran out (cleared by pent_check)
+    int sched_seg;           // seg_rows for kinds 2 and 4, prefetch depth for kind 1
+    unsigned int *d_err;     // status bits since the last pent_check: 1 a single-pass wait
+                             // ran out, 2 a refined solve missed its tolerance
+    double refine_tol;       // backward-error tolerance of pent_solve_mixed (0: none)
     int onepass_cap[2];      // co-resident single-pass units (32, 64 rows), 0 = not yet queried
     int fix_cap;             // co-resident units of the fused correction, 0 = not yet queried
     int t_cap;               // ... of the system-major single pass
@@ -250,8 +255,9 @@ hipError_t launch_factor(const double *d_diag, int64_t n, int64_t npad, double *
 hipError_t launch_seg_prep(const FwdRec *d_fwd, const BwdRec *d_bwd, int64_t n, int seg_rows,
                            SegRec *d_seg, hipStream_t s);
 
+// depth: rows prefetched per block (8, 16 or 32; anything else means 16)
 hipError_t launch_lane_sweep(const FwdRec *fwd, const BwdRec *bwd, int64_t n, double *F,
-                             int64_t batch, int64_t ld, hipStream_t s);
+                             int64_t batch, int64_t ld, int depth, hipStream_t s);
 hipError_t launch_part_sweep(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg,
                              int64_t n, int64_t npad, int seg_rows, double *F, int64_t batch,
                              int64_t ld, double *summ, int64_t summ_ld, hipStream_t s);
@@ -280,9 +286,12 @@ hipError_t launch_axpy(double *x, int64_t ldx, const double *d, int64_t ldd, int
                        int64_t batch, hipStream_t s);
 // eta[j] = ||f - A x||_inf / (||A||_inf ||x||_inf + ||f||_inf), compensated; acc is
 // 3*batch uint64 of scratch.
+// eta may be NULL (not stored); with tol > 0, a system whose eta exceeds tol
+// or is not finite sets bit 2 of *err.
 hipError_t launch_eta(const double *d_diag, const double *d_anorm, int64_t n, const void *f,
                       bool f32, int64_t ldf, const double *x, int64_t ldx, int64_t batch,
-                      unsigned long long *acc, double *eta, hipStream_t s);
+                      unsigned long long *acc, double *eta, double tol, unsigned int *err,
+                      hipStream_t s);
 hipError_t launch_anorm(const double *d_diag, int64_t n, double *d_anorm, hipStream_t s);
 
 // ---- 2-D Cahn-Hilliard explicit term (ch2d.hip, and fused into k_onepass_t) ----
@@ -332,6 +341,10 @@ hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *se
                           int seg_rows, const void *Fin, bool f32, int64_t ldf, double *X,
                           int64_t ldx, int64_t batch, void *scratch, unsigned int *err,
                           hipStream_t s);
+
+// ---- measurement (copy.hip): dst = src through the single pass's blocks ----
+hipError_t launch_block_copy(const double *src, double *dst, int64_t n, int64_t batch, int64_t lds,
+                             int64_t ldd, hipStream_t s);
 
 // ---- per-system matrices, refactored every call (rewrite.hip) ----
 // work: 256 bytes of header (first failing pivot key, system * n + row) and
@@ -383,22 +396,14 @@ hipError_t launch_cyc_correct(const CycAux *aux, const double *Z, double *F, int
 hipError_t launch_cn_rhs(const double *cd, int64_t n, const double *C, int64_t ldc, double *R,
                          int64_t ldr, int64_t batch, hipStream_t s);
 
-// ---- group solve (group.hip) ----
-// Kernel variants (rows per segment x waves per workgroup), chosen by the
-// group autotuner.  Summary offsets in GroupItem are in units of the 64-row
-// variant; a 32-row variant scales them by 2.
-int group_variants();
-bool group_variant_is_tasks(int v);
-int group_variant_seg_rows(int v);
-int group_max_blocks(int v);  // co-resident workgroups of variant v on the current device
+// ---- group solve (group.hip): the persistent kernel ----
+// Items (matrix, up to 64 systems) handed out longest first from ctr[0] to
+// nblocks resident workgroups, each solving its item alone (summaries in
+// summ at the item's offset); the last workgroup out clears ctr[0..1].
+int group_max_blocks();  // co-resident workgroups on the current device
 hipError_t launch_group_init(unsigned int *ctr, hipStream_t s);  // ctr[0..2] = 0
-hipError_t launch_zero_u32(unsigned int *p, int count, hipStream_t s);
-// tasks: (item, segment) pairs of the variant's segment length, items in
-// work-list order; cnt / ready: one counter and one flag per item, zero on
-// entry and left zero on exit; ctr[2] becomes 1 if a wait timed out.
-hipError_t launch_group(int v, const GroupMat *mats, const GroupItem *items, int nitems,
-                        const int2 *tasks, int ntasks, double *summ, unsigned int *ctr,
-                        unsigned int *cnt, unsigned int *ready, int nblocks, hipStream_t s);
+hipError_t launch_group(const GroupMat *mats, const GroupItem *items, int nitems, double *summ,
+                        unsigned int *ctr, int nblocks, hipStream_t s);
 hipError_t launch_strided_sweep(const FwdRec *fwd, const BwdRec *bwd, int64_t n, double *F,
                                 int64_t batch, int64_t ld, hipStream_t s);
 

@@ -256,7 +256,8 @@ __device__ __forceinline__ void stage_load(const double *blk, double *dst)
 
 // Group-level look-back (FWD) or look-ahead: the incoming carry of group g
 // of the tile whose first group unit is u0, given this group's aggregate
-// (c0, c1), which is posted first.  Statuses: 1 aggregate posted, 2
+// (c0, c1), which is posted first.  A wait that runs out raises *err and
+// returns a NaN carry.  Statuses: 1 aggregate posted, 2
 // inclusive posted; the first group (forward) and the last group (backward)
 // post only inclusive values.  Exchange rows: forward 0,1 aggregate, 2,3
 // inclusive; backward 4,5 aggregate, 6,7 inclusive.
@@ -275,6 +276,7 @@ __device__ __forceinline__ void group_carry(CSeg seg, int g, int ngroups, unsign
     xstore(&me[(ra + 1) * 64], c1);
     publish(&st_word[u0 + g], 1u);
     int base = FWD ? g - 1 : g + 1, pstar = base;
+    bool timed_out = false;
     for (int spin = 0;; spin++) {
         const int p = FWD ? base - lane : base + lane;
         const bool in = FWD ? p >= 0 : p < ngroups;
@@ -293,6 +295,7 @@ __device__ __forceinline__ void group_carry(CSeg seg, int g, int ngroups, unsign
         }
         if (spin >= kSpin) {
             atomicOr(err, 1u);
+            timed_out = true;
             break;
         }
         __builtin_amdgcn_s_sleep(1);
@@ -345,6 +348,13 @@ __device__ __forceinline__ void group_carry(CSeg seg, int g, int ngroups, unsign
         }
         __atomic_signal_fence(__ATOMIC_SEQ_CST);  // LDS reads before the next chunk's loads
         __builtin_amdgcn_s_waitcnt(0xC07F);       // lgkmcnt(0)
+    }
+    // a wait that ran out replayed from a status it never saw: the carry is
+    // NaN, so every value that depends on it (this tile's x, the carries it
+    // publishes) comes out NaN instead of a plausible wrong number
+    if (timed_out) {
+        y0 = __builtin_nan("");
+        y1 = __builtin_nan("");
     }
 }
 

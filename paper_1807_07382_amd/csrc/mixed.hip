@@ -73,8 +73,8 @@ __device__ __forceinline__ void residual_interior(const double *__restrict__ dia
     if (MAXES) {
 #pragma unroll
         for (int k = 0; k < kRB; k++) {
-            *xm = fmax(*xm, fabs(xw[k + 2]));
-            *fm = fmax(*fm, fabs(fv[k]));
+            *xm = nan_max(*xm, fabs(xw[k + 2]));
+            *fm = nan_max(*fm, fabs(fv[k]));
         }
     }
     CDbl dg = (CDbl)diag;
@@ -131,7 +131,8 @@ __global__ void k_fill_u64(unsigned long long *__restrict__ p, int64_t count)
 }
 
 // Non-negative doubles order like their bit patterns, so the maxima are
-// taken with integer atomics on the bits.
+// taken with integer atomics on the bits; a (positive) NaN's bits exceed
+// every number's, so a NaN in any block survives the atomics.
 template <typename TI>
 __global__ __launch_bounds__(64) void k_eta_partial(const double *__restrict__ diag, int64_t n,
                                                     const TI *__restrict__ f, int64_t ldf,
@@ -154,21 +155,24 @@ __global__ __launch_bounds__(64) void k_eta_partial(const double *__restrict__ d
             residual_block<TI, false>(diag, n, f, ldf, x, ldx, j, i0, rv, fv, xw);
 #pragma unroll
             for (int k = 0; k < kRB; k++) {
-                xm = fmax(xm, fabs(xw[k + 2]));
-                fm = fmax(fm, fabs(fv[k]));
+                xm = nan_max(xm, fabs(xw[k + 2]));
+                fm = nan_max(fm, fabs(fv[k]));
             }
         }
 #pragma unroll
-        for (int k = 0; k < kRB; k++) rm = fmax(rm, fabs(rv[k]));
+        for (int k = 0; k < kRB; k++) rm = nan_max(rm, fabs(rv[k]));
     }
     atomicMax(acc + 3 * j + 0, (unsigned long long)__double_as_longlong(rm));
     atomicMax(acc + 3 * j + 1, (unsigned long long)__double_as_longlong(xm));
     atomicMax(acc + 3 * j + 2, (unsigned long long)__double_as_longlong(fm));
 }
 
+// eta from the maxima; eta may be NULL.  tol > 0: a system with eta > tol,
+// or a non-finite eta, raises bit 2 of *err (the refinement missed its
+// tolerance).
 __global__ void k_eta_final(const unsigned long long *__restrict__ acc,
                             const double *__restrict__ anorm, int64_t batch,
-                            double *__restrict__ eta)
+                            double *__restrict__ eta, double tol, unsigned int *err)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= batch) return;
@@ -176,7 +180,10 @@ __global__ void k_eta_final(const unsigned long long *__restrict__ acc,
     const double xm = __longlong_as_double((long long)acc[3 * j + 1]);
     const double fm = __longlong_as_double((long long)acc[3 * j + 2]);
     const double den = anorm[0] * xm + fm;
-    eta[j] = den > 0.0 ? rm / den : 0.0;
+    // den == 0 only for x = 0 and f = 0 (then r = 0); NaN reaches eta
+    const double e = (den > 0.0 || den != den) ? rm / den : rm;
+    if (eta) eta[j] = e;
+    if (tol > 0.0 && !(e <= tol)) atomicOr(err, 2u);
 }
 
 // ||A||_inf = max_i sum_k |A_ik| over the (zero-padded) diagonals.
@@ -225,7 +232,8 @@ hipError_t launch_axpy(double *x, int64_t ldx, const double *d, int64_t ldd, int
 
 hipError_t launch_eta(const double *d_diag, const double *d_anorm, int64_t n, const void *f,
                       bool f32, int64_t ldf, const double *x, int64_t ldx, int64_t batch,
-                      unsigned long long *acc, double *eta, hipStream_t s)
+                      unsigned long long *acc, double *eta, double tol, unsigned int *err,
+                      hipStream_t s)
 {
     const int64_t cnt = 3 * batch;
     hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, acc, cnt);
@@ -242,7 +250,7 @@ hipError_t launch_eta(const double *d_diag, const double *d_anorm, int64_t n, co
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_eta_final, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, acc,
-                       d_anorm, batch, eta);
+                       d_anorm, batch, eta, tol, err);
     return hipGetLastError();
 }
 

@@ -8,7 +8,8 @@
 //                 consecutive systems, so every row access is one coalesced
 //                 512-byte segment; the per-row factors are wave-uniform and
 //                 come through scalar loads; the two carried values live in
-//                 registers; rows are prefetched D at a time, double-buffered.
+//                 registers; rows are prefetched D at a time, double-buffered
+//                 (D = 8, 16 or 32: the prefetch depth, a tuning knob).
 //                 g is written over f between the sweeps.
 //  * partitioned: the rows are cut into segments of K rows and every
 //                 (segment, system) pair gets its own lane.  By linearity the
@@ -369,11 +370,15 @@ __global__ __launch_bounds__(64) void k_strided(const FwdRec *__restrict__ fwd,
 }  // namespace
 
 hipError_t launch_lane_sweep(const FwdRec *fwd, const BwdRec *bwd, int64_t n, double *F,
-                             int64_t batch, int64_t ld, hipStream_t s)
+                             int64_t batch, int64_t ld, int depth, hipStream_t s)
 {
     const int bs = 256;
     const dim3 grid((unsigned)((batch + bs - 1) / bs));
-    hipLaunchKernelGGL(k_lane<16>, grid, dim3(bs), 0, s, fwd, bwd, (int)n, F, batch, ld);
+    switch (depth) {
+    case 8: hipLaunchKernelGGL(k_lane<8>, grid, dim3(bs), 0, s, fwd, bwd, (int)n, F, batch, ld); break;
+    case 32: hipLaunchKernelGGL(k_lane<32>, grid, dim3(bs), 0, s, fwd, bwd, (int)n, F, batch, ld); break;
+    default: hipLaunchKernelGGL(k_lane<16>, grid, dim3(bs), 0, s, fwd, bwd, (int)n, F, batch, ld); break;
+    }
     return hipGetLastError();
 }
 

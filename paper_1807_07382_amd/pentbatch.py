@@ -14,7 +14,8 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpentbatch.so")
+# PENTBATCH_LIB names another build of the same sources (the sanitizer job's)
+LIB_PATH = os.environ.get("PENTBATCH_LIB") or os.path.join(HERE, "libpentbatch.so")
 
 OK = 0
 INVALID_VALUE = 1
@@ -25,6 +26,11 @@ NOT_CONVERGED = 5
 SIZE_MISMATCH = 6
 NOT_SUPPORTED = 7
 TIMEOUT = 8
+
+# group solve modes (pent_group_solve)
+GROUP_FP64 = 0
+GROUP_MIXED = 1       # rejected with NOT_SUPPORTED (see the header)
+GROUP_PER_MATRIX = 2
 
 # every symbol include/pentbatch.h declares: name -> (restype, argtypes)
 _P = ctypes.c_void_p
@@ -38,7 +44,9 @@ SIGNATURES = {
     "pent_solve": (_I, [_P, _P, _I64, _I64, _P]),
     "pent_solve_strided": (_I, [_P, _P, _I64, _I64, _P]),
     "pent_solve_mixed": (_I, [_P, _P, _I, _I64, _P, _I64, _I64, _I, _P, _P, ctypes.c_size_t, _P]),
-    "pent_mixed_workspace_size": (ctypes.c_size_t, [_P, _I64, _I, _I]),
+    "pent_mixed_workspace_size": (ctypes.c_size_t, [_P, _I64]),
+    "pent_mixed_workspace_size_ex": (ctypes.c_size_t, [_P, _I64, _I, _I]),
+    "pent_set_refine_tolerance": (_I, [_P, _D]),
     "pent_backward_error": (_I, [_P, _P, _I, _I64, _P, _I64, _I64, _P, _P, ctypes.c_size_t, _P]),
     "pent_group_create": (_P, [ctypes.POINTER(_P), _I64]),
     "pent_group_workspace_size": (ctypes.c_size_t, [_P, ctypes.POINTER(_I64)]),
@@ -77,6 +85,7 @@ SIGNATURES = {
     "pent_set_schedule": (_I, [_P, _I, _I]),
     "pent_check": (_I, [_P]),
     "pent_query_schedule": (_I, [_P, _I64, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "pent_stream_copy": (_I, [_P, _I64, _P, _I64, _I64, _I64, _P]),
     "pent_last_status": (_I, []),
     "pent_last_pivot_row": (_I64, []),
     "pent_status_string": (ctypes.c_char_p, [_I]),
@@ -126,6 +135,17 @@ def _stream_ptr(stream):
     if isinstance(stream, int):
         return stream
     return stream.cuda_stream
+
+
+def _torch_stream(stream):
+    """The torch stream a solve is enqueued on (torch's current one for None;
+    a raw hipStream_t handle is wrapped)."""
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream()
+    if isinstance(stream, int):
+        return torch.cuda.ExternalStream(stream)
+    return stream
 
 
 def _dptr(t, dtype_name: str):
@@ -231,9 +251,12 @@ class Plan:
         fdt = {torch.float32: 1, torch.float64: 0}.get(F.dtype)
         if fdt is None:
             raise ValueError("F must be float32 or float64")
-        nbytes = lib().pent_mixed_workspace_size(self._h, m, int(refine_steps), int(eta is not None))
+        nbytes = lib().pent_mixed_workspace_size_ex(self._h, m, int(refine_steps), int(eta is not None))
         if work is None and nbytes:
-            work = torch.empty(nbytes, dtype=torch.uint8, device=F.device)
+            # allocated on the solve's stream, so the caching allocator does
+            # not hand it out again while the kernels there still use it
+            with torch.cuda.stream(_torch_stream(stream)):
+                work = torch.empty(nbytes, dtype=torch.uint8, device=F.device)
         wptr = work.data_ptr() if work is not None else None
         wlen = work.numel() * work.element_size() if work is not None else 0
         if eta is not None and (eta.dtype != torch.float64 or eta.numel() < m):
@@ -251,7 +274,8 @@ class Plan:
         m = F.shape[1]
         fdt = {torch.float32: 1, torch.float64: 0}[F.dtype]
         if work is None:
-            work = torch.empty(24 * max(m, 1), dtype=torch.uint8, device=F.device)
+            with torch.cuda.stream(_torch_stream(stream)):
+                work = torch.empty(24 * max(m, 1), dtype=torch.uint8, device=F.device)
         _check(lib().pent_backward_error(self._h, F.data_ptr(), fdt, max(F.stride(0), m),
                                          _dptr(X, "float64"), max(X.stride(0), m), m,
                                          eta.data_ptr(), work.data_ptr(), work.numel(),
@@ -291,13 +315,27 @@ class Plan:
 
     def check(self):
         """Raise PentError(TIMEOUT) if a single-pass solve on this handle gave
-        up a wait since the last check (blocking)."""
+        up a wait since the last check, PentError(NOT_CONVERGED) if a refined
+        solve missed the tolerance set by set_refine_tolerance (blocking)."""
         _check(lib().pent_check(self._h), "check")
+
+    def set_refine_tolerance(self, tol: float):
+        """Backward-error tolerance of solve_mixed (0 turns the check off)."""
+        _check(lib().pent_set_refine_tolerance(self._h, float(tol)), "set_refine_tolerance")
+
+    def mixed_workspace_size(self, batch: int, refine_steps: int = None, eta: bool = True) -> int:
+        """Bytes of solve_mixed's workspace: for every refine_steps (None) or
+        for one configuration."""
+        if refine_steps is None:
+            return int(lib().pent_mixed_workspace_size(self._h, int(batch)))
+        return int(lib().pent_mixed_workspace_size_ex(self._h, int(batch), int(refine_steps),
+                                                      int(bool(eta))))
 
 
 class Group:
     """Several factored plans solved together (pent_group).  ``solve`` runs
-    one persistent launch (mode 0) or one solve per matrix (mode 1)."""
+    one launch for all matrices (mode GROUP_FP64) or one solve per matrix
+    (mode GROUP_PER_MATRIX); GROUP_MIXED is rejected by the library."""
 
     def __init__(self, plans):
         self.plans = list(plans)
@@ -362,7 +400,9 @@ class Group:
                                       w.data_ptr(), w.numel(), _stream_ptr(stream))
         if not gr:
             raise PentError(lib().pent_last_status(), "group_capture")
-        return Graph(gr)
+        # the graph's kernels read these buffers: keep them (and the plans,
+        # through the group) alive as long as the graph
+        return Graph(gr, keep=(self, w, list(Fs)))
 
     def close(self):
         if self._g:
@@ -377,8 +417,12 @@ class Group:
 
 
 class Graph:
-    def __init__(self, handle):
+    """An executable HIP graph of captured group solves.  It holds the group,
+    its workspace and the right-hand-side blocks it was captured on."""
+
+    def __init__(self, handle, keep=()):
         self._h = handle
+        self._keep = keep
 
     def launch(self, stream=None):
         _check(lib().pent_graph_launch(self._h, _stream_ptr(stream)), "graph_launch")
@@ -387,6 +431,7 @@ class Graph:
         if self._h:
             _check(lib().pent_graph_destroy(self._h), "graph_destroy")
             self._h = None
+        self._keep = ()
 
     def __del__(self):
         try:
@@ -583,3 +628,17 @@ def ch2d_step(plan_x: "Plan", plan_y: "Plan", C, R, dt, h: float, stream=None):
                                 _dptr(R, "float64"), ny, ninst, nx, _dptr(dt, "float64"),
                                 float(h), _stream_ptr(stream)), "ch2d_step")
     return C
+
+
+def stream_copy(src, dst, stream=None):
+    """dst = src (cuda float64, shape (n, batch), unit batch stride) through
+    the single pass's block pattern: the layout's copy ceiling."""
+    if src.shape != dst.shape or src.dim() != 2:
+        raise ValueError("src and dst must have one (n, batch) shape")
+    n, m = src.shape
+    for t in (src, dst):
+        if m > 1 and t.stride(1) != 1:
+            raise ValueError("unit batch stride required")
+    _check(lib().pent_stream_copy(_dptr(src, "float64"), max(src.stride(0), m), _dptr(dst, "float64"),
+                                  max(dst.stride(0), m), n, m, _stream_ptr(stream)), "stream_copy")
+    return dst

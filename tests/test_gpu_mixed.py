@@ -140,7 +140,7 @@ def test_mixed_argument_errors(torch):
         # aliasing with FP32 input or with refinement is refused
         assert L.pent_solve_mixed(h, X.data_ptr(), 1, m, X.data_ptr(), m, m, 0, None, None, 0,
                                   None) == pb.INVALID_VALUE
-        need = L.pent_mixed_workspace_size(h, m, 1, 0)
+        need = L.pent_mixed_workspace_size_ex(h, m, 1, 0)
         assert need > 0
         assert L.pent_solve_mixed(h, F64.data_ptr(), 0, m, F64.data_ptr(), m, m, 1, None, None, 0,
                                   None) == pb.INVALID_VALUE
@@ -177,3 +177,61 @@ def test_precision_workload_full_size_sampled(torch):
         Xs = X[:, torch.from_numpy(cols).cuda()].cpu().numpy()
         ref = oracle.solve(oracle.assemble_d4(n, sigma), f32[:, cols].astype(np.float64))
         assert np.all(colerr(Xs, ref) <= d4_tol(sigma))
+
+
+def test_refine_tolerance_miss_reports_not_converged(torch):
+    """A tolerance no solve can meet (1e-30) makes pent_check report
+    NOT_CONVERGED after a refined solve, with or without eta_out; the status
+    clears on reading; a reachable tolerance (1e-12) reports OK; the
+    two-argument workspace query covers every configuration."""
+    n, m = 1500, 200
+    f = np.random.Generator(np.random.PCG64(12)).uniform(-1, 1, (n, m)).astype(np.float32)
+    print_case(test="refine_tol", n=n, m=m)
+    with pb.Plan.factor_d4(n, 1e2) as p:
+        full = p.mixed_workspace_size(m)
+        for k in range(0, 17):
+            for e in (0, 1):
+                assert p.mixed_workspace_size(m, k, bool(e)) <= full
+        F = torch.from_numpy(f).cuda()
+        X = torch.empty((n, m), dtype=torch.float64, device="cuda")
+        eta = torch.empty(m, dtype=torch.float64, device="cuda")
+        p.set_refine_tolerance(1e-30)
+        for with_eta in (False, True):
+            p.solve_mixed(F, X, refine_steps=1, eta=eta if with_eta else None)
+            torch.cuda.synchronize()
+            with pytest.raises(pb.PentError) as ei:
+                p.check()
+            assert ei.value.status == pb.NOT_CONVERGED
+            p.check()                         # cleared by the read
+        p.set_refine_tolerance(1e-12)
+        p.solve_mixed(F, X, refine_steps=1, eta=eta)
+        torch.cuda.synchronize()
+        p.check()
+        assert float(eta.max()) <= 1e-12
+        p.set_refine_tolerance(0.0)
+        with pytest.raises(pb.PentError):
+            p.set_refine_tolerance(-1.0)
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_device_backward_error_of_non_finite_solution(torch, bad):
+    """The device backward error lets a non-finite solution through (NaN or
+    Inf in x gives a non-finite eta), as the oracle's does."""
+    n, m = 300, 70
+    f = np.random.Generator(np.random.PCG64(13)).uniform(-1, 1, (n, m))
+    print_case(test="eta_nonfinite", bad=bad)
+    with pb.Plan.factor_d4(n, 5.0) as p:
+        F = torch.from_numpy(f).cuda()
+        X = F.clone()
+        p.solve_(X)
+        X[17, 3] = bad
+        X[:, 66] = bad
+        eta = torch.empty(m, dtype=torch.float64, device="cuda")
+        p.backward_error(F, X, eta)
+        torch.cuda.synchronize()
+        e = eta.cpu().numpy()
+        ref, _ = oracle.residual(oracle.assemble_d4(n, 5.0), X.cpu().numpy(), f)
+        assert not np.isfinite(e[3]) and not np.isfinite(e[66])
+        assert not np.isfinite(ref[3]) and not np.isfinite(ref[66])
+        ok = np.setdiff1d(np.arange(m), [3, 66])
+        assert np.all(e[ok] <= 1e-15)
