@@ -88,6 +88,23 @@ int pent_destroy(pent_handle h);
  * scratch memory on `stream`. */
 int pent_solve(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream);
 
+/* Same solve, allocating nothing: for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, schedule, kernels and results (bit
+ * for bit) as pent_solve; the scratch that pent_solve takes from the
+ * stream-ordered allocator comes instead from a fixed 72 MiB buffer in the
+ * library's device memory, one per GPU, held until the process ends.
+ * Returns PENT_NOT_SUPPORTED, before any HIP call, when the schedule needs
+ * more scratch than that (e.g. the single pass beyond about 18 000
+ * 64-system x 256-row units: n = 4096 with more than 72 000 systems) or
+ * tables that do not exist yet (a schedule forced by pent_set_schedule and
+ * not yet used by pent_solve; pent_factor builds the automatic schedule's).
+ * Every call on one GPU shares that GPU's buffer and the buffer keeps the
+ * last call's contents (the kernels clear what must start at zero), so
+ * calls that may overlap in time on one GPU (other streams, other threads)
+ * race: serialise them. */
+int pent_solve_noalloc(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream);
+
 /* Same solve for system-major storage: system j occupies n contiguous
  * doubles at F + j*ld (element (i, j) at F[j*ld + i]), ld >= n.  This is the
  * layout of the second direction of an alternating-direction (ADI-style)

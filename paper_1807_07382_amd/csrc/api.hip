@@ -570,12 +570,12 @@ int cyc_run_single(pent_cyclic c, bool cn, const double *F, int64_t ldf, double 
     int st;
     const SegRec *seg = seg_cache(c->E, c->seg_rows, &st);
     if (!seg) return st;
-    void *scratch = nullptr;
-    hipError_t e = hipMallocAsync(&scratch, cyc_onepass_scratch_bytes(c->n, c->seg_rows, batch), s);
+    void *xbuf = nullptr;
+    hipError_t e = hipMallocAsync(&xbuf, cyc_onepass_scratch_bytes(c->n, c->seg_rows, batch), s);
     if (e != hipSuccess) return hip_status(e);
     e = launch_cyc_onepass(c->E->d_fwd, c->E->d_bwd, seg, c->d_cd, c->d_Z, c->d_W, c->d_aux, c->n,
-                           c->seg_rows, cn, F, ldf, X, ldx, batch, scratch, c->E->d_err, s);
-    const hipError_t e2 = hipFreeAsync(scratch, s);
+                           c->seg_rows, cn, F, ldf, X, ldx, batch, xbuf, c->E->d_err, s);
+    const hipError_t e2 = hipFreeAsync(xbuf, s);
     return hip_status(e != hipSuccess ? e : e2);
 }
 
@@ -846,6 +846,54 @@ int group_check_args(pent_group g, double *const *F, const int64_t *batch, const
     return PENT_OK;
 }
 
+// ---- allocation-free solve (pent_solve_noalloc) ----
+
+// Scratch of pent_solve_noalloc: device memory that belongs to the library's
+// code object, one copy per GPU (each GPU holds it until the process ends),
+// used where pent_solve takes stream-ordered scratch.  72 MiB covers the
+// single pass's status words and exchange area up to 18 000 units (64-system
+// tiles x 256-row groups), e.g. n = 4096 with 72 000 systems.  In host code
+// the name is only a stand-in for the symbol: kernels get the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoallocScratchBytes = (size_t)72 << 20;
+__device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_addr;  // device -> address of its copy of scratch
+
+// Address of the current device's copy of scratch, looked up once per device
+// (with that device current).
+int noalloc_scratch(void **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_status(e);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it == g_scratch_addr.end()) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr) return e != hipSuccess ? hip_status(e) : PENT_HIP_ERROR;
+        it = g_scratch_addr.emplace(dev, ptr).first;
+    }
+    *out = it->second;
+    return PENT_OK;
+}
+
+// The tables a schedule reads already exist (built by pent_factor or an
+// earlier solve), so solve_io will not build (allocate) them.
+bool tables_ready(pent_plan *p, int kind, int seg_rows)
+{
+    std::lock_guard<std::mutex> lk(p->mu);
+    if (kind == 1) return true;
+    if (kind == 3) {
+        const int rows = tile_rows_for(p->n);
+        return p->d_scan != nullptr && p->scan_rows == rows;
+    }
+    const int slot = seg_rows == 16 ? 0 : seg_rows == 32 ? 1 : 2;
+    return p->seg[slot].d_seg != nullptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -924,6 +972,24 @@ int pent_solve(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream
     if (batch == 0) return ret(PENT_OK);
     if (!F) return ret(PENT_INVALID_VALUE);
     return ret(solve_io_scratch(h, F, ld, F, ld, batch, (hipStream_t)stream));
+}
+
+int pent_solve_noalloc(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream)
+{
+    if (!valid(h) || batch < 0 || ld < batch) return ret(PENT_INVALID_VALUE);
+    if (batch == 0) return ret(PENT_OK);
+    if (!F) return ret(PENT_INVALID_VALUE);
+    int kind, seg_rows;
+    io_schedule(h, batch, true, &kind, &seg_rows);
+    if (!tables_ready(h, kind, seg_rows)) return ret(PENT_NOT_SUPPORTED);
+    const size_t bytes = summ_bytes(h, kind, seg_rows, batch);
+    if (bytes > kNoallocScratchBytes) return ret(PENT_NOT_SUPPORTED);
+    void *ws = nullptr;
+    if (bytes > 0) {
+        const int st = noalloc_scratch(&ws);
+        if (st != PENT_OK) return ret(st);
+    }
+    return ret(solve_io(h, F, false, ld, F, ld, batch, ws, (hipStream_t)stream));
 }
 
 size_t pent_mixed_workspace_size_ex(pent_handle h, int64_t batch, int refine_steps, int want_eta)
@@ -1341,12 +1407,12 @@ int pent_ch2d_step(pent_handle hx, pent_handle hy, double *C, double *R, int64_t
         int st;
         const SegRec *seg64 = seg_cache(hx, 64, &st);
         if (!seg64) return ret(st);
-        void *scratch = nullptr;
-        hipError_t e = hipMallocAsync(&scratch, onepass_t_scratch_bytes(nx, batch), s);
+        void *xbuf = nullptr;
+        hipError_t e = hipMallocAsync(&xbuf, onepass_t_scratch_bytes(nx, batch), s);
         if (e != hipSuccess) return ret(hip_status(e));
-        e = launch_onepass_t_ch2d(hx->d_fwd, hx->d_bwd, seg64, nx, C, R, ny, ninst, dt, h, scratch,
+        e = launch_onepass_t_ch2d(hx->d_fwd, hx->d_bwd, seg64, nx, C, R, ny, ninst, dt, h, xbuf,
                                   hx->d_err, s);
-        const hipError_t e2 = hipFreeAsync(scratch, s);
+        const hipError_t e2 = hipFreeAsync(xbuf, s);
         if (e != hipSuccess || e2 != hipSuccess) return ret(hip_status(e != hipSuccess ? e : e2));
     } else {
         int st = pent_ch2d_rhs(C, R, ny, ninst, nx, dt, h, stream);
@@ -1539,11 +1605,11 @@ int pent_solve_strided(pent_handle h, double *F, int64_t batch, int64_t ld, void
         int st;
         const SegRec *seg64 = seg_cache(h, 64, &st);
         if (!seg64) return ret(st);
-        void *scratch = nullptr;
-        hipError_t e = hipMallocAsync(&scratch, onepass_t_scratch_bytes(h->n, batch), s);
+        void *xbuf = nullptr;
+        hipError_t e = hipMallocAsync(&xbuf, onepass_t_scratch_bytes(h->n, batch), s);
         if (e != hipSuccess) return ret(hip_status(e));
-        e = launch_onepass_t(h->d_fwd, h->d_bwd, seg64, h->n, F, batch, ld, scratch, h->d_err, s);
-        const hipError_t e2 = hipFreeAsync(scratch, s);
+        e = launch_onepass_t(h->d_fwd, h->d_bwd, seg64, h->n, F, batch, ld, xbuf, h->d_err, s);
+        const hipError_t e2 = hipFreeAsync(xbuf, s);
         return ret(hip_status(e != hipSuccess ? e : e2));
     }
     return ret(hip_status(launch_strided_sweep(h->d_fwd, h->d_bwd, h->n, F, batch, ld, s)));

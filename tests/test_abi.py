@@ -64,6 +64,7 @@ def test_null_handle_is_rejected_everywhere():
     buf = (ctypes.c_double * 8)()
     assert L.pent_solve(None, buf, 1, 1, None) == pb.INVALID_VALUE
     assert L.pent_solve_strided(None, buf, 1, 1, None) == pb.INVALID_VALUE
+    assert L.pent_solve_noalloc(None, buf, 1, 1, None) == pb.INVALID_VALUE
     assert L.pent_get_factors(None, buf, buf, buf, buf) == pb.INVALID_VALUE
     assert L.pent_get_diagonals(None, buf, buf, buf, buf, buf) == pb.INVALID_VALUE
     assert L.pent_size(None) == -1
@@ -76,6 +77,7 @@ def test_forged_handle_is_rejected():
     junk = (ctypes.c_uint64 * 64)()
     h = ctypes.cast(junk, ctypes.c_void_p)
     assert L.pent_solve(h, None, 0, 0, None) == pb.INVALID_VALUE
+    assert L.pent_solve_noalloc(h, None, 0, 0, None) == pb.INVALID_VALUE
     assert L.pent_destroy(h) == pb.INVALID_VALUE
     assert L.pent_size(h) == -1
 
