@@ -8,9 +8,14 @@ seed 2), factor once, every step solves A C^{k+1} = C^k in place.  A step is
 one full solve of all 65536 systems; inputs are resident in HBM before the
 timed region.  Prints one JSON line.
 
-The same line carries a ``precision`` object: FP64 sweeps against FP32
-right-hand-side streams (FP64 arithmetic, with 0 and 1 refinement steps) on
-N=8192 with 131072 right-hand sides, sigma=1e2.
+The same line carries a ``configs`` object with every other configuration,
+each timed in this run and followed by its status check (a single-pass wait
+that ran out makes the run fail): the plain N=256 solve, the 2-D
+Cahn-Hilliard run, the precision comparison (FP64 sweeps against FP32
+right-hand-side streams with 0 and 1 refinement steps, N=8192, 131072
+right-hand sides, sigma in {1, 1e2, 1e4}), the 48-matrix group run,
+periodic Crank-Nicolson, per-system matrices against rocSPARSE, and the copy
+ceiling.  ``--headline-only`` skips them.
 
 Other workloads (for tuning runs): ``plain`` (N=256, 256 RHS), ``precision``
 (all three sigma), ``shape`` (any n / batch), ``copy`` (device copy),
@@ -114,6 +119,13 @@ def run_hyperdiff(args, torch):
     probe0 = C0[:, probe].copy()
     T = torch.from_numpy(C0).cuda()
     stream = torch.cuda.current_stream()
+    # factorisation (excluded from the timed steps, as in the paper): the
+    # first call also loads the library's device code; the second is the
+    # cost of a factorisation (allocation, assembly, the serial recurrence,
+    # the sweep and segment tables, one synchronisation)
+    t_fac0 = time.perf_counter()
+    pb.Plan.factor_d4(n, sigma).close()
+    fac_cold_s = time.perf_counter() - t_fac0
     t_fac0 = time.perf_counter()
     plan = pb.Plan.factor_d4(n, sigma)
     fac_s = time.perf_counter() - t_fac0
@@ -132,6 +144,7 @@ def run_hyperdiff(args, torch):
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
+    plan.check()  # raises if a single-pass wait ran out (its values would be NaN)
     # parity of the probe systems after all warmup + timed steps
     X = T[:, torch.from_numpy(probe).cuda()].cpu().numpy()
     ref = workloads.hyperdiffusion(n, sigma, probe0, args.warmup + args.steps)
@@ -155,14 +168,99 @@ def run_hyperdiff(args, torch):
                       traffic=tr),
         row_updates_per_s=solves_s * n,
         factor_ms=fac_s * 1e3,
+        factor_first_call_ms=fac_cold_s * 1e3,
         parity=dict(probe_systems=len(probe), max_rel_err_vs_oracle=err),
     )
-    if not args.no_precision:
-        del T
-        torch.cuda.empty_cache()
-        out["precision"] = precision_compare(torch, 1e2)
+    del T
+    torch.cuda.empty_cache()
+    if not args.headline_only:
+        out["configs"] = all_configs(args, torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline_hyperdiff(n, sigma, C0)
+    return out
+
+
+def _sub(args, **kw):
+    ns = argparse.Namespace(**vars(args))
+    ns.schedule = ""
+    for k, v in kw.items():
+        setattr(ns, k, v)
+    return ns
+
+
+def _roof(r):
+    rf = r.get("roofline")
+    if not rf:
+        return None
+    return {k: rf[k] for k in ("achieved", "frac", "traffic") if k in rf}
+
+
+def all_configs(args, torch):
+    """Every other configuration of the benchmark set, compact: the small
+    plain solve, the 2-D Cahn-Hilliard run, the precision comparison at the
+    three sigmas, the 48-matrix group run, periodic Crank-Nicolson, per-system
+    matrices against rocSPARSE, and the copy ceiling measured in the same
+    run.  Each timed loop is followed by the handle's status check."""
+    res = {}
+    r = run_plain(_sub(args, steps=200, warmup=5), torch)
+    res["plain"] = dict(us_per_solve=r["ms_per_step"] * 1e3, solves_per_s=r["value"],
+                        schedule=r["config"]["schedule"], parity=r["parity"])
+    r = run_cahn2d(_sub(args, steps=50, warmup=2), torch)
+    res["cahn2d"] = dict(steps=r["steps"], ms_per_step=r["ms_per_step"], solves_per_s=r["value"],
+                         roofline=_roof(r), parity=r["parity"])
+    prec = {}
+    for sg in (1.0, 1e2, 1e4):
+        prec[f"sigma={sg:g}"] = precision_compare(torch, sg)
+    prec["note"] = ("FP32 is the storage precision of the right-hand-side stream; the factors, "
+                    "every operation and x are FP64, so the k=0 solve already has FP64 accuracy "
+                    "(same eta as the FP64 solve) and is the form that beats FP64 (12 instead of "
+                    "16 B per unknown); a correction adds a second pass over x")
+    res["precision"] = prec
+    r = run_group(_sub(args, steps=200, warmup=1), torch)
+    res["group"] = dict(graph_steps=r["steps"], ms_per_step=r["ms_per_step"],
+                        solves_per_s=r["value"], roofline=_roof(r),
+                        unknowns_per_step=r["config"]["unknowns_per_step"],
+                        kernel_variant=r["config"]["kernel_variant"],
+                        max_rel_err_vs_oracle=r["persistent"]["max_rel_err_vs_oracle"],
+                        per_matrix_ms_per_step=r["per_matrix"]["ms_per_step"],
+                        speedup_of_persistent=r["per_matrix"]["speedup_of_persistent"])
+    r = run_periodic(_sub(args, steps=100, warmup=3), torch)
+    res["periodic"] = dict(ms_per_step=r["ms_per_step"], solves_per_s=r["value"],
+                           form=r["config"]["form"], roofline=_roof(r), parity=r["parity"],
+                           other_form=r["other_form"])
+    r = run_rewrite(_sub(args, steps=20, warmup=2), torch)
+    g = r["rocsparse_gpsv"] or {}
+    res["rewrite"] = dict(ms_per_step=r["ms_per_step"], solves_per_s=r["value"],
+                          roofline_56B=_roof(r), roofline_104B=r["kernel_plan_roofline"],
+                          parity=r["parity"],
+                          rocsparse_gpsv_ms_with_restore=g.get("ms_per_step_with_restore"),
+                          rocsparse_gpsv_ms_solve_only=g.get("ms_solve_only"),
+                          speedup_over_rocsparse=g.get("speedup_of_rewrite"))
+    res["copy_ceiling"] = copy_ceiling(torch)
+    return res
+
+
+def copy_ceiling(torch, reps=20):
+    """Read+write bandwidth of plain copies of the hyperdiffusion state (2
+    GiB, FP64) in this run: torch's device copy, and the library's copy
+    through the single pass's blocks (64 systems x 64 rows per wave, four
+    waves down the rows, in place)."""
+    from paper_1807_07382_amd import inputs
+    from paper_1807_07382_amd import pentbatch as pb
+    n, batch = inputs.HYPERDIFF["n"], inputs.HYPERDIFF["batch"]
+    src = torch.empty((n, batch), dtype=torch.float64, device="cuda").uniform_()
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    nbytes = 2 * src.numel() * 8
+    out = {}
+    dst.copy_(src)
+    ms = _timed(torch, stream, lambda: dst.copy_(src), reps)
+    out["torch_copy_GBs"] = nbytes / (ms / 1e3) / 1e9
+    pb.stream_copy(dst, dst, stream)
+    ms = _timed(torch, stream, lambda: pb.stream_copy(dst, dst, stream), reps)
+    out["single_pass_blocks_GBs"] = nbytes / (ms / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
     return out
 
 
@@ -235,6 +333,7 @@ def precision_compare(torch, sigma, reps=10, seed=4):
                 ms=ms, solves_per_s=m / (ms / 1e3), bytes_per_unknown=solve32 if k == 0 else refine1,
                 max_eta=float(eta.max()), max_rel_err_vs_oracle=rel_err(X),
                 speedup_vs_fp64=ms64 / ms)
+        plan.check()
     del F32, F64, X, work
     torch.cuda.empty_cache()
     return out
@@ -285,6 +384,7 @@ def run_group(args, torch):
             T.copy_(I)
         torch.cuda.synchronize()
         ms = _timed(torch, s, lambda: graph.launch(stream=s), 1)
+        g.check()
         # parity: the state after one replay (= steps implicit steps)
         errs = []
         for k, cols in probe:
@@ -337,6 +437,7 @@ def run_cahn2d(args, torch):
         pb.ch2d_step(plan, plan, C, R, dt, h, stream)
     C.copy_(C0)
     ms = _timed(torch, stream, lambda: pb.ch2d_step(plan, plan, C, R, dt, h, stream), steps)
+    plan.check()
     # parity of one instance after `steps` steps
     sub = np.ascontiguousarray(w["C0"][:, :1, :])
     ref = workloads.ch_run(sub, gam[:1], sigma, steps)
@@ -380,13 +481,25 @@ def run_plain(args, torch):
     ev1.record(stream)
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1)
+    plan.check()
+    sched = plan.schedule_for(F.shape[1])
+    X = T.cpu().numpy()
     plan.close()
+    import oracle
+    ref = oracle.solve(oracle.assemble_d4(n, sigma), F)
+    for _ in range(args.warmup + args.steps - 1):
+        ref = oracle.solve(oracle.assemble_d4(n, sigma), ref)
+    err = float(np.max(np.max(np.abs(X - ref), axis=0) / np.max(np.abs(ref), axis=0)))
     ms_step = ms / args.steps
     return dict(metric=METRIC, value=F.shape[1] / (ms_step / 1e3), unit="RHS-solves/s",
                 n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms_step,
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
                 data="synthetic", config=dict(workload="plain", n=n, systems=F.shape[1],
-                                              sigma=sigma))
+                                              sigma=sigma,
+                                              schedule=SCHEDULE_NAMES[sched[0]] +
+                                              (f"{sched[1]}" if sched[0] in (2, 4) else "")),
+                parity=dict(systems=F.shape[1], solves=args.warmup + args.steps,
+                            max_rel_err_vs_oracle=err))
 
 
 def run_copy(args, torch):
@@ -439,6 +552,7 @@ def run_shape(args, torch):
     ev1.record(stream)
     torch.cuda.synchronize()
     ms_step = ev0.elapsed_time(ev1) / args.steps
+    plan.check()
     plan.close()
     gbs = BYTES_PER_UNKNOWN_FP64 * n * batch / (ms_step / 1e3) / 1e9
     return dict(metric=METRIC, value=batch / (ms_step / 1e3), unit="RHS-solves/s", n_gpus=1,
@@ -474,6 +588,7 @@ def run_periodic(args, torch):
     for _ in range(args.warmup):
         step()
     ms = _timed(torch, stream, step, steps)
+    cy.check()
     X = state["C"][:, torch.from_numpy(probe).cuda()].cpu().numpy()
     ref = cyclic.cn_run(sigma, w["C0"][:, probe], args.warmup + steps)
     err = float(np.max(np.max(np.abs(X - ref), axis=0) / np.max(np.abs(ref), axis=0)))
@@ -482,6 +597,7 @@ def run_periodic(args, torch):
     cy.set_schedule(other, 64)
     step()
     ms_other = _timed(torch, stream, step, max(5, steps // 5))
+    cy.check()
     cy.close()
     names = {1: "stencil, E-solve, update (three passes)", 2: "single pass"}
     alg = BYTES_PER_UNKNOWN_FP64 * n * batch  # one CN step: read C once, write C' once
@@ -594,15 +710,21 @@ def run_rewrite(args, torch):
         L.rocsparse_destroy_handle(h)
     except (OSError, RuntimeError) as exc:
         gpsv = dict(error=str(exc))
-    alg = 104 * n * batch  # read 5 diagonals + f, write gamma, delta, g; read them back, write x
+    # the method's minimum: five diagonals and f read, x written (56 B per
+    # unknown); the kernel's own plan also writes gamma, delta and g and reads
+    # them back (104 B)
+    alg = 56 * n * batch
     gbs = alg / (ms / 1e3) / 1e9
+    gbs104 = 104 * n * batch / (ms / 1e3) / 1e9
     return dict(metric=METRIC, value=batch / (ms / 1e3), unit="RHS-solves/s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=ms, higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
                 config=dict(workload="rewrite", n=n, systems=batch,
                             matrices="one per system, refactored every call"),
                 roofline=dict(bound="hbm", achieved=gbs, peak=PEAK_HBM_GBS, unit="GB/s",
-                              frac=gbs / PEAK_HBM_GBS, traffic=None),
+                              frac=gbs / PEAK_HBM_GBS, traffic=None, bytes_per_unknown=56),
+                kernel_plan_roofline=dict(bytes_per_unknown=104, achieved=gbs104,
+                                          frac=gbs104 / PEAK_HBM_GBS),
                 parity=dict(probe_systems=len(cols), max_rel_err_vs_oracle=err),
                 rocsparse_gpsv=gpsv)
 
@@ -620,8 +742,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="hyperdiff", choices=sorted(WORKLOADS))
     ap.add_argument("--schedule", default="", help="force kind,seg_rows (tuning)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-precision", action="store_true",
-                    help="skip the FP32-stream vs FP64 comparison object")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="hyperdiff only: skip the other configurations (profiling runs)")
     ap.add_argument("--n", type=int, default=1024, help="shape workload: rows")
     ap.add_argument("--batch", type=int, default=32768, help="shape workload: systems")
     ap.add_argument("--sigma", type=float, default=200.0, help="shape workload: sigma")
