@@ -236,8 +236,43 @@ def all_configs(args, torch):
                           rocsparse_gpsv_ms_with_restore=g.get("ms_per_step_with_restore"),
                           rocsparse_gpsv_ms_solve_only=g.get("ms_solve_only"),
                           speedup_over_rocsparse=g.get("speedup_of_rewrite"))
+    res["hyperdiff_tiled_layout"] = tiled_layout(torch)
     res["copy_ceiling"] = copy_ceiling(torch)
     return res
+
+
+def tiled_layout(torch, steps=50):
+    """The hyperdiffusion solve (N = 4096, 65536 systems) with each
+    64-system tile its own contiguous interleaved block (pent_solve_tiled):
+    ms per solve, and the bits of every system against the ordinary layout
+    after one solve."""
+    import ctypes
+    from paper_1807_07382_amd import inputs
+    from paper_1807_07382_amd import pentbatch as pb
+    n, batch, sigma = inputs.HYPERDIFF["n"], inputs.HYPERDIFF["batch"], inputs.HYPERDIFF["sigma"]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(2)
+    F = torch.empty((n, batch), dtype=torch.float64, device="cuda").uniform_(-1, 1, generator=g)
+    T = F.reshape(n, batch // 64, 64).permute(1, 0, 2).contiguous()
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    L = pb.lib()
+    with pb.Plan.factor_d4(n, sigma) as plan:
+        def solve():
+            st = L.pent_solve_tiled(plan.handle, ctypes.c_void_p(T.data_ptr()), batch, 64, n * 64, sp)
+            if st != pb.OK:
+                raise pb.PentError(st, "solve_tiled")
+        solve()
+        plan.solve_(F, stream)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(T.permute(1, 0, 2).reshape(n, batch), F))
+        ms = _timed(torch, stream, solve, steps)
+        plan.check()
+    gbs = BYTES_PER_UNKNOWN_FP64 * n * batch / (ms / 1e3) / 1e9
+    del F, T
+    torch.cuda.empty_cache()
+    return dict(ms_per_solve=ms, solves_per_s=batch / (ms / 1e3), achieved_GBs=gbs,
+                frac=gbs / PEAK_HBM_GBS, bits_equal_interleaved=same)
 
 
 def copy_ceiling(torch, reps=20):

@@ -105,6 +105,22 @@ int pent_solve(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream
  * race: serialise them. */
 int pent_solve_noalloc(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream);
 
+/* Same solve for right-hand sides stored in tiles of 64 systems, each tile
+ * its own interleaved block (the layout of Sec. 2.6 applied per tile):
+ * element (i, j) at F[(j / 64) * tile_stride + i * ld + j % 64], with
+ * ld >= 64 and tile_stride >= (n - 1) * ld + 64; with ld = 64 and
+ * tile_stride = 64 n a tile's n rows are one contiguous run, which the
+ * single pass streams with fewer open DRAM pages than rows a whole batch
+ * apart.  A partial last tile needs its 64 columns of storage; columns past
+ * the batch are not written.  Results are the bits pent_solve gives the
+ * same systems.  Runs as the single pass only: PENT_NOT_SUPPORTED (before
+ * any HIP call) where pent_solve would use another schedule.
+ * PENT_INVALID_VALUE for a bad handle, batch < 0, ld or tile_stride too
+ * small, or F == NULL with batch > 0.  Allocates stream-ordered scratch on
+ * `stream`; a wait that runs out is reported by pent_check. */
+int pent_solve_tiled(pent_handle h, double *F, int64_t batch, int64_t ld, int64_t tile_stride,
+                     void *stream);
+
 /* Same solve for system-major storage: system j occupies n contiguous
  * doubles at F + j*ld (element (i, j) at F[j*ld + i]), ld >= n.  This is the
  * layout of the second direction of an alternating-direction (ADI-style)

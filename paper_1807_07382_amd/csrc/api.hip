@@ -45,6 +45,8 @@ void free_plan(pent_plan *p)
     if (p->d_bwd) (void)hipFree(p->d_bwd);
     for (auto &c : p->seg)
         if (c.d_seg) (void)hipFree(c.d_seg);
+    for (auto &c : p->grp)
+        if (c.d_grp) (void)hipFree(c.d_grp);
     if (p->d_scan) (void)hipFree(p->d_scan);
     if (p->d_trec) (void)hipFree(p->d_trec);
     if (p->d_err) (void)hipFree(p->d_err);
@@ -104,6 +106,7 @@ void query_onepass_cap(pent_plan *p, int seg_rows)
 }
 
 const SegRec *seg_cache_locked(pent_plan *p, int seg_rows, int *st, bool sync);
+const GrpRec *grp_cache_locked(pent_plan *p, int seg_rows, int waves, int *st, bool sync);
 bool tile_cache(pent_plan *p, int rows, const ScanRec **scan, const double **trec, int *st,
                 bool sync);
 
@@ -123,7 +126,10 @@ pent_handle finish_factor(pent_plan *p)
     if (e == hipSuccess) e = launch_anorm(p->d_diag, p->n, p->d_anorm, 0);
     if (e == hipSuccess) {
         std::lock_guard<std::mutex> lk(p->mu);
-        if (!seg_cache_locked(p, 64, &st, false) || !seg_cache_locked(p, 32, &st, false))
+        // and the group constants of the many-matrix single pass (64-row
+        // segments, four per group)
+        if (!seg_cache_locked(p, 64, &st, false) || !seg_cache_locked(p, 32, &st, false) ||
+            !grp_cache_locked(p, 64, 4, &st, false))
             e = hipErrorUnknown;
     }
     if (e == hipSuccess && tile_rows_for(p->n) > 0) {
@@ -186,6 +192,49 @@ const SegRec *seg_cache(pent_plan *p, int seg_rows, int *st)
 {
     std::lock_guard<std::mutex> lk(p->mu);
     return seg_cache_locked(p, seg_rows, st);
+}
+
+// Group constants of the single pass for seg_rows-row segments, `waves`
+// per group, built once per handle from the segment constants (same stream
+// and synchronisation rules as seg_cache_locked).
+const GrpRec *grp_cache_locked(pent_plan *p, int seg_rows, int waves, int *st, bool sync = true)
+{
+    GrpCache *slot = nullptr;
+    for (auto &c : p->grp) {
+        if (c.d_grp && c.seg_rows == seg_rows && c.waves == waves) {
+            *st = PENT_OK;
+            return c.d_grp;
+        }
+        if (!c.d_grp && !slot) slot = &c;
+    }
+    if (!slot) {
+        *st = PENT_NOT_SUPPORTED;
+        return nullptr;
+    }
+    const SegRec *seg = seg_cache_locked(p, seg_rows, st, sync);
+    if (!seg) return nullptr;
+    const int64_t ngroups = (p->n + (int64_t)seg_rows * waves - 1) / ((int64_t)seg_rows * waves);
+    GrpRec *d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(GrpRec) * ngroups);
+    if (e == hipSuccess) e = launch_grp_prep(seg, waves, ngroups, d, 0);
+    if (e == hipSuccess && sync) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        if (d) (void)hipFree(d);
+        *st = hip_status(e);
+        return nullptr;
+    }
+    slot->seg_rows = seg_rows;
+    slot->waves = waves;
+    slot->ngroups = ngroups;
+    slot->d_grp = d;
+    *st = PENT_OK;
+    return d;
+}
+
+const GrpRec *grp_cache(pent_plan *p, int seg_rows, int waves, int *st)
+{
+    std::lock_guard<std::mutex> lk(p->mu);
+    return grp_cache_locked(p, seg_rows, waves, st);
 }
 
 // Interface-scan constants and record image of the resident-tile schedule
@@ -655,6 +704,8 @@ int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64
         pent_plan *p = g->plans[k];
         const SegRec *seg64 = seg_cache(p, 64, &st);
         if (!seg64) return st;
+        const GrpRec *grp64 = grp_cache(p, 64, 4, &st);
+        if (!grp64) return st;
         int kind, seg_rows;
         io_schedule(p, batch[k], true, &kind, &seg_rows);
         if ((kind == 2 || kind == 4) && !seg_cache(p, seg_rows, &st)) return st;
@@ -663,7 +714,7 @@ int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64
             const double *tr;
             if (!tile_cache(p, tile_rows_for(p->n), &sc, &tr, &st)) return st;
         }
-        mats[k] = GroupMat{p->d_fwd, p->d_bwd, seg64, F[k], p->n, p->npad, ld[k], batch[k]};
+        mats[k] = GroupMat{p->d_fwd, p->d_bwd, seg64, grp64, F[k], p->n, p->npad, ld[k], batch[k]};
     }
     for (size_t k = 0; k < cnt; k++)
         for (int64_t c0 = 0; c0 < batch[k]; c0 += 64)
@@ -972,6 +1023,28 @@ int pent_solve(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream
     if (batch == 0) return ret(PENT_OK);
     if (!F) return ret(PENT_INVALID_VALUE);
     return ret(solve_io_scratch(h, F, ld, F, ld, batch, (hipStream_t)stream));
+}
+
+int pent_solve_tiled(pent_handle h, double *F, int64_t batch, int64_t ld, int64_t tile_stride,
+                     void *stream)
+{
+    if (!valid(h) || batch < 0 || ld < 64 || tile_stride < (h->n - 1) * ld + 64)
+        return ret(PENT_INVALID_VALUE);
+    if (batch == 0) return ret(PENT_OK);
+    if (!F) return ret(PENT_INVALID_VALUE);
+    int kind, seg_rows, st;
+    io_schedule(h, batch, true, &kind, &seg_rows);
+    if (kind != 4) return ret(PENT_NOT_SUPPORTED);
+    const SegRec *seg = seg_cache(h, seg_rows, &st);
+    if (!seg) return ret(st);
+    hipStream_t s = (hipStream_t)stream;
+    void *summ = nullptr;
+    hipError_t e = hipMallocAsync(&summ, summ_bytes(h, kind, seg_rows, batch), s);
+    if (e != hipSuccess) return ret(hip_status(e));
+    e = launch_onepass(h->d_fwd, h->d_bwd, seg, h->n, seg_rows, F, false, ld, F, ld, batch, summ,
+                       h->d_err, s, tile_stride, tile_stride);
+    const hipError_t e2 = hipFreeAsync(summ, s);
+    return ret(hip_status(e != hipSuccess ? e : e2));
 }
 
 int pent_solve_noalloc(pent_handle h, double *F, int64_t batch, int64_t ld, void *stream)

@@ -225,7 +225,64 @@ __global__ void k_seg_prep(const FwdRec *__restrict__ fwd, const BwdRec *__restr
     seg[s] = out;
 }
 
+// C = A B for column-major 2x2 matrices, explicit fused multiply-adds.
+__device__ __forceinline__ void mat2_mul(const double *a, const double *b, double *c)
+{
+    const double c0 = fma(a[2], b[1], a[0] * b[0]), c1 = fma(a[3], b[1], a[1] * b[0]);
+    const double c2 = fma(a[2], b[3], a[0] * b[2]), c3 = fma(a[3], b[3], a[1] * b[2]);
+    c[0] = c0;
+    c[1] = c1;
+    c[2] = c2;
+    c[3] = c3;
+}
+
+// Group constants of the single pass (GrpRec) from the segment records of
+// segments [G*W, G*W + W) of each group G (the segment table is padded with
+// all-zero records past the matrix).  One lane, serial over the groups; a
+// few hundred matrix products per matrix, once per handle.
+__global__ void k_grp_prep(const SegRec *__restrict__ seg, int W, int64_t ngroups,
+                           GrpRec *__restrict__ grp)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int64_t G = 0; G < ngroups; G++) {
+        const SegRec *sg = seg + G * W;
+        // tg = Tf_{W-1} ... Tf_0, tbg = Tb_0 ... Tb_{W-1},
+        // cg = sum_i (Tb_0 ... Tb_{i-1}) Cg_i (Tf_{i-1} ... Tf_0)
+        double tg[4] = {1.0, 0.0, 0.0, 1.0}, bp[4] = {1.0, 0.0, 0.0, 1.0}, cg[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int i = 0; i < W; i++) {
+            double t[4], u[4];
+            mat2_mul(sg[i].cg, tg, t);  // Cg_i M_i
+            mat2_mul(bp, t, u);         // (Tb_0 ... Tb_{i-1}) Cg_i M_i
+            for (int k = 0; k < 4; k++) cg[k] = cg[k] + u[k];
+            mat2_mul(sg[i].tf, tg, tg);
+            mat2_mul(bp, sg[i].tb, bp);
+        }
+        for (int k = 0; k < 4; k++) {
+            grp[G].tg[k] = tg[k];
+            grp[G].tbg[k] = bp[k];
+            grp[G].cg[k] = cg[k];
+        }
+    }
+    // q_last = 0, q_G = cg_{G+1} + tbg_{G+1} q_{G+1} tg_{G+1}
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t G = ngroups - 1; G >= 0; G--) {
+        for (int k = 0; k < 4; k++) grp[G].q[k] = q[k];
+        if (G == 0) break;
+        double t[4], u[4];
+        mat2_mul(q, grp[G].tg, t);
+        mat2_mul(grp[G].tbg, t, u);
+        for (int k = 0; k < 4; k++) q[k] = grp[G].cg[k] + u[k];
+    }
+}
+
 }  // namespace
+
+hipError_t launch_grp_prep(const SegRec *d_seg, int waves, int64_t ngroups, GrpRec *d_grp,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_grp_prep, dim3(1), dim3(64), 0, s, d_seg, waves, ngroups, d_grp);
+    return hipGetLastError();
+}
 
 hipError_t launch_assemble_d4(double *d_diag, int64_t n, double sigma, hipStream_t s)
 {

@@ -83,6 +83,22 @@ struct alignas(128) SegRec {
     double pad[4];
 };
 
+// Per-group constants of the single-pass sweeps (a group = W consecutive
+// segments), column-major 2x2 matrices as in SegRec:
+//   tg  = Tf_last ... Tf_first: forward state in -> forward state out;
+//   tbg = Tb_first ... Tb_last: backward state in (from below) -> out (top);
+//   cg  = forward state in -> backward top state (zero right-hand side,
+//         zero state below);
+//   q   = response of the backward state entering the group from below to
+//         the forward state leaving it, through all later groups:
+//         q_last = 0, q_G = cg_{G+1} + tbg_{G+1} q_{G+1} tg_{G+1}.
+struct alignas(128) GrpRec {
+    double tg[4];
+    double tbg[4];
+    double cg[4];
+    double q[4];
+};
+
 // Interface-scan constants of the resident-tile schedule, one record per
 // segment (64 segments): p[l] and q[l] are the products of 2^l consecutive
 // forward / backward transfer matrices ending (p) or starting (q) at the
@@ -104,6 +120,7 @@ struct GroupMat {
     const FwdRec *fwd;
     const BwdRec *bwd;
     const SegRec *seg64;  // transfer matrices for 64-row segments
+    const GrpRec *grp64;  // group constants for 64-row segments, four per group
     double *F;          // right-hand sides, batch-fastest, overwritten in place
     int64_t n, npad, ld, batch;
 };
@@ -149,6 +166,15 @@ struct SegCache {
     SegRec *d_seg = nullptr;
 };
 
+// Group constants of the single pass for (seg_rows, waves per group).
+constexpr int kMaxGrpCaches = 6;
+struct GrpCache {
+    int seg_rows = 0;
+    int waves = 0;
+    int64_t ngroups = 0;
+    GrpRec *d_grp = nullptr;
+};
+
 }  // namespace pent
 
 struct pent_plan {
@@ -172,6 +198,7 @@ struct pent_plan {
     int tst_cap;             // ... of its form with the 2-D Cahn-Hilliard stencil
     std::mutex mu;           // guards seg caches (lazy build)
     pent::SegCache seg[pent::kMaxSegCaches];
+    pent::GrpCache grp[pent::kMaxGrpCaches];  // lazily built, guarded by mu
     pent::ScanRec *d_scan;   // resident-tile scan constants (64 records), lazily built
     double *d_trec;          // resident-tile record image (5 x 64 x rows doubles)
     int scan_rows;           // rows per lane they were built for
@@ -254,6 +281,10 @@ hipError_t launch_factor(const double *d_diag, int64_t n, int64_t npad, double *
                          FwdRec *d_fwd, BwdRec *d_bwd, int64_t *d_bad, hipStream_t s);
 hipError_t launch_seg_prep(const FwdRec *d_fwd, const BwdRec *d_bwd, int64_t n, int seg_rows,
                            SegRec *d_seg, hipStream_t s);
+// Group constants for groups of `waves` segments from the segment table
+// (which holds at least ngroups * waves records).
+hipError_t launch_grp_prep(const SegRec *d_seg, int waves, int64_t ngroups, GrpRec *d_grp,
+                           hipStream_t s);
 
 // depth: rows prefetched per block (8, 16 or 32; anything else means 16)
 hipError_t launch_lane_sweep(const FwdRec *fwd, const BwdRec *bwd, int64_t n, double *F,
@@ -340,7 +371,7 @@ hipError_t launch_onepass_fix(const FwdRec *fwd, const BwdRec *bwd, const SegRec
 hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg, int64_t n,
                           int seg_rows, const void *Fin, bool f32, int64_t ldf, double *X,
                           int64_t ldx, int64_t batch, void *scratch, unsigned int *err,
-                          hipStream_t s);
+                          hipStream_t s, int64_t tsf = 64, int64_t tsx = 64);
 
 // ---- measurement (copy.hip): dst = src through the single pass's blocks ----
 hipError_t launch_block_copy(const double *src, double *dst, int64_t n, int64_t batch, int64_t lds,

@@ -1,7 +1,8 @@
 // lookback.h -- device pieces of the single-pass sweeps (onepass.hip,
 // cyclic.hip): ticketing, status words, the interface link, the sweeps of a
-// block held in registers, and the phases of a workgroup of W such blocks
-// (group_phases) with its look-back and look-ahead (group_carry).
+// block held in registers, and the phases of a workgroup of W such blocks in
+// two forms: two-phase (group_phases, with its look-back and look-ahead
+// group_carry) and single-wait (group_phases_1w, group_wait).
 //
 // By linearity (Sec. 2.4's recurrences are affine in the carried pair), a
 // segment's outgoing forward state is
@@ -132,6 +133,27 @@ __device__ __forceinline__ void forward(double (&v)[K], CFwd fwd, int64_t r0, do
     }
 }
 
+// Adds to v the forward sweep's response to the incoming state (p2, p1)
+// with a zero right-hand side: g = g0 + h, h_k = -ap h_{k-2} - bp h_{k-1}
+// (the sweep is affine in its incoming state).
+template <int K, bool LREC = false>
+__device__ __forceinline__ void respond(double (&v)[K], CFwd fwd, int64_t r0, double p2, double p1,
+                                        const FwdRec *lf = nullptr)
+{
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        if (!LREC && k % kSchedRows == 0) {
+            __builtin_amdgcn_sched_barrier(0);
+            fwd = fresh(fwd);
+        }
+        const double ap = LREC ? lf[k].ap : fwd[r0 + k].ap, bp = LREC ? lf[k].bp : fwd[r0 + k].bp;
+        const double h = fma(-bp, p1, -ap * p2);
+        v[k] += h;
+        p2 = p1;
+        p1 = h;
+    }
+}
+
 // Back substitution over the segment from (q1, q2) = (x_{r0+K}, x_{r0+K+1});
 // on exit (q1, q2) = (x_{r0}, x_{r0+1}).  STORE writes x over v.
 template <int K, bool STORE, bool LREC = false>
@@ -230,15 +252,21 @@ __device__ __forceinline__ void group_matrix(CSeg seg, int64_t s0, double &m0, d
 constexpr int kStage = 16;
 constexpr int kCoherentLoad = 16;  // cache-policy bits of a direct load: sc1, as xload
 
-// LDS of a group of W waves (declared by each kernel, as arrays: the
-// direct loads need plain LDS addresses): sh [W + 1][2][64], the waves'
-// carries; agg [kStage][128] and mat [kStage][W][4], the replay's staging
-// area (aggregate pairs of the tile's 64 systems, and the W segment matrices
-// of each of those groups).
-#define PENT_GROUP_LDS(W)                          \
-    __shared__ double sh[(W) + 1][2][64];          \
-    __shared__ double agg[pent::lb::kStage][128];  \
-    __shared__ double mat[pent::lb::kStage][(W)][4]
+// LDS of a group of W waves (declared by each kernel, as arrays: the direct
+// loads need plain LDS addresses): sh[W + 1][4][64], per wave the states it
+// hands on (rows 0, 1 forward, 2, 3 backward; row W the group's); agg
+// [kStage][128] and mat, the replay's staging area (aggregate pairs of the
+// tile's 64 systems, and the link matrices of those groups: kStage x W x 4
+// segment matrices in the two-phase form, 2 kStage x 4 group matrices in
+// the single-wait form); ucon: the group's W segment records and its group
+// record (single-wait form, stage_consts).
+#define PENT_GROUP_LDS(W)                                                      \
+    __shared__ double sh[(W) + 1][4][64];                                      \
+    __shared__ double agg[pent::lb::kStage][128];                              \
+    __shared__ double mat[pent::lb::kStage * ((W) > 2 ? (W) : 2) * 4];         \
+    __shared__ double ucon[((W) * 16 + 16 + 127) / 128 * 128]
+
+typedef __attribute__((address_space(4))) const GrpRec *CGrp;
 
 // One group's aggregate pair for the tile's 64 systems (1 KB: row ra then
 // row ra+1 of its exchange block) straight into LDS row dst, without
@@ -252,8 +280,6 @@ __device__ __forceinline__ void stage_load(const double *blk, double *dst)
         (__attribute__((address_space(3))) void *)(uint32_t)(uintptr_t)dst, 16, 0, kCoherentLoad);
 }
 
-
-
 // Group-level look-back (FWD) or look-ahead: the incoming carry of group g
 // of the tile whose first group unit is u0, given this group's aggregate
 // (c0, c1), which is posted first.  A wait that runs out raises *err and
@@ -265,10 +291,11 @@ template <int W, bool FWD>
 __device__ __forceinline__ void group_carry(CSeg seg, int g, int ngroups, unsigned int u0,
                                             unsigned int *st_word, double *ex, unsigned int *err,
                                             double c0, double c1, double &y0, double &y1,
-                                            double (*agg)[128], double (*mat)[W][4])
+                                            double (*agg)[128], double *matp)
 {
     const int lane = threadIdx.x & 63;
     const int ra = FWD ? 0 : 4;  // aggregate rows
+    double (*mat)[W][4] = (double (*)[W][4])matp;
     double *me = ex + (int64_t)(u0 + g) * (kExRows * 64) + lane;
     // the aggregate goes out first: later groups can use it while this one
     // is still looking
@@ -408,8 +435,8 @@ __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd,
                                              int64_t r0, int w, int g, int ngroups,
                                              unsigned int u0, unsigned int *fst,
                                              unsigned int *bst, double *ex, unsigned int *err,
-                                             double (*sh)[2][64], double (*agg)[128],
-                                             double (*mat)[W][4], const FwdRec *lf = nullptr,
+                                             double (*sh)[4][64], double (*agg)[128],
+                                             double *mat, const FwdRec *lf = nullptr,
                                              const BwdRec *lb = nullptr)
 {
     const int lane = threadIdx.x & 63;
@@ -485,6 +512,275 @@ __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd,
         for (int i = W - 1; i > w; i--)
             link(sh[i][0][lane], sh[i][1][lane], seg[s0 + i].tb[0], seg[s0 + i].tb[1],
                  seg[s0 + i].tb[2], seg[s0 + i].tb[3], z0, z1);
+        backward<K, true, LREC>(v, bwd, r0, z0, z1, lb);
+    }
+    // x is complete here: keep the compiler from sinking the sweep into the
+    // block that stores x (past a caller's waits, with every coefficient
+    // held live across them)
+#pragma unroll
+    for (int k = 0; k < K; k++) asm volatile("" : "+v"(v[k]));
+}
+
+
+// ---- single-wait form (group_phases_1w), used where tiles have few groups
+// (the many-matrix kernel).  In the two-phase form above the backward
+// look-ahead waits for the forward chain to resolve first; here both chains
+// are resolved from quantities every group forms from its own block alone,
+// so a group waits once, for its tile's other groups to have loaded their
+// blocks, and never for another group's carries.  With segment i of a group entered by forward state y_i and left (upward) by
+// backward state up_i = a0_i + Cg_i y_i + Tb_i z_i, where a0_i is the top of
+// a zero-start back substitution over the zero-start forward values g0 (the
+// true forward values are g0 + the response to y_i), the groups G of a tile
+// satisfy
+//     Y_{G+1} = E_G + TG_G Y_G,                   Y_0 = 0,
+//     Zin_G   = A0_{G+1} + CG_{G+1} Y_{G+1} + TBG_{G+1} Zin_{G+1},
+//                                                 Zin_last = 0,
+// with E_G, A0_G the group's states for zero carries, Zin_G the backward
+// state entering G from below and TG, TBG, CG constants of A (GrpRec).
+// Writing Zin_G = P_G + Q_G Y_{G+1} (Q constant) gives
+//     P_G = A'_{G+1} + TBG_{G+1} P_{G+1},   A'_H = A0_H + TBG_H Q_H E_H,
+// a scan of the same form as the forward one, over aggregates A' that need
+// no forward carry.  So every group posts (E_G, A'_G) right after its
+// zero-start sweeps, then looks back for Y_G and ahead for P_G (decoupled:
+// it replays aggregates back to the nearest posted inclusive value, Y_{G'}
+// or P_{G'}), and posts its own inclusive values.  Each link is evaluated by
+// one function in one order, with the group constants from one table, so a
+// carry has the same bits whichever group produced it.
+
+// The W segment records of group g (from segment s0) and its group record
+// into LDS (ucon: W x 16 doubles, then 16), by direct loads of 1 KB: lane l
+// of load k moves 16-byte chunk 64 k + l (chunks past the records repeat
+// the group record into the unused tail).  Issued after the block's loads,
+// they land with them (loads complete in order).
+template <int W>
+__device__ __forceinline__ void stage_consts(const SegRec *seg, const GrpRec *grp, int64_t s0, int g,
+                                             double *ucon)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < (W * 8 + 8 + 63) / 64; k++) {
+        const int c = 64 * k + lane;  // 16-byte chunk of ucon
+        const char *src = c < W * 8 ? (const char *)(seg + s0) + 16 * c
+                                    : (const char *)(grp + g) + 16 * ((c - W * 8) & 7);
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                         (__attribute__((address_space(3))) void *)(uint32_t)(uintptr_t)(ucon + 128 * k),
+                                         16, 0, 0);
+    }
+}
+
+// (z0, z1) <- (a0, a1) + C (y0, y1) + T (z0, z1): the upward state of a
+// segment from its zero-start top state a, its forward state in y and the
+// backward state below it z, one fixed order of fused multiply-adds.
+__device__ __forceinline__ void up_link(double a0, double a1, double c0, double c1, double c2,
+                                        double c3, double y0, double y1, double t0, double t1,
+                                        double t2, double t3, double &z0, double &z1)
+{
+    const double n0 = fma(t2, z1, fma(t0, z0, fma(c2, y1, fma(c0, y0, a0))));
+    const double n1 = fma(t3, z1, fma(t1, z0, fma(c3, y1, fma(c1, y0, a1))));
+    z0 = n0;
+    z1 = n1;
+}
+
+// Group-level look-back (FWD: the forward state Y_g entering group g) or
+// look-ahead (P_g of the backward scan) of the tile whose first unit is u0,
+// once every group has posted its aggregates.  Waits until a contiguous run
+// of posted statuses reaches an inclusive one (2), then replays the
+// aggregates between, innermost first.  A wait that runs out raises *err
+// and returns a NaN carry, so every value that depends on it (this tile's
+// x, the carries it posts) comes out NaN instead of a plausible wrong
+// number.  Exchange rows: forward 0,1 aggregate E, 2,3 inclusive Y;
+// backward 4,5 aggregate A', 6,7 inclusive P.
+template <bool FWD>
+__device__ __forceinline__ void group_wait(CGrp grp, int g, int ngroups, unsigned int u0,
+                                           unsigned int *st_word, double *ex, unsigned int *err,
+                                           double &y0, double &y1, double (*agg)[128],
+                                           double (*mat)[4])
+{
+    const int lane = threadIdx.x & 63;
+    const int ra = FWD ? 0 : 4;  // aggregate rows
+    int base = FWD ? g - 1 : g + 1, pstar = base;
+    bool timed_out = false;
+    for (int spin = 0;; spin++) {
+        const int p = FWD ? base - lane : base + lane;
+        const bool in = FWD ? p >= 0 : p < ngroups;
+        const unsigned int st = lane_status(st_word, (int64_t)u0 + p, in);
+        const unsigned long long incl = __ballot(st == 2);
+        const unsigned long long none = __ballot(in && st == 0);
+        if (incl != 0) {
+            const int l = __builtin_ctzll(incl);
+            if ((none & ((1ull << l) - 1)) == 0) {
+                pstar = FWD ? base - l : base + l;
+                break;
+            }
+        } else if (none == 0 && (FWD ? base >= 64 : base + 64 < ngroups)) {
+            base = FWD ? base - 64 : base + 64;
+            continue;
+        }
+        if (spin >= kSpin) {
+            atomicOr(err, 1u);
+            timed_out = true;
+            break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    // replay the groups between pstar and g, innermost first.  The replay
+    // is latency-bound and registers hold the block, so each round trip
+    // brings up to kStage groups' aggregates and link matrices into LDS at
+    // once; they are then linked in order.
+    const int cnt = FWD ? g - 1 - pstar : pstar - g - 1;
+    auto group_at = [&](int i) { return FWD ? pstar + 1 + i : pstar - 1 - i; };
+    const double *nb = ex + (int64_t)(u0 + pstar) * (kExRows * 64) + lane;
+    y0 = xload(&nb[(ra + 2) * 64]);
+    y1 = xload(&nb[(ra + 3) * 64]);
+    for (int c = 0; c < cnt; c += kStage) {
+        const int m = cnt - c < kStage ? cnt - c : kStage;
+#pragma unroll
+        for (int i = 0; i < kStage; i++)
+            if (i < m) stage_load(ex + (int64_t)(u0 + group_at(c + i)) * (kExRows * 64) + ra * 64, agg[i]);
+        {
+            // link matrices, half a matrix (16 bytes) per lane: lane l lands
+            // at LDS byte 16 l of mat, so lanes 2i, 2i+1 fill mat[i] (lanes
+            // 32..63 repeat lanes 0..31 into the upper half); slots past the
+            // chunk reload its first group
+            const int i = (lane >> 1) & (kStage - 1);
+            const int q = group_at(c + (i < m ? i : 0));
+            const CDbl src = FWD ? &grp[q].tg[2 * (lane & 1)] : &grp[q].tbg[2 * (lane & 1)];
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                             (__attribute__((address_space(3))) void *)(uint32_t)(uintptr_t)&mat[0][0],
+                                             16, 0, 0);
+        }
+        store_fence();  // the direct loads have landed in LDS
+        // the serial links, without branches (slots past the chunk are
+        // computed and dropped), so the reads can run ahead of the chain
+#pragma unroll
+        for (int i = 0; i < kStage; i++) {
+            double n0 = y0, n1 = y1;
+            link(agg[i][lane], agg[i][64 + lane], mat[i][0], mat[i][1], mat[i][2], mat[i][3], n0, n1);
+            y0 = i < m ? n0 : y0;
+            y1 = i < m ? n1 : y1;
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);  // LDS reads before the next chunk's loads
+        __builtin_amdgcn_s_waitcnt(0xC07F);       // lgkmcnt(0)
+    }
+    if (timed_out) {
+        y0 = __builtin_nan("");
+        y1 = __builtin_nan("");
+    }
+}
+
+// The single-wait form of group_phases (see above): on exit v holds x.
+// Sweeps: zero-start forward (v becomes g0), zero-start
+// back substitution over g0 (its top state only), then, once the carries
+// are known, g = g0 + the response to the incoming forward state, and the
+// back substitution over g from the state below, which leaves x in v.
+template <int K, int W, bool LREC = false>
+__device__ __forceinline__ void group_phases_1w(double (&v)[K], CFwd fwd, CBwd bwd, CSeg seg, CGrp grp,
+                                             int64_t r0, int w, int g, int ngroups,
+                                             unsigned int u0, unsigned int *fst,
+                                             unsigned int *bst, double *ex, unsigned int *err,
+                                             double (*sh)[4][64], double (*agg)[128],
+                                             double *matp, double *ucon,
+                                             const FwdRec *lf = nullptr, const BwdRec *lb = nullptr)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t s0 = (int64_t)g * W;
+    double (*mat)[4] = (double (*)[4])matp;
+    if (w == 0) stage_consts<W>((const SegRec *)seg, (const GrpRec *)grp, s0, g, ucon);
+    // segment record i (tf at 0, cg at 4, tb at 8) and the group record (tg
+    // at 0, tbg at 4, q at 12) as staged in LDS
+    auto sc = [&](int i, int k) { return ucon[16 * i + k]; };
+    auto gc = [&](int k) { return ucon[16 * W + k]; };
+    {
+        double e0 = 0.0, e1 = 0.0, a0 = 0.0, a1 = 0.0;
+        forward<K, true, LREC>(v, fwd, r0, e0, e1, lf);
+        backward<K, false, LREC>(v, bwd, r0, a0, a1, lb);
+        sh[w][0][lane] = e0;
+        sh[w][1][lane] = e1;
+        sh[w][2][lane] = a0;
+        sh[w][3][lane] = a1;
+    }
+    __syncthreads();
+    if (w == 0) {
+        store_fence();  // the staged records have landed (they came in with the block)
+        // the group's states for zero carries: E (forward out) and A0
+        // (backward top, over the group's own forward values)
+        double yi0[W], yi1[W];
+        double E0 = 0.0, E1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < W; i++) {
+            yi0[i] = E0;
+            yi1[i] = E1;
+            link(sh[i][0][lane], sh[i][1][lane], sc(i, 0), sc(i, 1), sc(i, 2), sc(i, 3), E0, E1);
+        }
+        double A0 = 0.0, A1 = 0.0;
+#pragma unroll
+        for (int i = W - 1; i >= 0; i--)
+            up_link(sh[i][2][lane], sh[i][3][lane], sc(i, 4), sc(i, 5), sc(i, 6), sc(i, 7), yi0[i],
+                    yi1[i], sc(i, 8), sc(i, 9), sc(i, 10), sc(i, 11), A0, A1);
+        // the backward scan's aggregate A' = A0 + TBG (Q E)
+        double B0 = E0, B1 = E1;
+        link(0.0, 0.0, gc(12), gc(13), gc(14), gc(15), B0, B1);
+        link(A0, A1, gc(4), gc(5), gc(6), gc(7), B0, B1);
+        // post both aggregates (the first group's forward value and the last
+        // group's backward value are already inclusive)
+        const bool first = g == 0, last = g == ngroups - 1;
+        double *me = ex + (int64_t)(u0 + g) * (kExRows * 64) + lane;
+        xstore(&me[(first ? 2 : 0) * 64], E0);
+        xstore(&me[(first ? 3 : 1) * 64], E1);
+        xstore(&me[(last ? 6 : 4) * 64], B0);
+        xstore(&me[(last ? 7 : 5) * 64], B1);
+        store_fence();
+        __hip_atomic_store(&fst[u0 + g], first ? 2u : 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&bst[u0 + g], last ? 2u : 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // forward: Y_g, then Y_{g+1} = E + TG Y_g, posted as inclusive
+        double Y0 = 0.0, Y1 = 0.0;
+        if (!first) group_wait<true>(grp, g, ngroups, u0, fst, ex, err, Y0, Y1, agg, mat);
+        double N0 = Y0, N1 = Y1;
+        link(E0, E1, gc(0), gc(1), gc(2), gc(3), N0, N1);
+        if (!first && !last) {
+            xstore(&me[2 * 64], N0);
+            xstore(&me[3 * 64], N1);
+            publish(&fst[u0 + g], 2u);
+        }
+        // backward: P_g, then P_{g-1} = A' + TBG P_g, posted as inclusive
+        double P0 = 0.0, P1 = 0.0;
+        if (!last) group_wait<false>(grp, g, ngroups, u0, bst, ex, err, P0, P1, agg, mat);
+        if (!first && !last) {
+            double O0 = P0, O1 = P1;
+            link(B0, B1, gc(4), gc(5), gc(6), gc(7), O0, O1);
+            xstore(&me[6 * 64], O0);
+            xstore(&me[7 * 64], O1);
+            publish(&bst[u0 + g], 2u);
+        }
+        // the state entering the group from below: Zin = P + Q Y_{g+1}
+        double Z0 = N0, Z1 = N1;
+        link(P0, P1, gc(12), gc(13), gc(14), gc(15), Z0, Z1);
+        // every wave's states: forward through the waves above it, backward
+        // through the waves below it (over their true forward states); sh
+        // row i then holds wave i's (y, z)
+#pragma unroll
+        for (int i = 0; i < W; i++) {
+            yi0[i] = Y0;
+            yi1[i] = Y1;
+            if (i + 1 < W)
+                link(sh[i][0][lane], sh[i][1][lane], sc(i, 0), sc(i, 1), sc(i, 2), sc(i, 3), Y0, Y1);
+        }
+#pragma unroll
+        for (int i = W - 1; i >= 0; i--) {
+            const double a0 = sh[i][2][lane], a1 = sh[i][3][lane];
+            sh[i][0][lane] = yi0[i];
+            sh[i][1][lane] = yi1[i];
+            sh[i][2][lane] = Z0;
+            sh[i][3][lane] = Z1;
+            if (i > 0)
+                up_link(a0, a1, sc(i, 4), sc(i, 5), sc(i, 6), sc(i, 7), yi0[i], yi1[i], sc(i, 8),
+                        sc(i, 9), sc(i, 10), sc(i, 11), Z0, Z1);
+        }
+    }
+    __syncthreads();
+    respond<K, LREC>(v, fwd, r0, sh[w][0][lane], sh[w][1][lane], lf);
+    {
+        double z0 = sh[w][2][lane], z1 = sh[w][3][lane];
         backward<K, true, LREC>(v, bwd, r0, z0, z1, lb);
     }
     // x is complete here: keep the compiler from sinking the sweep into the

@@ -35,7 +35,7 @@ template <int K, int W, typename TI>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_onepass(
     const FwdRec *fwd_, const BwdRec *bwd_, const SegRec *seg_, int64_t n, int ngroups,
     const TI *Fin, int64_t ldf, double *X, int64_t ldx, int64_t batch, unsigned int *ctr,
-    unsigned int *fst, unsigned int *bst, double *ex, unsigned int *err)
+    unsigned int *fst, unsigned int *bst, double *ex, unsigned int *err, int64_t tsf, int64_t tsx)
 {
     PENT_GROUP_LDS(W);
     __shared__ unsigned int s_unit;
@@ -50,16 +50,17 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     const int t = (int)(u / (unsigned int)ngroups), g = (int)(u % (unsigned int)ngroups);
     const int64_t j = (int64_t)t * 64 + lane;
     const bool act = j < batch;
-    const int64_t jj = act ? j : 0;
+    // column j of tile t at t * ts + (j % 64); idle lanes read the tile's first column
+    const int64_t jf = (int64_t)t * tsf + (act ? lane : 0), jx = (int64_t)t * tsx + (act ? lane : 0);
     const int64_t r0 = ((int64_t)g * W + w) * K;
     const int64_t rem = n - r0;
     const int L = (int)(rem < 0 ? 0 : rem < K ? rem : K);
     double v[K];
-    load_rows<K, TI>(v, Fin + jj + (L > 0 ? r0 * ldf : 0), ldf, act ? L : 0);
+    load_rows<K, TI>(v, Fin + jf + (L > 0 ? r0 * ldf : 0), ldf, act ? L : 0);
     group_phases<K, W>(v, fwd, bwd, seg, r0, w, g, ngroups, u - (unsigned int)g, fst, bst, ex, err,
                        sh, agg, mat);
     if (!act || L == 0) return;
-    double *base = X + jj + r0 * ldx;
+    double *base = X + jx + r0 * ldx;
     if (L == K) {
 #pragma unroll
         for (int k = 0; k < K; k++) __builtin_nontemporal_store(v[k], base + k * ldx);
@@ -72,7 +73,9 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
 
 // Many matrices in one launch: the unit table lists (matrix, 64-system
 // tile, row group) with each tile's groups consecutive; otherwise as
-// k_onepass.
+// k_onepass, but with the single-wait phases (group_phases_1w): the many
+// short matrices give tiles of few groups, where the chain latency, not
+// the wait for the tile's loads, dominates.
 template <int K, int W>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_group_onepass(
     const GroupMat *__restrict__ mats, const GroupUnit *__restrict__ units, unsigned int *ctr,
@@ -90,6 +93,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     const CFwd fwd = (CFwd)m.fwd;
     const CBwd bwd = (CBwd)m.bwd;
     const CSeg seg = (CSeg)m.seg64;
+    const CGrp gtab = (CGrp)m.grp64;
     const int64_t j = un.col0 + lane;
     const bool act = j < m.batch;
     const int64_t jj = act ? j : 0;
@@ -105,8 +109,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     stage_records<K>(m.fwd, m.bwd, r0, lf[w], lb[w]);
     load_rows<K, double>(v, m.F + jj + (L > 0 ? r0 * m.ld : 0), m.ld, act ? L : 0);
     rec_wait<K>(L == K);
-    group_phases<K, W, true>(v, fwd, bwd, seg, r0, w, un.g, un.ngroups, (unsigned int)un.u0, fst, bst,
-                             ex, err, sh, agg, mat, lf[w], lb[w]);
+    group_phases_1w<K, W, true>(v, fwd, bwd, seg, gtab, r0, w, un.g, un.ngroups, (unsigned int)un.u0,
+                                fst, bst, ex, err, sh, agg, mat, ucon, lf[w], lb[w]);
     if (!act || L == 0) return;
     double *base = m.F + jj + r0 * m.ld;
     if (L == K) {
@@ -537,7 +541,7 @@ int onepass_capacity(int seg_rows)
 hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg, int64_t n,
                           int seg_rows, const void *Fin, bool f32, int64_t ldf, double *X,
                           int64_t ldx, int64_t batch, void *scratch, unsigned int *err,
-                          hipStream_t s)
+                          hipStream_t s, int64_t tsf, int64_t tsx)
 {
     if (seg_rows != 32 && seg_rows != 64) return hipErrorInvalidValue;
     const int W = onepass_waves(seg_rows);
@@ -559,7 +563,7 @@ hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *se
     int ng = (int)ngroups;
     void *args[] = {(void *)&fwd, (void *)&bwd, (void *)&segp, (void *)&n, (void *)&ng, (void *)&Fin,
                     (void *)&ldf, (void *)&X, (void *)&ldx, (void *)&batch, (void *)&ctr,
-                    (void *)&fst, (void *)&bst, (void *)&ex, (void *)&err};
+                    (void *)&fst, (void *)&bst, (void *)&ex, (void *)&err, (void *)&tsf, (void *)&tsx};
     e = hipLaunchKernel(fn, dim3((unsigned)units), dim3(64 * W), args, 0, s);
     return e;
 }

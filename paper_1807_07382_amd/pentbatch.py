@@ -43,6 +43,7 @@ SIGNATURES = {
     "pent_destroy": (_I, [_P]),
     "pent_solve": (_I, [_P, _P, _I64, _I64, _P]),
     "pent_solve_noalloc": (_I, [_P, _P, _I64, _I64, _P]),
+    "pent_solve_tiled": (_I, [_P, _P, _I64, _I64, _I64, _P]),
     "pent_solve_strided": (_I, [_P, _P, _I64, _I64, _P]),
     "pent_solve_mixed": (_I, [_P, _P, _I, _I64, _P, _I64, _I64, _I, _P, _P, ctypes.c_size_t, _P]),
     "pent_mixed_workspace_size": (ctypes.c_size_t, [_P, _I64]),

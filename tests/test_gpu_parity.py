@@ -287,3 +287,66 @@ def test_single_pass_full_hyperdiff(torch, seg):
     X = T[:, torch.from_numpy(cols).cuda()].cpu().numpy()
     ref = workloads.hyperdiffusion(n, sigma, w["C0"][:, cols], 2)
     assert np.all(colerr(X, ref) <= 2 * d4_tol(sigma))
+
+
+@pytest.mark.parametrize("seg", [32, 64])
+@pytest.mark.parametrize("n,m,extra", [(1024, 64, 0), (1500, 1000, 64), (4097, 333, 8)])
+def test_tiled_layout_equals_interleaved(torch, seg, n, m, extra):
+    """pent_solve_tiled (each 64-system tile its own interleaved block, with
+    padding between tiles) gives every system the bits pent_solve gives it in
+    the ordinary interleaved layout (same single-pass kernel, same
+    arithmetic); the padding is not touched; sampled systems against the
+    oracle."""
+    import ctypes
+    print_case(test="tiled", n=n, m=m, seg=seg)
+    rng = np.random.default_rng(7)
+    sigma = 50.0
+    F = rng.uniform(-1, 1, (n, m))
+    tiles = (m + 63) // 64
+    ts = n * 64 + extra
+    buf = rng.uniform(-9, 9, tiles * ts)
+    Fp = np.zeros((n, tiles * 64))
+    Fp[:, :m] = F
+    for t in range(tiles):
+        blk = buf[t * ts: t * ts + n * 64].reshape(n, 64)
+        cols = min(64, m - 64 * t)
+        blk[:, :cols] = F[:, 64 * t: 64 * t + cols]
+    T = torch.from_numpy(buf.copy()).cuda()
+    with pb.Plan.factor_d4(n, sigma) as plan:
+        plan.set_schedule(4, seg)
+        st = pb.lib().pent_solve_tiled(plan.handle, ctypes.c_void_p(T.data_ptr()), m, 64, ts,
+                                       ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert st == pb.OK
+        R = torch.from_numpy(F.copy()).cuda()
+        plan.solve_(R)
+        torch.cuda.synchronize()
+        plan.check()
+    out = T.cpu().numpy()
+    ref = R.cpu().numpy()
+    for t in range(tiles):
+        cols = min(64, m - 64 * t)
+        blk = out[t * ts: t * ts + n * 64].reshape(n, 64)
+        assert np.array_equal(blk[:, :cols], ref[:, 64 * t: 64 * t + cols]), f"tile {t}"
+        orig = buf[t * ts: t * ts + n * 64].reshape(n, 64)
+        assert np.array_equal(blk[:, cols:], orig[:, cols:])  # idle columns of a partial tile
+        assert np.array_equal(out[t * ts + n * 64:(t + 1) * ts], buf[t * ts + n * 64:(t + 1) * ts])
+    cols = np.unique(np.linspace(0, m - 1, 12).astype(np.int64))
+    oref = oracle.solve(oracle.assemble_d4(n, sigma), F[:, cols])
+    assert np.max(colerr(ref[:, cols], oref)) <= d4_tol(sigma)
+
+
+def test_tiled_layout_argument_errors(torch):
+    import ctypes
+    with pb.Plan.factor_d4(2048, 1.0) as plan:
+        T = torch.zeros(2048 * 64, dtype=torch.float64, device="cuda")
+        p = ctypes.c_void_p(T.data_ptr())
+        L = pb.lib()
+        assert L.pent_solve_tiled(plan.handle, p, 64, 63, 2048 * 64, None) == pb.INVALID_VALUE
+        assert L.pent_solve_tiled(plan.handle, p, 64, 64, 2047 * 64 + 63, None) == pb.INVALID_VALUE
+        assert L.pent_solve_tiled(plan.handle, p, -1, 64, 2048 * 64, None) == pb.INVALID_VALUE
+        assert L.pent_solve_tiled(plan.handle, None, 64, 64, 2048 * 64, None) == pb.INVALID_VALUE
+        assert L.pent_solve_tiled(plan.handle, None, 0, 64, 2048 * 64, None) == pb.OK
+        plan.set_schedule(2, 64)  # not the single pass
+        assert L.pent_solve_tiled(plan.handle, p, 64, 64, 2048 * 64, None) == pb.NOT_SUPPORTED
+        torch.cuda.synchronize()
+        assert torch.count_nonzero(T).item() == 0
