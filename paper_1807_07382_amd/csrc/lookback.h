@@ -253,17 +253,23 @@ constexpr int kStage = 16;
 constexpr int kCoherentLoad = 16;  // cache-policy bits of a direct load: sc1, as xload
 
 // LDS of a group of W waves (declared by each kernel, as arrays: the direct
-// loads need plain LDS addresses): sh[W + 1][4][64], per wave the states it
-// hands on (rows 0, 1 forward, 2, 3 backward; row W the group's); agg
-// [kStage][128] and mat, the replay's staging area (aggregate pairs of the
-// tile's 64 systems, and the link matrices of those groups: kStage x W x 4
-// segment matrices in the two-phase form, 2 kStage x 4 group matrices in
-// the single-wait form); ucon: the group's W segment records and its group
-// record (single-wait form, stage_consts).
-#define PENT_GROUP_LDS(W)                                                      \
-    __shared__ double sh[(W) + 1][4][64];                                      \
-    __shared__ double agg[pent::lb::kStage][128];                              \
-    __shared__ double mat[pent::lb::kStage * ((W) > 2 ? (W) : 2) * 4];         \
+// loads need plain LDS addresses): sh [W + 1][2][64], the waves' carries;
+// agg [kStage][128] and mat [kStage][W][4], the replay's staging area
+// (aggregate pairs of the tile's 64 systems, and the W segment matrices of
+// each of those groups).
+#define PENT_GROUP_LDS(W)                          \
+    __shared__ double sh[(W) + 1][2][64];          \
+    __shared__ double agg[pent::lb::kStage][128];  \
+    __shared__ double mat[pent::lb::kStage][(W)][4]
+
+// The same for the single-wait form (group_phases_1w): sh [W + 1][4][64],
+// per wave its forward and backward states (row W: the group's); mat
+// [2 kStage][4], one group matrix per staged group; ucon, the group's W
+// segment records and its group record (stage_consts).
+#define PENT_GROUP1W_LDS(W)                                    \
+    __shared__ double sh[(W) + 1][4][64];                      \
+    __shared__ double agg[pent::lb::kStage][128];              \
+    __shared__ double mat[2 * pent::lb::kStage][4];            \
     __shared__ double ucon[((W) * 16 + 16 + 127) / 128 * 128]
 
 typedef __attribute__((address_space(4))) const GrpRec *CGrp;
@@ -291,11 +297,10 @@ template <int W, bool FWD>
 __device__ __forceinline__ void group_carry(CSeg seg, int g, int ngroups, unsigned int u0,
                                             unsigned int *st_word, double *ex, unsigned int *err,
                                             double c0, double c1, double &y0, double &y1,
-                                            double (*agg)[128], double *matp)
+                                            double (*agg)[128], double (*mat)[W][4])
 {
     const int lane = threadIdx.x & 63;
     const int ra = FWD ? 0 : 4;  // aggregate rows
-    double (*mat)[W][4] = (double (*)[W][4])matp;
     double *me = ex + (int64_t)(u0 + g) * (kExRows * 64) + lane;
     // the aggregate goes out first: later groups can use it while this one
     // is still looking
@@ -435,8 +440,8 @@ __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd,
                                              int64_t r0, int w, int g, int ngroups,
                                              unsigned int u0, unsigned int *fst,
                                              unsigned int *bst, double *ex, unsigned int *err,
-                                             double (*sh)[4][64], double (*agg)[128],
-                                             double *mat, const FwdRec *lf = nullptr,
+                                             double (*sh)[2][64], double (*agg)[128],
+                                             double (*mat)[W][4], const FwdRec *lf = nullptr,
                                              const BwdRec *lb = nullptr)
 {
     const int lane = threadIdx.x & 63;
@@ -679,12 +684,11 @@ __device__ __forceinline__ void group_phases_1w(double (&v)[K], CFwd fwd, CBwd b
                                              unsigned int u0, unsigned int *fst,
                                              unsigned int *bst, double *ex, unsigned int *err,
                                              double (*sh)[4][64], double (*agg)[128],
-                                             double *matp, double *ucon,
+                                             double (*mat)[4], double *ucon,
                                              const FwdRec *lf = nullptr, const BwdRec *lb = nullptr)
 {
     const int lane = threadIdx.x & 63;
     const int64_t s0 = (int64_t)g * W;
-    double (*mat)[4] = (double (*)[4])matp;
     if (w == 0) stage_consts<W>((const SegRec *)seg, (const GrpRec *)grp, s0, g, ucon);
     // segment record i (tf at 0, cg at 4, tb at 8) and the group record (tg
     // at 0, tbg at 4, q at 12) as staged in LDS

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     const GroupMat *__restrict__ mats, const GroupUnit *__restrict__ units, unsigned int *ctr,
     unsigned int *fst, unsigned int *bst, double *ex, unsigned int *err)
 {
-    PENT_GROUP_LDS(W);
+    PENT_GROUP1W_LDS(W);
     __shared__ unsigned int s_unit;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
     const int lane = threadIdx.x & 63;
@@ -200,9 +200,12 @@ __device__ __forceinline__ void fix_residual(double (&v)[K], const double *diag,
 // tile does not straddle two): a system's y neighbours are the adjacent
 // lanes, read back through the transpose buffer, plus one halo system above
 // and below the tile (one row per lane); its x neighbours are the adjacent
-// rows in registers, plus one value past each end of the block.
+// rows in registers, plus one value past each end of the block.  Three
+// waves per SIMD in both forms (the stencil's batches are not fenced off
+// from each other by scheduling barriers: with them its y-neighbour reads
+// were hoisted into a long-lived set that spilled).
 template <int K, int W, bool ST>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(ST ? 2 : 3))) void k_onepass_t(
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_onepass_t(
     const FwdRec *fwd_, const BwdRec *bwd_, const SegRec *seg_, int64_t n, int ngroups, double *F,
     int64_t ld, int64_t batch, unsigned int *ctr, unsigned int *fst, unsigned int *bst, double *ex,
     unsigned int *err, const double *Cin, int64_t ny, int64_t ninst, const double *dt,
@@ -362,7 +365,6 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(ST ? 2 :
                 v[row] = row < L ? r : 0.0;
             }
             __atomic_signal_fence(__ATOMIC_SEQ_CST);
-            __builtin_amdgcn_sched_barrier(0);  // one batch at a time
         }
     }
     group_phases<K, W>(v, fwd, bwd, seg, r0, w, g, ngroups, u - (unsigned int)g, fst, bst, ex, err,
