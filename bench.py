@@ -397,7 +397,16 @@ def run_group(args, torch):
     steps = args.steps if args.steps != 100 else inputs.GROUP["steps"]
     mats = inputs.group()
     plans = [pb.Plan.factor_d4(F.shape[0], sg) for sg, F in mats]
-    Ts = [torch.from_numpy(F).cuda() for _, F in mats]
+    # each matrix's block with its rows padded to whole 128-byte lines (ld a
+    # multiple of 16 doubles; PENT_GROUP_LD_PAD overrides, for comparisons),
+    # so no 64-system row segment straddles a line it only partly uses
+    pad = int(os.environ.get("PENT_GROUP_LD_PAD", "16"))
+    Ts = []
+    for _, F in mats:
+        ld = (F.shape[1] + pad - 1) // pad * pad
+        T = torch.zeros((F.shape[0], ld), dtype=torch.float64, device="cuda")
+        T[:, :F.shape[1]].copy_(torch.from_numpy(F))
+        Ts.append(T[:, :F.shape[1]])
     probe = [(k, np.unique([0, F.shape[1] - 1])) for k, (_, F) in enumerate(mats)]
     init = [T.clone() for T in Ts]
     unknowns = sum(F.shape[0] * F.shape[1] for _, F in mats)
@@ -437,7 +446,8 @@ def run_group(args, torch):
                 n_gpus=1, steps=steps, warmup=1, ms_per_step=ms_step, higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
                 config=dict(workload="group", matrices=len(mats), unknowns_per_step=unknowns,
-                            systems=systems, graph_steps=steps, kernel_variant=variant),
+                            systems=systems, graph_steps=steps, kernel_variant=variant,
+                            layout=f"interleaved per matrix, ld rounded up to a multiple of {pad}"),
                 roofline=dict(bound="hbm", achieved=gbs, peak=PEAK_HBM_GBS, unit="GB/s",
                               frac=gbs / PEAK_HBM_GBS,
                               traffic=traffic_for("group_onepass64", "group",
