@@ -237,7 +237,8 @@ int pent_group_destroy(pent_group g); /* NULL is a no-op; graphs captured from g
 
 /* Autotune the group kernel for these right-hand-side counts (HOST array
  * batch[count]): every variant that can run is timed on scratch blocks of
- * the same shapes (the caller's data and binding are not touched) and the
+ * the same shapes, rows padded to a multiple of 16 doubles (the caller's
+ * data and binding are not touched) and the
  * fastest is kept for later PENT_GROUP_FP64 solves.  Blocking; allocates
  * scratch for the duration of the call.  variant_out / ms_out (HOST,
  * optional) receive the choice and its time. */

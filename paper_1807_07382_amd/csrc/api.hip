@@ -1303,13 +1303,15 @@ int pent_group_autotune(pent_group g, const int64_t *batch, int *variant_out, do
     for (size_t k = 0; k < cnt; k++)
         if (batch[k] < 0) return ret(PENT_INVALID_VALUE);
     hipStream_t s = (hipStream_t)stream;
-    // scratch blocks of the same shapes (the caller's data is never touched)
+    // scratch blocks of the same shapes (the caller's data is never touched),
+    // rows padded to whole 128-byte lines as a caller would store them
     std::vector<double *> F(cnt, nullptr);
-    std::vector<int64_t> ld(batch, batch + cnt);
+    std::vector<int64_t> ld(cnt);
+    for (size_t k = 0; k < cnt; k++) ld[k] = (batch[k] + 15) / 16 * 16;
     void *work = nullptr;
     hipError_t e = hipSuccess;
     for (size_t k = 0; k < cnt && e == hipSuccess; k++) {
-        const size_t m = (size_t)g->plans[k]->n * std::max<int64_t>(batch[k], 1);
+        const size_t m = (size_t)g->plans[k]->n * std::max<int64_t>(ld[k], 1);
         e = hipMalloc(&F[k], sizeof(double) * m);
         if (e == hipSuccess) e = fill_const(F[k], (int64_t)m, 1.0, s);
     }

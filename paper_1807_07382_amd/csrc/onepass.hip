@@ -96,7 +96,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     const CGrp gtab = (CGrp)m.grp64;
     const int64_t j = un.col0 + lane;
     const bool act = j < m.batch;
-    const int64_t jj = act ? j : 0;
+    const int64_t jj = act ? j : un.col0;  // idle lanes read the tile's first column (its own lines)
     const int64_t r0 = ((int64_t)un.g * W + w) * K;
     const int64_t rem = m.n - r0;
     const int L = (int)(rem < 0 ? 0 : rem < K ? rem : K);
