@@ -35,11 +35,26 @@ __global__ void k_assemble_d4(double *__restrict__ diag, int64_t n, double sigma
 // LDS, kFU rows per batch with the batch's diagonal entries read ahead of
 // its arithmetic, so a row costs the latency of its dependent arithmetic
 // (one product, one difference, one division) and no memory round trip.
+//
+// Where the diagonals repeat (the interior of a constant-coefficient matrix
+// such as I + sigma D4) the rounded recurrence falls into an exact cycle: a
+// row's factors are a function of its diagonals and the previous two rows'
+// factors, so once two consecutive rows equal, bit for bit, the rows p
+// earlier, every following row whose diagonals equal those p rows earlier
+// repeats the row p earlier too.  Every kFCheck rows the wave looks for such
+// a period p <= 63 among the rows it has just produced; when one holds, the
+// block finds the first later row whose diagonals break the period and
+// copies the p-periodic rows up to it in parallel, then the serial lane
+// resumes there.  The factors are the same bits as without the shortcut; a
+// matrix with no repeating stretch runs fully serial.
+//
 // The loop has no branch on the pivot: the first row with a zero or
 // non-finite pivot is recorded and the rows from it on are overwritten
-// afterwards.  *bad receives that row, or -1.
-constexpr int kFC = 512;  // rows per chunk
-constexpr int kFU = 8;    // rows per batch of the serial lane
+// afterwards (no shortcut is taken after such a row).  *bad receives that
+// row, or -1.
+constexpr int kFC = 512;     // rows per chunk
+constexpr int kFU = 8;       // rows per batch of the serial lane
+constexpr int kFCheck = 64;  // rows between checks for a period
 
 __global__ __launch_bounds__(256) void k_factor_serial(const double *__restrict__ diag, int64_t n,
                                                        double *__restrict__ fac,
@@ -49,71 +64,142 @@ __global__ __launch_bounds__(256) void k_factor_serial(const double *__restrict_
     __shared__ double din[2][5][kFC];  // diagonals a..e of the chunk (zero outside the matrix)
     __shared__ double dout[4][kFC];    // alpha, beta, gamma, delta of the chunk
     __shared__ long long s_bad;
-    const int tid = threadIdx.x;
+    __shared__ int s_period;           // period found by the serial wave (0: none)
+    __shared__ int s_done;             // rows of the chunk computed when it was found
+    __shared__ unsigned long long s_until;
+    const int tid = threadIdx.x, lane = tid & 63;
     double *alpha = fac, *beta = fac + n, *gamma = fac + 2 * n, *delta = fac + 3 * n;
-    const int64_t nch = (n + kFC - 1) / kFC;
-    // threads [t0, t0 + nt) fetch chunk c into din[buf]
-    auto load_chunk = [&](int64_t c, int buf, int t0, int nt) {
+    // diagonal q of row i (zero outside the matrix)
+    auto dg = [&](int q, int64_t i) -> double {
+        if (i < 0 || i >= n) return 0.0;
+        const bool in = q == 0 ? i >= 2 : q == 1 ? i >= 1 : q == 3 ? i + 1 < n : q == 4 ? i + 2 < n : true;
+        return in ? diag[(int64_t)q * n + i] : 0.0;
+    };
+    // threads [t0, t0 + nt) fetch rows r0 .. r0 + kFC - 1 into din[buf]
+    auto load_chunk = [&](int64_t r0, int buf, int t0, int nt) {
         for (int k = tid - t0; k < 5 * kFC; k += nt) {
             const int q = k / kFC, r = k % kFC;
-            const int64_t i = c * kFC + r;
-            double v = 0.0;
-            if (i < n) {
-                // entries that fall outside the matrix are zero
-                const bool in = q == 0 ? i >= 2 : q == 1 ? i >= 1 : q == 3 ? i + 1 < n : q == 4 ? i + 2 < n : true;
-                if (in) v = diag[(int64_t)q * n + i];
-            }
-            din[buf][q][r] = v;
+            din[buf][q][r] = dg(q, r0 + r);
         }
     };
     if (tid == 0) s_bad = -1;
-    load_chunk(0, 0, 0, 256);
-    __syncthreads();
-    double gam2 = 0.0, del2 = 0.0, gam1 = 0.0, del1 = 0.0;
+    double gam2 = 0.0, del2 = 0.0, gam1 = 0.0, del1 = 0.0;  // the serial lane's state
     long long badrow = -1;
-    for (int64_t c = 0; c < nch; c++) {
-        const int buf = (int)(c & 1);
-        if (tid >= 64) {
-            if (c + 1 < nch) load_chunk(c + 1, buf ^ 1, 64, 192);  // waves 1..3 fetch ahead
-        } else if (tid == 0) {
-            const double(*dg)[kFC] = din[buf];
-            for (int r0 = 0; r0 < kFC; r0 += kFU) {
-                double a[kFU], b[kFU], cc[kFU], d[kFU], e[kFU];
+    int64_t start = 0;
+    while (start < n) {
+        // serial phase from row `start`
+        const int64_t nch = (n - start + kFC - 1) / kFC;
+        if (tid == 0) s_period = 0;
+        load_chunk(start, 0, 0, 256);
+        __syncthreads();
+        int64_t next = n;
+        for (int64_t c = 0; c < nch; c++) {
+            const int buf = (int)(c & 1);
+            const int64_t c0 = start + c * kFC;
+            const int rows = (int)(n - c0 < kFC ? n - c0 : kFC);
+            if (tid >= 64) {
+                if (c + 1 < nch) load_chunk(c0 + kFC, buf ^ 1, 64, 192);  // waves 1..3 fetch ahead
+            } else {
+                const double(*d)[kFC] = din[buf];
+                for (int sb = 0; sb < kFC; sb += kFCheck) {
+                    if (lane == 0) {
+                        for (int r0 = sb; r0 < sb + kFCheck; r0 += kFU) {
+                            double a[kFU], b[kFU], cc[kFU], dd[kFU], e[kFU];
 #pragma unroll
-                for (int k = 0; k < kFU; k++) {
-                    a[k] = dg[0][r0 + k];
-                    b[k] = dg[1][r0 + k];
-                    cc[k] = dg[2][r0 + k];
-                    d[k] = dg[3][r0 + k];
-                    e[k] = dg[4][r0 + k];
-                }
+                            for (int k = 0; k < kFU; k++) {
+                                a[k] = d[0][r0 + k];
+                                b[k] = d[1][r0 + k];
+                                cc[k] = d[2][r0 + k];
+                                dd[k] = d[3][r0 + k];
+                                e[k] = d[4][r0 + k];
+                            }
 #pragma unroll
-                for (int k = 0; k < kFU; k++) {
-                    const double be = b[k] - a[k] * gam2;
-                    const double al = cc[k] - a[k] * del2 - be * gam1;
-                    const double ga = (d[k] - be * del1) / al;
-                    const double de = e[k] / al;
-                    const int64_t i = c * kFC + r0 + k;
-                    const bool pivot_bad = !(al != 0.0) || !__builtin_isfinite(al);
-                    badrow = (badrow < 0 && pivot_bad && i < n) ? (long long)i : badrow;
-                    dout[0][r0 + k] = al;
-                    dout[1][r0 + k] = be;
-                    dout[2][r0 + k] = ga;
-                    dout[3][r0 + k] = de;
-                    gam2 = gam1;
-                    del2 = del1;
-                    gam1 = ga;
-                    del1 = de;
+                            for (int k = 0; k < kFU; k++) {
+                                const double be = b[k] - a[k] * gam2;
+                                const double al = cc[k] - a[k] * del2 - be * gam1;
+                                const double ga = (dd[k] - be * del1) / al;
+                                const double de = e[k] / al;
+                                const int64_t i = c0 + r0 + k;
+                                const bool pivot_bad = !(al != 0.0) || !__builtin_isfinite(al);
+                                badrow = (badrow < 0 && pivot_bad && i < n) ? (long long)i : badrow;
+                                dout[0][r0 + k] = al;
+                                dout[1][r0 + k] = be;
+                                dout[2][r0 + k] = ga;
+                                dout[3][r0 + k] = de;
+                                gam2 = gam1;
+                                del2 = del1;
+                                gam1 = ga;
+                                del1 = de;
+                            }
+                        }
+                    }
+                    // a period: the chunk's last two rows equal, bit for bit, the
+                    // rows p earlier (lane p tests period p)
+                    const int eb = sb + kFCheck < rows ? sb + kFCheck : rows;
+                    const long long brow = __builtin_amdgcn_readfirstlane((int)badrow);
+                    bool ok = lane >= 1 && eb - 2 - lane >= 0 && brow < 0 && c0 + eb < n;
+                    if (ok) {
+#pragma unroll
+                        for (int q = 0; q < 4; q++)
+                            ok = ok &&
+                                 __double_as_longlong(dout[q][eb - 1]) == __double_as_longlong(dout[q][eb - 1 - lane]) &&
+                                 __double_as_longlong(dout[q][eb - 2]) == __double_as_longlong(dout[q][eb - 2 - lane]);
+                    }
+                    const unsigned long long hit = __ballot(ok);
+                    if (hit != 0) {
+                        if (lane == 0) {
+                            s_period = __builtin_ctzll(hit);
+                            s_done = eb;
+                        }
+                        break;
+                    }
+                    if (eb >= rows) break;
                 }
             }
+            __syncthreads();
+            const int done = s_period ? s_done : rows;
+            for (int k = tid; k < 4 * kFC; k += 256) {
+                const int q = k / kFC, r = k % kFC;
+                if (r < done) fac[(int64_t)q * n + c0 + r] = dout[q][r];
+            }
+            __syncthreads();  // dout and the next chunk's buffer are reused
+            if (s_period) {
+                next = c0 + done;
+                break;
+            }
+        }
+        if (next >= n) break;
+        // copy phase: rows next .. m-1 repeat the rows p earlier, m the first
+        // row whose diagonals differ from those p rows before it (or n)
+        const int p = s_period;
+        if (tid == 0) s_until = (unsigned long long)n;
+        __syncthreads();
+        for (int64_t i = next + tid; i < n; i += 256) {
+            bool same = true;
+#pragma unroll
+            for (int q = 0; q < 5; q++)
+                same = same && __double_as_longlong(dg(q, i)) == __double_as_longlong(dg(q, i - p));
+            if (!same) atomicMin(&s_until, (unsigned long long)i);
         }
         __syncthreads();
-        for (int k = tid; k < 4 * kFC; k += 256) {
-            const int q = k / kFC, r = k % kFC;
-            const int64_t i = c * kFC + r;
-            if (i < n) fac[(int64_t)q * n + i] = dout[q][r];
+        const int64_t m = (int64_t)s_until;
+        for (int64_t i = next + tid; i < m; i += 256) {
+            const int64_t src = next - p + (i - next) % p;
+            alpha[i] = alpha[src];
+            beta[i] = beta[src];
+            gamma[i] = gamma[src];
+            delta[i] = delta[src];
         }
-        __syncthreads();  // dout and the next chunk's buffer are reused
+        __syncthreads();
+        // the serial lane resumes at row m from the rows m-2, m-1
+        if (tid == 0 && m < n) {
+            gam2 = gamma[m - 2];
+            del2 = delta[m - 2];
+            gam1 = gamma[m - 1];
+            del1 = delta[m - 1];
+        }
+        start = m;
+        __syncthreads();
     }
     if (tid == 0) s_bad = badrow;
     __syncthreads();

@@ -49,6 +49,42 @@ def test_assembly_and_factors_bitwise(torch, n, sigma):
             assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("n,sigma", [(8192, 50.0), (8192, 1e4), (20000, 1e5), (777, 3.0), (130, 7.0)])
+def test_long_factors_bitwise(torch, n, sigma):
+    """Long constant-coefficient factorisations, where the device copies the
+    rows of the recurrence's exact cycle instead of recomputing them: the
+    same bits as the oracle's row-by-row recurrence."""
+    print_case(test="factor_long", n=n, sigma=sigma)
+    with pb.Plan.factor_d4(n, sigma) as p:
+        fac = oracle.factor(oracle.assemble_d4(n, sigma))
+        for got, ref in zip(p.factors(), fac):
+            assert np.array_equal(got, ref)
+
+
+def test_piecewise_constant_factors_bitwise(torch):
+    """Diagonals constant on three stretches (the cycle breaks where a
+    stretch ends and the serial recurrence resumes), non-symmetric, plus a
+    stretch of random rows: factors bit for bit against the oracle."""
+    n = 9000
+    print_case(test="factor_piecewise", n=n)
+    g = np.random.Generator(np.random.PCG64(31))
+    rows = [(0, 3000, (0.5, -2.0, 9.0, -1.5, 0.25)), (3000, 3500, None),
+            (3500, 7000, (1.0, -4.0, 10.0, -3.0, 0.75)), (7000, n, (2.0, 1.0, 12.0, 1.0, -2.0))]
+    dg = [np.zeros(n) for _ in range(5)]
+    for r0, r1, vals in rows:
+        for q in range(5):
+            if vals is None:
+                dg[q][r0:r1] = g.uniform(-1, 1, r1 - r0)
+                if q == 2:
+                    dg[q][r0:r1] += 6.0
+            else:
+                dg[q][r0:r1] = vals[q]
+    with pb.Plan.factor(*dg) as p:
+        fac = oracle.factor(oracle.Diagonals(*dg))
+        for got, ref in zip(p.factors(), fac):
+            assert np.array_equal(got, ref)
+
+
 @pytest.mark.parametrize("n", [1, 2, 7, 300])
 def test_general_factors_bitwise(torch, n):
     print_case(test="factor_general", n=n)
