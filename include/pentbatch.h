@@ -23,6 +23,13 @@
  *    until the stream work that uses it has finished.
  *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
  *    Solves are asynchronous: they only enqueue kernels.
+ *  - "Stream-ordered scratch" below is allocated on `stream` and freed on it
+ *    after the kernels that use it, from a memory pool of the library's own
+ *    on each device.  That pool keeps up to 4 GiB reserved after the stream
+ *    synchronises (the device's default pool hands freed memory back at
+ *    every synchronisation, and the next call would map it again), so a
+ *    program that synchronises after every solve pays no allocation on the
+ *    next one.  The reserve lasts until the process ends.
  *  - Errors are returned as a pent_status; nothing throws across the ABI.
  *    Argument checks run before any HIP call, so a bad argument never leaves
  *    work queued.  pent_last_status() repeats the status of the calling
