@@ -200,11 +200,13 @@ __global__ void k_cn_rhs(const double *__restrict__ cd, int64_t n, const double 
 // runs by look-back (lookback.h).  The last two unknowns need
 // h^T E^{-1} f^ = sum over rows of (h^T E^{-1})[q][i] f_i: every block forms
 // its part from the precomputed (h^T E^{-1})^T while f is in registers, every
-// group posts the sum of its waves' parts, and the tile's last group (which
-// finishes first: nothing lies below it) adds the groups' parts in order,
-// forms x_tail = Minv ((f_{n-2}, f_{n-1}) - h^T E^{-1} f^) and posts it.
-// Every block then applies x^ = y - Z x_tail to its rows before the one
-// store.  This is the paper's bordering formula with hT E^{-1} precomputed.
+// group posts the sum of its waves' parts, and the tile's last group adds
+// the groups' parts in order while its wave 0 waits for the forward carry
+// (the sum needs only the loaded blocks), forms
+// x_tail = Minv ((f_{n-2}, f_{n-1}) - h^T E^{-1} f^) and posts it.  Every
+// block applies x^ = y - Z x_tail in its back substitution, as the y rows
+// are formed (TailCorr).  This is the paper's bordering formula with
+// hT E^{-1} precomputed.
 //
 // With CN the block loads C rows r0-2 .. r0+K+1 (periodic) instead of f and
 // forms f = 2C - AC in registers (the explicit half of the step); C and X
@@ -252,148 +254,35 @@ __device__ __forceinline__ bool wait_nonzero(unsigned int *p, unsigned int want,
     return false;
 }
 
-template <int K, int W, bool CN>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_cyc_onepass(
-    const FwdRec *fwd_, const BwdRec *bwd_, const SegRec *seg_, const double *__restrict__ cd_,
-    const double *__restrict__ Z_, const double *__restrict__ Wt_, const CycAux *__restrict__ aux,
-    int64_t n, int ngroups, const double *Fin, int64_t ldf, double *X, int64_t ldx, int64_t batch,
-    unsigned int *ctr, unsigned int *fst, unsigned int *bst, unsigned int *pst, unsigned int *tst,
-    double *ex, double *pex, double *tex, unsigned int *err)
-{
-    PENT_GROUP_LDS(W);
-    __shared__ double sp[W][2][64];
-    __shared__ double sft[2][64];  // f_m, f_{m+1} of the tile (tail block), kept out of registers
-    __shared__ unsigned int s_unit;
-    const CFwd fwd = (CFwd)fwd_;
-    const CBwd bwd = (CBwd)bwd_;
-    const CSeg seg = (CSeg)seg_;
-    const CDbl Z = (CDbl)Z_;
-    const CDbl Wt = (CDbl)Wt_;
-    const CDbl cd = (CDbl)cd_;
-    const int64_t m = n - 2;
-    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
-    const int lane = threadIdx.x & 63;
-    if (w == 0) s_unit = take_unit(ctr);  // every lane of wave 0 stores the same value
-    __syncthreads();
-    const unsigned int u = (unsigned int)__builtin_amdgcn_readfirstlane((int)s_unit);
-    const int t = (int)(u / (unsigned int)ngroups), g = (int)(u % (unsigned int)ngroups);
-    const int64_t j = (int64_t)t * 64 + lane;
-    const bool act = j < batch;
-    const int64_t jj = act ? j : 0;
-    const int64_t r0 = ((int64_t)g * W + w) * K;
-    const int64_t rem = m - r0;
-    const int L = (int)(rem < 0 ? 0 : rem < K ? rem : K);  // E rows in this block
-    const bool last = g == ngroups - 1 && w == 0;  // forms x_tail for the tile
-    const double *col = Fin + jj;
-    double v[K];
-    if (CN) {
-        // C rows r0 .. r0+K-1 into v (two rows past the block's last E row are
-        // needed by the stencil: for a short last block they sit in v, else in
-        // the halo h2, h3), rows r0-2, r0-1 in h0, h1; all periodic.  f is then
-        // formed in place with the two overwritten originals kept rolling.
-        const int Lc = L + 2 < K ? L + 2 : K;
-        double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
-        if (act && L > 0) {
-            h0 = col[wrap(r0 - 2, n) * ldf];
-            h1 = col[wrap(r0 - 1, n) * ldf];
-            if (L + 1 >= K) h2 = col[wrap(r0 + K, n) * ldf];
-            if (L + 2 >= K) h3 = col[wrap(r0 + K + 1, n) * ldf];
-        }
-        // rows r0 .. r0+Lc-1 <= m+1 never wrap (only the halo rows can)
-        const double *base = col + (L > 0 ? r0 * ldf : 0);
-        if (Lc == K) {
-#pragma unroll
-            for (int k = 0; k < K; k++) v[k] = act ? __builtin_nontemporal_load(base + k * ldf) : 0.0;
-        } else {
-#pragma unroll
-            for (int k = 0; k < K; k++) v[k] = (act && k < Lc) ? base[k * ldf] : 0.0;
-        }
-        if (last) {
-            const double cm2 = act ? col[(m - 2) * ldf] : 0.0, cm1 = act ? col[(m - 1) * ldf] : 0.0;
-            const double c_m = act ? col[m * ldf] : 0.0, c_m1 = act ? col[(m + 1) * ldf] : 0.0;
-            const double c0 = act ? col[0] : 0.0, c1 = act ? col[ldf] : 0.0;
-            sft[0][lane] = cn_row(cd, cyc_ld(n), m, cm2, cm1, c_m, c_m1, c0);
-            sft[1][lane] = cn_row(cd, cyc_ld(n), m + 1, cm1, c_m, c_m1, c0, c1);
-        }
-        double p2 = h0, p1 = h1;  // C_{k-2}, C_{k-1}
-        CDbl cdf = cd;
-        // a copy of L the compiler cannot match with the later k < L tests,
-        // so it does not keep 64 row masks live from here to the stores
-        int Ls = L;
-        asm volatile("" : "+s"(Ls));
-#pragma unroll
-        for (int k = 0; k < K; k++) {
-            if (k % kSchedRows == 0) {
-                __builtin_amdgcn_sched_barrier(0);
-                cdf = fresh(cdf);
-            }
-            const double ck = v[k];
-            const double n1 = k + 1 < K ? v[k + 1] : h2;
-            const double n2 = k + 2 < K ? v[k + 2] : (k + 2 == K ? h2 : h3);
-            // rows past the E rows read zero padding (no select: the
-            // addresses stay affine in k, scalar loads with immediate offsets)
-            const double f = cn_row(cdf, cyc_ld(n), r0 + k, p2, p1, ck, n1, n2);
-            v[k] = k < Ls ? f : 0.0;
-            p2 = p1;
-            p1 = ck;
-        }
-    } else {
-        const double *base = col + (L > 0 ? r0 * ldf : 0);
-        if (L == K) {
-#pragma unroll
-            for (int k = 0; k < K; k++) v[k] = act ? __builtin_nontemporal_load(base + k * ldf) : 0.0;
-        } else {
-#pragma unroll
-            for (int k = 0; k < K; k++) v[k] = (act && k < L) ? base[k * ldf] : 0.0;
-        }
-        if (last) {
-            sft[0][lane] = act ? col[m * ldf] : 0.0;
-            sft[1][lane] = act ? col[(m + 1) * ldf] : 0.0;
-        }
-    }
-
-    // partial products of the border rows with the block: p_q = sum over its
-    // rows of (h^T E^{-1})[q][i] f_i, rows in order; the group's sum (waves
-    // in order) is posted for the tile's last group, which adds the groups
-    // in order: h^T E^{-1} f^ with one fixed summation order.
+// The bordering correction, run inside group_phases.  early(): on the
+// tile's last group, by a wave that waits for nothing else then, adds the
+// groups' partial products in group order (they need only the loaded
+// blocks), forms x_tail = Minv ((f_{n-2}, f_{n-1}) - h^T E^{-1} f^), posts it
+// (status tst, values tx) and stores it as rows n-2, n-1 of x.  fetch(): the
+// group's last wave reads x_tail while wave 0 waits for the backward carry
+// and leaves it in LDS (xt).  The back substitution then stores
+// x^_i = y_i - Z_i x_tail as it forms y_i.
+struct TailCorr {
+    static constexpr bool on = true;
+    CDbl Z;
+    unsigned int *tst;
+    double *tx;  // the lane's x_tail (rows 0 and 64)
+    unsigned int *err;
+    double (*xt)[64];  // LDS, 2 x 64
+    bool last;         // this group forms x_tail
+    unsigned int *pst;
+    const double *pex;
+    unsigned int u0;  // the tile's first unit
+    int ngroups;
+    const double (*sft)[64];  // LDS: f_{n-2}, f_{n-1} of the tile
+    const CycAux *aux;
+    double *xcol;  // the lane's column of X
+    int64_t m, ldx;
+    bool act;
+    __device__ void early(int lane) const
     {
-        double p0 = 0.0, p1 = 0.0;
-        CDbl Wf = Wt;
-#pragma unroll
-        for (int k = 0; k < K; k++) {
-            if (k % kSchedRows == 0) {
-                __builtin_amdgcn_sched_barrier(0);
-                Wf = fresh(Wf);
-            }
-            const int64_t i = r0 + k;
-            p0 = fma(Wf[2 * i], v[k], p0);
-            p1 = fma(Wf[2 * i + 1], v[k], p1);
-        }
-        sp[w][0][lane] = p0;
-        sp[w][1][lane] = p1;
-    }
-    __syncthreads();
-    if (w == 0) {
-        double P0 = 0.0, P1 = 0.0;
-#pragma unroll
-        for (int i = 0; i < W; i++) {
-            P0 += sp[i][0][lane];
-            P1 += sp[i][1][lane];
-        }
-        double *mp = pex + (int64_t)u * 128 + lane;
-        xstore(&mp[0], P0);
-        xstore(&mp[64], P1);
-        publish(&pst[u], 1u);
-    }
-
-    group_phases<K, W>(v, fwd, bwd, seg, r0, w, g, ngroups, u - (unsigned int)g, fst, bst, ex, err,
-                       sh, agg, mat);
-
-    double *tx = tex + (int64_t)t * 128 + lane;
-    double xt0, xt1;
-    if (last) {
+        if (!last) return;
         // every group's partial products, in group order (windows of 64)
-        const unsigned int u0 = u - (unsigned int)g;
         bool timed_out = false;
         for (int b0 = 0; b0 < ngroups; b0 += 64) {
             for (int spin = 0;; spin++) {
@@ -430,35 +319,173 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
             d1 = __builtin_nan("");
         }
         const double r0v = sft[0][lane] - d0, r1v = sft[1][lane] - d1;
-        xt0 = fma(aux->minv[1], r1v, aux->minv[0] * r0v);
-        xt1 = fma(aux->minv[3], r1v, aux->minv[2] * r0v);
+        const double xt0 = fma(aux->minv[1], r1v, aux->minv[0] * r0v);
+        const double xt1 = fma(aux->minv[3], r1v, aux->minv[2] * r0v);
         xstore(&tx[0], xt0);
         xstore(&tx[64], xt1);
-        publish(&tst[t], 1u);
+        publish(tst, 1u);
         if (act) {
-            X[jj + m * ldx] = xt0;
-            X[jj + (m + 1) * ldx] = xt1;
+            xcol[m * ldx] = xt0;
+            xcol[(m + 1) * ldx] = xt1;
+        }
+    }
+    __device__ void fetch(int lane) const
+    {
+        const bool seen = wait_nonzero(tst, 1u, err);
+        double a = xload(&tx[0]), b = xload(&tx[64]);
+        if (!seen) {  // the tail never arrived: NaN instead of stale values
+            a = __builtin_nan("");
+            b = __builtin_nan("");
+        }
+        xt[0][lane] = a;
+        xt[1][lane] = b;
+    }
+    __device__ void get(int lane, double &c0, double &c1) const
+    {
+        c0 = xt[0][lane];
+        c1 = xt[1][lane];
+    }
+};
+
+template <int K, int W, bool CN>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_cyc_onepass(
+    const FwdRec *fwd_, const BwdRec *bwd_, const SegRec *seg_, const double *__restrict__ cd_,
+    const double *__restrict__ Z_, const double *__restrict__ Wt_, const CycAux *__restrict__ aux,
+    int64_t n, int ngroups, const double *Fin, int64_t ldf, double *X, int64_t ldx, int64_t batch,
+    unsigned int *ctr, unsigned int *fst, unsigned int *bst, unsigned int *pst, unsigned int *tst,
+    double *ex, double *pex, double *tex, unsigned int *err)
+{
+    PENT_GROUP_LDS(W);
+    __shared__ double sp[W][2][64];
+    __shared__ double sft[2][64];  // f_m, f_{m+1} of the tile (tail block), kept out of registers
+    __shared__ unsigned int s_unit;
+    const CFwd fwd = (CFwd)fwd_;
+    const CBwd bwd = (CBwd)bwd_;
+    const CSeg seg = (CSeg)seg_;
+    const CDbl Z = (CDbl)Z_;
+    const CDbl Wt = (CDbl)Wt_;
+    const CDbl cd = (CDbl)cd_;
+    const int64_t m = n - 2;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+    const int lane = threadIdx.x & 63;
+    if (w == 0) s_unit = take_unit(ctr);  // every lane of wave 0 stores the same value
+    __syncthreads();
+    const unsigned int u = (unsigned int)__builtin_amdgcn_readfirstlane((int)s_unit);
+    const int t = (int)(u / (unsigned int)ngroups), g = (int)(u % (unsigned int)ngroups);
+    const int64_t j = (int64_t)t * 64 + lane;
+    const bool act = j < batch;
+    const int64_t jj = act ? j : 0;
+    const int64_t r0 = ((int64_t)g * W + w) * K;
+    const int64_t rem = m - r0;
+    const int L = (int)(rem < 0 ? 0 : rem < K ? rem : K);  // E rows in this block
+    const bool last = g == ngroups - 1;  // forms x_tail for the tile
+    const double *col = Fin + jj;
+    double v[K];
+    if (CN) {
+        // C rows r0 .. r0+K-1 into v (two rows past the block's last E row are
+        // needed by the stencil: for a short last block they sit in v, else in
+        // the halo h2, h3), rows r0-2, r0-1 in h0, h1; all periodic.  f is then
+        // formed in place with the two overwritten originals kept rolling.
+        const int Lc = L + 2 < K ? L + 2 : K;
+        double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
+        if (act && L > 0) {
+            h0 = col[wrap(r0 - 2, n) * ldf];
+            h1 = col[wrap(r0 - 1, n) * ldf];
+            if (L + 1 >= K) h2 = col[wrap(r0 + K, n) * ldf];
+            if (L + 2 >= K) h3 = col[wrap(r0 + K + 1, n) * ldf];
+        }
+        // rows r0 .. r0+Lc-1 <= m+1 never wrap (only the halo rows can)
+        const double *base = col + (L > 0 ? r0 * ldf : 0);
+        if (Lc == K) {
+#pragma unroll
+            for (int k = 0; k < K; k++) v[k] = act ? __builtin_nontemporal_load(base + k * ldf) : 0.0;
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; k++) v[k] = (act && k < Lc) ? base[k * ldf] : 0.0;
+        }
+        if (last && w == 0) {
+            const double cm2 = act ? col[(m - 2) * ldf] : 0.0, cm1 = act ? col[(m - 1) * ldf] : 0.0;
+            const double c_m = act ? col[m * ldf] : 0.0, c_m1 = act ? col[(m + 1) * ldf] : 0.0;
+            const double c0 = act ? col[0] : 0.0, c1 = act ? col[ldf] : 0.0;
+            sft[0][lane] = cn_row(cd, cyc_ld(n), m, cm2, cm1, c_m, c_m1, c0);
+            sft[1][lane] = cn_row(cd, cyc_ld(n), m + 1, cm1, c_m, c_m1, c0, c1);
+        }
+        double c2 = h0, c1 = h1;  // C_{k-2}, C_{k-1}
+        CDbl cdf = cd;
+        // a copy of L the compiler cannot match with the later k < L tests,
+        // so it does not keep 64 row masks live from here to the stores
+        int Ls = L;
+        asm volatile("" : "+s"(Ls));
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            if (k % kSchedRows == 0) {
+                __builtin_amdgcn_sched_barrier(0);
+                cdf = fresh(cdf);
+            }
+            const double ck = v[k];
+            const double n1 = k + 1 < K ? v[k + 1] : h2;
+            const double n2 = k + 2 < K ? v[k + 2] : (k + 2 == K ? h2 : h3);
+            // rows past the E rows read zero padding (no select: the
+            // addresses stay affine in k, scalar loads with immediate offsets)
+            const double f = cn_row(cdf, cyc_ld(n), r0 + k, c2, c1, ck, n1, n2);
+            v[k] = k < Ls ? f : 0.0;
+            c2 = c1;
+            c1 = ck;
         }
     } else {
-        const bool seen = wait_nonzero(&tst[t], 1u, err);
-        xt0 = xload(&tx[0]);
-        xt1 = xload(&tx[64]);
-        if (!seen) {  // the tail never arrived: NaN instead of stale values
-            xt0 = __builtin_nan("");
-            xt1 = __builtin_nan("");
-        }
-    }
-    if (!act || L == 0) return;
-    CDbl Zf = Z;  // loaded here, not hoisted over the waits above
+        const double *base = col + (L > 0 ? r0 * ldf : 0);
+        if (L == K) {
 #pragma unroll
-    for (int k = 0; k < K; k++) {
-        if (k % kSchedRows == 0) {
-            __builtin_amdgcn_sched_barrier(0);
-            Zf = fresh(Zf);
+            for (int k = 0; k < K; k++) v[k] = act ? __builtin_nontemporal_load(base + k * ldf) : 0.0;
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; k++) v[k] = (act && k < L) ? base[k * ldf] : 0.0;
         }
-        const int64_t i = r0 + k;
-        v[k] = fma(-Zf[2 * i + 1], xt1, fma(-Zf[2 * i], xt0, v[k]));
+        if (last && w == 0) {
+            sft[0][lane] = act ? col[m * ldf] : 0.0;
+            sft[1][lane] = act ? col[(m + 1) * ldf] : 0.0;
+        }
     }
+
+    // partial products of the border rows with the block: p_q = sum over its
+    // rows of (h^T E^{-1})[q][i] f_i, rows in order; the group's sum (waves
+    // in order) is posted for the tile's last group, which adds the groups
+    // in order: h^T E^{-1} f^ with one fixed summation order.
+    double p0 = 0.0, p1 = 0.0;
+    {
+        CDbl Wf = Wt;
+#pragma unroll
+        for (int k = 0; k < K; k++) {
+            if (k % kSchedRows == 0) {
+                __builtin_amdgcn_sched_barrier(0);
+                Wf = fresh(Wf);
+            }
+            const int64_t i = r0 + k;
+            p0 = fma(Wf[2 * i], v[k], p0);
+            p1 = fma(Wf[2 * i + 1], v[k], p1);
+        }
+    }
+    sp[w][0][lane] = p0;
+    sp[w][1][lane] = p1;
+    __syncthreads();
+    if (w == 0) {
+        double P0 = 0.0, P1 = 0.0;
+#pragma unroll
+        for (int i = 0; i < W; i++) {
+            P0 += sp[i][0][lane];
+            P1 += sp[i][1][lane];
+        }
+        double *mp = pex + (int64_t)u * 128 + lane;
+        xstore(&mp[0], P0);
+        xstore(&mp[64], P1);
+        publish(&pst[u], 1u);
+    }
+
+    const TailCorr corr{Z,      &tst[t], tex + (int64_t)t * 128 + lane, err, sp[0], last, pst,
+                        pex,    u - (unsigned int)g, ngroups, sft, aux, X + jj, m, ldx, act};
+    group_phases<K, W, false, TailCorr>(v, fwd, bwd, seg, r0, w, g, ngroups, u - (unsigned int)g, fst,
+                                        bst, ex, err, sh, agg, mat, nullptr, nullptr, corr);
+    if (!act || L == 0) return;
     double *base = X + jj + r0 * ldx;
     if (L == K) {
 #pragma unroll

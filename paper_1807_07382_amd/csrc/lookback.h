@@ -155,24 +155,38 @@ __device__ __forceinline__ void respond(double (&v)[K], CFwd fwd, int64_t r0, do
 }
 
 // Back substitution over the segment from (q1, q2) = (x_{r0+K}, x_{r0+K+1});
-// on exit (q1, q2) = (x_{r0}, x_{r0+1}).  STORE writes x over v.
-template <int K, bool STORE, bool LREC = false>
+// on exit (q1, q2) = (x_{r0}, x_{r0+1}).  STORE writes x over v.  CORR
+// (periodic bordering) stores x_i - Z_i (c0, c1) instead, Z_i = rows 2i,
+// 2i+1 of Z, while the recurrence carries x itself; its Z rows come in the
+// same scalar batches as the records.
+template <int K, bool STORE, bool LREC = false, bool CORR = false>
 __device__ __forceinline__ void backward(double (&v)[K], CBwd bwd, int64_t r0, double &q1, double &q2,
-                                         const BwdRec *lb = nullptr)
+                                         const BwdRec *lb = nullptr, CDbl Z = nullptr,
+                                         double c0 = 0.0, double c1 = 0.0)
 {
 #pragma unroll
     for (int k = K - 1; k >= 0; k--) {
         if (!LREC && (k + 1) % kSchedRows == 0) {
             __builtin_amdgcn_sched_barrier(0);
             bwd = fresh(bwd);
+            if (CORR) Z = fresh(Z);
         }
         const double gm = LREC ? lb[k].gm : bwd[r0 + k].gm, dl = LREC ? lb[k].dl : bwd[r0 + k].dl;
         const double x = fma(-gm, q1, fma(-dl, q2, v[k]));
-        if (STORE) v[k] = x;
+        if (STORE) v[k] = CORR ? fma(-Z[2 * (r0 + k) + 1], c1, fma(-Z[2 * (r0 + k)], c0, x)) : x;
         q2 = q1;
         q1 = x;
     }
 }
+
+// No correction in group_phases (the plain single pass).
+struct NoCorr {
+    static constexpr bool on = false;
+    CDbl Z = nullptr;
+    __device__ void early(int) const {}
+    __device__ void fetch(int) const {}
+    __device__ void get(int, double &, double &) const {}
+};
 
 // One link of the interface chain, (y0, y1) <- w + T (y0, y1), T column-major.
 // Publishers and look-back use this one function with explicit fused
@@ -435,14 +449,14 @@ __device__ __forceinline__ void rec_wait(bool full)
 
 // Both sweeps of the block held by wave w of group g (rows r0 .. r0+K-1):
 // on exit v holds x.
-template <int K, int W, bool LREC = false>
+template <int K, int W, bool LREC = false, typename Corr = NoCorr>
 __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd, CSeg seg,
                                              int64_t r0, int w, int g, int ngroups,
                                              unsigned int u0, unsigned int *fst,
                                              unsigned int *bst, double *ex, unsigned int *err,
                                              double (*sh)[2][64], double (*agg)[128],
                                              double (*mat)[W][4], const FwdRec *lf = nullptr,
-                                             const BwdRec *lb = nullptr)
+                                             const BwdRec *lb = nullptr, Corr corr = Corr())
 {
     const int lane = threadIdx.x & 63;
     const int64_t s0 = (int64_t)g * W;
@@ -454,6 +468,7 @@ __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd,
         sh[w][1][lane] = e1;
     }
     __syncthreads();
+    if (W == 1) corr.early(lane);
     if (w == 0) {
         double E0 = 0.0, E1 = 0.0;
 #pragma unroll
@@ -473,6 +488,8 @@ __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd,
         }
         sh[W][0][lane] = Y0;
         sh[W][1][lane] = Y1;
+    } else if (w == W - 1) {
+        corr.early(lane);  // work that needs only the loaded blocks (an idle wave)
     }
     __syncthreads();
     {
@@ -511,13 +528,16 @@ __device__ __forceinline__ void group_phases(double (&v)[K], CFwd fwd, CBwd bwd,
         sh[W][0][lane] = Z0;
         sh[W][1][lane] = Z1;
     }
+    if (w == W - 1) corr.fetch(lane);  // the correction's coefficients into LDS (an idle wave)
     __syncthreads();
     {
         double z0 = sh[W][0][lane], z1 = sh[W][1][lane];
         for (int i = W - 1; i > w; i--)
             link(sh[i][0][lane], sh[i][1][lane], seg[s0 + i].tb[0], seg[s0 + i].tb[1],
                  seg[s0 + i].tb[2], seg[s0 + i].tb[3], z0, z1);
-        backward<K, true, LREC>(v, bwd, r0, z0, z1, lb);
+        double c0 = 0.0, c1 = 0.0;
+        corr.get(lane, c0, c1);
+        backward<K, true, LREC, Corr::on>(v, bwd, r0, z0, z1, lb, corr.Z, c0, c1);
     }
     // x is complete here: keep the compiler from sinking the sweep into the
     // block that stores x (past a caller's waits, with every coefficient
