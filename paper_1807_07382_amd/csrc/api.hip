@@ -11,6 +11,7 @@
 #include <new>
 #include <string>
 #include <tuple>
+#include <vector>
 
 #include "internal.h"
 
@@ -536,6 +537,8 @@ struct pent_cyclic_s {
     int kind = 0;               // 0 automatic, 1 E-solve + update kernels, 2 single pass
     int seg_rows = 64;          // single-pass segment height
     int cap[2][2] = {{0, 0}, {0, 0}};  // co-resident single-pass units [seg 32/64][solve/CN]
+    bool uni = false;           // each diagonal is the same in every row (bit for bit) ...
+    double uc[5] = {0, 0, 0, 0, 0};  // ... with these values, a..e
 };
 
 namespace {
@@ -645,6 +648,24 @@ pent_cyclic finish_cyclic(pent_cyclic c)
         ret(PENT_ZERO_PIVOT);
         return nullptr;
     }
+    // row-invariant diagonals (the constant-coefficient operators of the
+    // paper's periodic problems): the CN step then reads them from its
+    // arguments instead of five per-row loads
+    {
+        const int64_t ld = cyc_ld(n);
+        std::vector<double> h((size_t)(5 * ld));
+        if (hipMemcpy(h.data(), c->d_cd, sizeof(double) * 5 * ld, hipMemcpyDeviceToHost) != hipSuccess) {
+            free_cyclic(c);
+            ret(PENT_HIP_ERROR);
+            return nullptr;
+        }
+        bool uni = true;
+        for (int k = 0; k < 5 && uni; k++)
+            for (int64_t i = 1; i < n && uni; i++)
+                uni = std::memcmp(&h[k * ld + i], &h[k * ld], sizeof(double)) == 0;
+        c->uni = uni;
+        for (int k = 0; k < 5; k++) c->uc[k] = h[k * ld];
+    }
     c->magic = kCyclicMagic;
     ret(PENT_OK);
     return c;
@@ -674,7 +695,8 @@ int cyc_run_single(pent_cyclic c, bool cn, const double *F, int64_t ldf, double 
     hipError_t e = scratch_alloc(&xbuf, cyc_onepass_scratch_bytes(c->n, c->seg_rows, batch), s);
     if (e != hipSuccess) return hip_status(e);
     e = launch_cyc_onepass(c->E->d_fwd, c->E->d_bwd, seg, c->d_cd, c->d_Z, c->d_W, c->d_aux, c->n,
-                           c->seg_rows, cn, F, ldf, X, ldx, batch, xbuf, c->E->d_err, s);
+                           c->seg_rows, cn, F, ldf, X, ldx, batch, xbuf, c->E->d_err, s,
+                           c->uni ? c->uc : nullptr);
     const hipError_t e2 = hipFreeAsync(xbuf, s);
     return hip_status(e != hipSuccess ? e : e2);
 }

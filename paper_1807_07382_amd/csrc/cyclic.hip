@@ -242,6 +242,23 @@ __device__ __forceinline__ int64_t wrap(int64_t r, int64_t n)
     return r;
 }
 
+// f_i = 2 C_i - (A C)_i with row-invariant diagonals u (same operations in
+// the same order as cn_row).
+struct CycUni {
+    double c[5];
+};
+__device__ __forceinline__ double cn_row_u(const CycUni &u, double c0, double c1, double c2,
+                                           double c3, double c4)
+{
+    double acc = 2.0 * c2;
+    acc = fma(-u.c[0], c0, acc);
+    acc = fma(-u.c[1], c1, acc);
+    acc = fma(-u.c[2], c2, acc);
+    acc = fma(-u.c[3], c3, acc);
+    acc = fma(-u.c[4], c4, acc);
+    return acc;
+}
+
 // Waits until *p >= want; false (and *err raised) if the wait ran out.
 __device__ __forceinline__ bool wait_nonzero(unsigned int *p, unsigned int want, unsigned int *err)
 {
@@ -347,13 +364,13 @@ struct TailCorr {
     }
 };
 
-template <int K, int W, bool CN>
+template <int K, int W, bool CN, bool UNI>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_cyc_onepass(
     const FwdRec *fwd_, const BwdRec *bwd_, const SegRec *seg_, const double *__restrict__ cd_,
     const double *__restrict__ Z_, const double *__restrict__ Wt_, const CycAux *__restrict__ aux,
     int64_t n, int ngroups, const double *Fin, int64_t ldf, double *X, int64_t ldx, int64_t batch,
     unsigned int *ctr, unsigned int *fst, unsigned int *bst, unsigned int *pst, unsigned int *tst,
-    double *ex, double *pex, double *tex, unsigned int *err)
+    double *ex, double *pex, double *tex, unsigned int *err, CycUni uc)
 {
     PENT_GROUP_LDS(W);
     __shared__ double sp[W][2][64];
@@ -407,8 +424,10 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
             const double cm2 = act ? col[(m - 2) * ldf] : 0.0, cm1 = act ? col[(m - 1) * ldf] : 0.0;
             const double c_m = act ? col[m * ldf] : 0.0, c_m1 = act ? col[(m + 1) * ldf] : 0.0;
             const double c0 = act ? col[0] : 0.0, c1 = act ? col[ldf] : 0.0;
-            sft[0][lane] = cn_row(cd, cyc_ld(n), m, cm2, cm1, c_m, c_m1, c0);
-            sft[1][lane] = cn_row(cd, cyc_ld(n), m + 1, cm1, c_m, c_m1, c0, c1);
+            sft[0][lane] = UNI ? cn_row_u(uc, cm2, cm1, c_m, c_m1, c0)
+                               : cn_row(cd, cyc_ld(n), m, cm2, cm1, c_m, c_m1, c0);
+            sft[1][lane] = UNI ? cn_row_u(uc, cm1, c_m, c_m1, c0, c1)
+                               : cn_row(cd, cyc_ld(n), m + 1, cm1, c_m, c_m1, c0, c1);
         }
         double c2 = h0, c1 = h1;  // C_{k-2}, C_{k-1}
         CDbl cdf = cd;
@@ -418,7 +437,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
         asm volatile("" : "+s"(Ls));
 #pragma unroll
         for (int k = 0; k < K; k++) {
-            if (k % kSchedRows == 0) {
+            if (!UNI && k % kSchedRows == 0) {
                 __builtin_amdgcn_sched_barrier(0);
                 cdf = fresh(cdf);
             }
@@ -427,7 +446,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
             const double n2 = k + 2 < K ? v[k + 2] : (k + 2 == K ? h2 : h3);
             // rows past the E rows read zero padding (no select: the
             // addresses stay affine in k, scalar loads with immediate offsets)
-            const double f = cn_row(cdf, cyc_ld(n), r0 + k, c2, c1, ck, n1, n2);
+            const double f = UNI ? cn_row_u(uc, c2, c1, ck, n1, n2)
+                                 : cn_row(cdf, cyc_ld(n), r0 + k, c2, c1, ck, n1, n2);
             v[k] = k < Ls ? f : 0.0;
             c2 = c1;
             c1 = ck;
@@ -545,15 +565,16 @@ size_t cyc_onepass_scratch_bytes(int64_t n, int seg_rows, int64_t batch)
 }
 
 template <int K, int W>
-static const void *cyc_fn(bool cn)
+static const void *cyc_fn(bool cn, bool uni)
 {
-    return cn ? (const void *)k_cyc_onepass<K, W, true> : (const void *)k_cyc_onepass<K, W, false>;
+    if (!cn) return (const void *)k_cyc_onepass<K, W, false, false>;
+    return uni ? (const void *)k_cyc_onepass<K, W, true, true> : (const void *)k_cyc_onepass<K, W, true, false>;
 }
 
-static const void *cyc_fn_kw(int K, int W, bool cn)
+static const void *cyc_fn_kw(int K, int W, bool cn, bool uni = false)
 {
-    if (K == 64) return W == 2 ? cyc_fn<64, 2>(cn) : W == 4 ? cyc_fn<64, 4>(cn) : cyc_fn<64, 8>(cn);
-    return W == 2 ? cyc_fn<32, 2>(cn) : W == 4 ? cyc_fn<32, 4>(cn) : cyc_fn<32, 8>(cn);
+    if (K == 64) return W == 2 ? cyc_fn<64, 2>(cn, uni) : W == 4 ? cyc_fn<64, 4>(cn, uni) : cyc_fn<64, 8>(cn, uni);
+    return W == 2 ? cyc_fn<32, 2>(cn, uni) : W == 4 ? cyc_fn<32, 4>(cn, uni) : cyc_fn<32, 8>(cn, uni);
 }
 
 int cyc_onepass_capacity(int seg_rows, bool cn)
@@ -573,7 +594,7 @@ hipError_t launch_cyc_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec
                               const CycAux *aux, int64_t n,
                               int seg_rows, bool cn, const double *Fin, int64_t ldf, double *X,
                               int64_t ldx, int64_t batch, void *scratch, unsigned int *err,
-                              hipStream_t s)
+                              hipStream_t s, const double *uni)
 {
     if (seg_rows != 32 && seg_rows != 64) return hipErrorInvalidValue;
     const int W = cyc_waves(seg_rows);
@@ -592,13 +613,16 @@ hipError_t launch_cyc_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     int ng = (int)ngroups;
+    CycUni uc = {{0.0, 0.0, 0.0, 0.0, 0.0}};
+    if (uni)
+        for (int k = 0; k < 5; k++) uc.c[k] = uni[k];
     void *args[] = {(void *)&fwd, (void *)&bwd, (void *)&seg, (void *)&cd, (void *)&Z, (void *)&Wt,
                     (void *)&aux, (void *)&n, (void *)&ng, (void *)&Fin, (void *)&ldf, (void *)&X,
                     (void *)&ldx, (void *)&batch, (void *)&ctr, (void *)&fst, (void *)&bst,
                     (void *)&pst, (void *)&tst, (void *)&ex, (void *)&pex, (void *)&tex,
-                    (void *)&err};
-    return hipLaunchKernel(cyc_fn_kw(seg_rows, W, cn), dim3((unsigned)units), dim3(64 * W), args, 0,
-                           s);
+                    (void *)&err, (void *)&uc};
+    return hipLaunchKernel(cyc_fn_kw(seg_rows, W, cn, uni != nullptr), dim3((unsigned)units),
+                           dim3(64 * W), args, 0, s);
 }
 
 hipError_t launch_cyc_assemble_d4(double *cd, int64_t n, double sigma, hipStream_t s)

@@ -408,12 +408,14 @@ int64_t cyc_onepass_groups(int64_t n, int seg_rows);  // workgroups per 64-syste
 int64_t cyc_onepass_units(int64_t n, int seg_rows, int64_t batch);
 size_t cyc_onepass_scratch_bytes(int64_t n, int seg_rows, int64_t batch);
 int cyc_onepass_capacity(int seg_rows, bool cn);
+// uni (host, 5 doubles, or null): the five cyclic diagonals when each is
+// the same in every row; the CN step then takes them as arguments.
 hipError_t launch_cyc_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg,
                               const double *cd, const double *Z, const double *Wt,
                               const CycAux *aux, int64_t n,
                               int seg_rows, bool cn, const double *Fin, int64_t ldf, double *X,
                               int64_t ldx, int64_t batch, void *scratch, unsigned int *err,
-                              hipStream_t s);
+                              hipStream_t s, const double *uni = nullptr);
 hipError_t launch_cyc_finish(const double *cd, int64_t n, const double *Z, CycAux *aux,
                              hipStream_t s);
 // etd: 5(n-2) diagonals of E^T; H: zrows x 2, ld 2, H[i][q] = A[n-2+q][i]

@@ -151,6 +151,37 @@ def test_cn_step_against_oracle(torch, n, batch, sigma, kind, seg):
     assert np.max(np.abs(got - ref)) <= 4 * d4_tol(sigma) * np.max(np.abs(C))
 
 
+@pytest.mark.parametrize("kind,seg", SCHEDULES)
+@pytest.mark.parametrize("n,batch", [(5, 3), (67, 65), (1000, 130), (4097, 64)])
+def test_cn_step_general_against_oracle(torch, n, batch, kind, seg):
+    """The Crank-Nicolson step X = A^{-1}(2C - AC) for row-varying
+    diagonals (the single pass then reads them per row; the constant
+    operator of factor_d4 takes them as kernel arguments), against the
+    oracle's dense product and bordered solve."""
+    print_case(test="cn_step_general", n=n, batch=batch, kind=kind, seg=seg)
+    dg = random_dominant(n, seed=3 * n + 1)
+    C = rhs(n, batch, seed=n + 5)
+    R = 2.0 * C - cyclic.dense_cyclic(dg) @ C
+    ref = cyclic.solve_cyclic(cyclic.bordering(dg), R)
+    with pb.Cyclic.factor(*dg) as cy:
+        cy.set_schedule(kind, seg or 64)
+        assert cy.schedule_for(batch, cn=True)[0] == kind
+        Ct = torch.from_numpy(C).cuda()
+        X = torch.full_like(Ct, 5.0)
+        cy.cn_step(Ct, X)
+        torch.cuda.synchronize()
+        cy.check()
+        got = X.cpu().numpy()
+    off = np.abs(dg.a) + np.abs(dg.b) + np.abs(dg.d) + np.abs(dg.e)
+    norm_a = float(np.max(off + np.abs(dg.c)))
+    dom = float(np.min(np.abs(dg.c) - off))  # ||A^{-1}||_inf <= 1 / dom (Varah)
+    # the stencil's rounding (six terms bounded by (2 + ||A||) max|C|)
+    # through A^{-1}, plus the solve's own error
+    tol = 16 * U * (2 + norm_a) * np.max(np.abs(C)) / dom + \
+        64 * U * varah_kappa(dg) * np.max(np.abs(ref))
+    assert np.max(np.abs(got - ref)) <= tol
+
+
 @pytest.mark.parametrize("seg", [32, 64])
 def test_cn_step_single_pass_deterministic(torch, seg):
     """The single-pass step gives the same bits on every run and for a
