@@ -283,7 +283,7 @@ struct TailCorr {
     static constexpr bool on = true;
     CDbl Z;
     unsigned int *tst;
-    double *tx;  // the lane's x_tail (rows 0 and 64)
+    double *tx;  // the tile's x_tail (rows 0 and 64, a column per lane)
     unsigned int *err;
     double (*xt)[64];  // LDS, 2 x 64
     bool last;         // this group forms x_tail
@@ -293,7 +293,7 @@ struct TailCorr {
     int ngroups;
     const double (*sft)[64];  // LDS: f_{n-2}, f_{n-1} of the tile
     const CycAux *aux;
-    double *xcol;  // the lane's column of X
+    double *xt_rows;  // X + the tile's first column
     int64_t m, ldx;
     bool act;
     __device__ void early(int lane) const
@@ -338,18 +338,18 @@ struct TailCorr {
         const double r0v = sft[0][lane] - d0, r1v = sft[1][lane] - d1;
         const double xt0 = fma(aux->minv[1], r1v, aux->minv[0] * r0v);
         const double xt1 = fma(aux->minv[3], r1v, aux->minv[2] * r0v);
-        xstore(&tx[0], xt0);
-        xstore(&tx[64], xt1);
+        xstore(&tx[lane], xt0);
+        xstore(&tx[64 + lane], xt1);
         publish(tst, 1u);
         if (act) {
-            xcol[m * ldx] = xt0;
-            xcol[(m + 1) * ldx] = xt1;
+            xt_rows[m * ldx + lane] = xt0;
+            xt_rows[(m + 1) * ldx + lane] = xt1;
         }
     }
     __device__ void fetch(int lane) const
     {
         const bool seen = wait_nonzero(tst, 1u, err);
-        double a = xload(&tx[0]), b = xload(&tx[64]);
+        double a = xload(&tx[lane]), b = xload(&tx[64 + lane]);
         if (!seen) {  // the tail never arrived: NaN instead of stale values
             a = __builtin_nan("");
             b = __builtin_nan("");
@@ -501,8 +501,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
         publish(&pst[u], 1u);
     }
 
-    const TailCorr corr{Z,      &tst[t], tex + (int64_t)t * 128 + lane, err, sp[0], last, pst,
-                        pex,    u - (unsigned int)g, ngroups, sft, aux, X + jj, m, ldx, act};
+    const TailCorr corr{Z,   &tst[t], tex + (int64_t)t * 128, err, sp[0], last, pst, pex,
+                        u - (unsigned int)g, ngroups, sft, aux, X + (int64_t)t * 64, m, ldx, act};
     group_phases<K, W, false, TailCorr>(v, fwd, bwd, seg, r0, w, g, ngroups, u - (unsigned int)g, fst,
                                         bst, ex, err, sh, agg, mat, nullptr, nullptr, corr);
     if (!act || L == 0) return;
