@@ -132,6 +132,19 @@ __device__ __forceinline__ double lane_double(double v, int l)
     return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
 }
 
+// The double of lane l - 1 (UP) or l + 1 of the wave, by a DPP wave shift;
+// the lane with no such neighbour (0, resp. 63) gets edge.  Every lane of
+// the wave must be active.
+template <bool UP>
+__device__ __forceinline__ double lane_shift(double x, double edge)
+{
+    constexpr int ctrl = UP ? 0x138 : 0x130;  // wave_shr:1 / wave_shl:1
+    const long long xi = __double_as_longlong(x), ei = __double_as_longlong(edge);
+    const int lo = __builtin_amdgcn_update_dpp((int)ei, (int)xi, ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(ei >> 32), (int)(xi >> 32), ctrl, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
 // r = f - A x over a block held in v (x on entry, r on exit), compensated
 // (dot2_row); rows k >= L zero.  8 rows per batch, one batch ahead: f by
 // row, and the batch's 5 x 8 diagonal entries by one gathering load (lane
@@ -200,10 +213,10 @@ __device__ __forceinline__ void fix_residual(double (&v)[K], const double *diag,
 // tile does not straddle two): a system's y neighbours are the adjacent
 // lanes, read back through the transpose buffer, plus one halo system above
 // and below the tile (one row per lane); its x neighbours are the adjacent
-// rows in registers, plus one value past each end of the block.  Three
-// waves per SIMD in both forms (the stencil's batches are not fenced off
-// from each other by scheduling barriers: with them its y-neighbour reads
-// were hoisted into a long-lived set that spilled).
+// rows in registers, plus one value past each end of the block.  The y
+// neighbours' terms come by DPP wave shifts of the row's own term (lanes 0
+// and 63 take the halo systems' instead).  Three waves per SIMD in both
+// forms.
 template <int K, int W, bool ST>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) void k_onepass_t(
     const FwdRec *fwd_, const BwdRec *bwd_, const SegRec *seg_, int64_t n, int ngroups, double *F,
@@ -214,7 +227,6 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     static_assert(!ST || K == 64, "the halo rows are held one per lane");
     PENT_GROUP_LDS(W);
     __shared__ double tb[W][8][66];  // row stride 66: the transposing writes hit distinct banks
-    __shared__ double hw[ST ? W : 1][2][64];  // ST: the halo systems' C^3 - C, by row
     __shared__ double xe[ST ? W : 1][2][64];  // ST: each block's first and last row of C
     __shared__ unsigned int s_unit;
     const CFwd fwd = (CFwd)fwd_;
@@ -325,15 +337,12 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
         }
     }
     if constexpr (ST) {
-        // right-hand side in place, 8 rows at a time: the rows' C^3 - C go
-        // through the buffer (column 1 + lane) so each lane reads its y
-        // neighbours'; lanes 0 and 63 read the halo systems' (hw, by row)
-        // instead.  Every lane reads (from a selected address) and masks
-        // the value: a read under a per-lane test would become a branch per
-        // row.  x neighbours roll along the rows.
+        // right-hand side in place, row by row: the y neighbours' C^3 - C by
+        // wave shifts of the row's own (lanes 0 and 63 take the halo
+        // systems', held lane = row and read out per row); x neighbours roll
+        // along the rows
         const bool west = r0 >= 1, east = r0 + K < n;
-        hw[w][0][lane] = ch_wterm(h0);
-        hw[w][1][lane] = ch_wterm(h1);
+        const double hs = ch_wterm(h0), hn = ch_wterm(h1);
         xe[w][0][lane] = v[0];
         xe[w][1][lane] = v[K - 1];
         __syncthreads();
@@ -342,29 +351,17 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
         double wprev = west ? ch_wterm(xl) : 0.0;
         double wcur = ch_wterm(v[0]);
 #pragma unroll
-        for (int b = 0; b < K / 8; b++) {
-#pragma unroll
-            for (int k = 0; k < 8; k++) tw[k][lane + 1] = ch_wterm(v[8 * b + k]);
-            // other lanes' writes are read below, and this batch's reads
-            // precede the next batch's writes: to one lane the addresses
-            // never coincide, so without these fences the compiler may
-            // reorder them (the wave's LDS accesses then run in order)
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
-#pragma unroll
-            for (int k = 0; k < 8; k++) {
-                const int row = 8 * b + k;
-                const double tn = *(lane == 63 ? &hw[w][1][row] : &tw[k][lane + 2]);
-                const double ts = *(lane == 0 ? &hw[w][0][row] : &tw[k][lane]);
-                const double wn = dn ? tn : 0.0;
-                const double ws = up ? ts : 0.0;
-                const double wnext = ch_wterm(row + 1 < K ? v[row + 1] : xr);
-                const double we = (row + 1 < K ? r0 + row + 1 < n : east) ? wnext : 0.0;
-                const double r = ch_point(v[row], wcur, we, wprev, wn, ws, dtk, inv_h2);
-                wprev = wcur;
-                wcur = wnext;
-                v[row] = row < L ? r : 0.0;
-            }
-            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        for (int row = 0; row < K; row++) {
+            const double ts = lane_shift<true>(wcur, lane_double(hs, row));
+            const double tn = lane_shift<false>(wcur, lane_double(hn, row));
+            const double wn = dn ? tn : 0.0;
+            const double ws = up ? ts : 0.0;
+            const double wnext = ch_wterm(row + 1 < K ? v[row + 1] : xr);
+            const double we = (row + 1 < K ? r0 + row + 1 < n : east) ? wnext : 0.0;
+            const double r = ch_point(v[row], wcur, we, wprev, wn, ws, dtk, inv_h2);
+            wprev = wcur;
+            wcur = wnext;
+            v[row] = row < L ? r : 0.0;
         }
     }
     group_phases<K, W>(v, fwd, bwd, seg, r0, w, g, ngroups, u - (unsigned int)g, fst, bst, ex, err,
