@@ -263,6 +263,32 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     // in one instance) is one per-lane base plus uniform offsets; a ragged
     // one clamps each address.  (the 16-byte accesses also need every
     // system's run 16-byte aligned: an even ld and F itself aligned)
+    // ST: the values around the block, issued ahead of the block's loads
+    // (they come from scattered lines; the stencil waits for them last)
+    double xl = 0.0, xr = 0.0, h0 = 0.0, h1 = 0.0, dtk = 0.0;
+    bool up = false, dn = false;
+    if constexpr (ST) {
+        const int64_t sl = s0 + lane < batch ? s0 + lane : batch - 1;  // this lane's system
+        const int64_t kl = sl / ny, yl = sl - kl * ny;
+        const int64_t bl = (yl * ninst + kl) * ld;
+        up = yl >= 1;
+        dn = yl + 1 < ny;
+        // the rows just past the block: inside the workgroup they are its
+        // neighbour waves' (exchanged below); only the group's first and
+        // last wave load them (a block wholly past the matrix, r0 >= n,
+        // clamps both to row n - 1)
+        if (w == 0) xl = Cin[bl + (r0 < 1 ? 0 : r0 - 1 < n ? r0 - 1 : n - 1)];
+        if (w == W - 1) xr = Cin[bl + (r0 + K < n ? r0 + K : n - 1)];
+        dtk = dt[kl];
+        // halo systems: s0 - 1 above lane 0, s0 + 64 below lane 63 (each used
+        // only where that lane's own mask allows: same instance, inside the
+        // grid), row r0 + lane of each
+        const int64_t hrow = r0 + lane < n ? r0 + lane : n - 1;
+        const int64_t sa = s0 >= 1 ? s0 - 1 : 0;
+        const int64_t sb = s0 + 64 < batch ? s0 + 64 : batch - 1;
+        h0 = Cin[sbase(sa) + hrow];
+        h1 = Cin[sbase(sb) + hrow];
+    }
     typedef double Dbl2 __attribute__((ext_vector_type(2)));
     bool full = L == K && s0 + 64 <= batch && ld % 2 == 0 && (uintptr_t)F % 16 == 0;
     if constexpr (ST) full = full && s0 % ny + 64 <= ny && (uintptr_t)Cin % 16 == 0;
@@ -293,31 +319,6 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
             }
             __builtin_amdgcn_sched_barrier(0);  // 16 loads at a time: few addresses live
         }
-    }
-    // ST: the values around the block, loaded now to arrive with it
-    double xl = 0.0, xr = 0.0, h0 = 0.0, h1 = 0.0, dtk = 0.0;
-    bool up = false, dn = false;
-    if constexpr (ST) {
-        const int64_t sl = s0 + lane < batch ? s0 + lane : batch - 1;  // this lane's system
-        const int64_t kl = sl / ny, yl = sl - kl * ny;
-        const int64_t bl = (yl * ninst + kl) * ld;
-        up = yl >= 1;
-        dn = yl + 1 < ny;
-        // the rows just past the block: inside the workgroup they are its
-        // neighbour waves' (exchanged below); only the group's first and
-        // last wave load them (a block wholly past the matrix, r0 >= n,
-        // clamps both to row n - 1)
-        if (w == 0) xl = Cin[bl + (r0 < 1 ? 0 : r0 - 1 < n ? r0 - 1 : n - 1)];
-        if (w == W - 1) xr = Cin[bl + (r0 + K < n ? r0 + K : n - 1)];
-        dtk = dt[kl];
-        // halo systems: s0 - 1 above lane 0, s0 + 64 below lane 63 (each used
-        // only where that lane's own mask allows: same instance, inside the
-        // grid), row r0 + lane of each
-        const int64_t hrow = r0 + lane < n ? r0 + lane : n - 1;
-        const int64_t sa = s0 >= 1 ? s0 - 1 : 0;
-        const int64_t sb = s0 + 64 < batch ? s0 + 64 : batch - 1;
-        h0 = Cin[sbase(sa) + hrow];
-        h1 = Cin[sbase(sb) + hrow];
     }
     // transpose in place, one row parity at a time (8 rows through the 8-row
     // buffer): afterwards v[k] = (row r0 + k, system s0 + lane)
