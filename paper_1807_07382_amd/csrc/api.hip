@@ -49,10 +49,10 @@ constexpr uint64_t kPoolKeepBytes = (uint64_t)4 << 30;
 std::mutex g_pool_mu;
 std::map<int, hipMemPool_t> g_pools;  // device -> pool
 
-hipError_t device_pool(hipMemPool_t *out)
+hipError_t device_pool(hipStream_t s, hipMemPool_t *out)
 {
     int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
+    hipError_t e = hipStreamGetDevice(s, &dev);  // the stream's device, as hipMallocAsync
     if (e != hipSuccess) return e;
     std::lock_guard<std::mutex> lk(g_pool_mu);
     auto it = g_pools.find(dev);
@@ -78,11 +78,12 @@ hipError_t device_pool(hipMemPool_t *out)
     return hipSuccess;
 }
 
-// Stream-ordered scratch of `bytes` on s (free it with hipFreeAsync on s).
+// Stream-ordered scratch of `bytes` on s, on the stream's device (free it
+// with hipFreeAsync on s).
 hipError_t scratch_alloc(void **p, size_t bytes, hipStream_t s)
 {
     hipMemPool_t pool = nullptr;
-    const hipError_t e = device_pool(&pool);
+    const hipError_t e = device_pool(s, &pool);
     if (e != hipSuccess) return e;
     return hipMallocFromPoolAsync(p, bytes, pool, s);
 }
