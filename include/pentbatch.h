@@ -375,6 +375,9 @@ int pent_cyclic_destroy(pent_cyclic c);
  *   formula).  C, X DEVICE FP64, layout as above, different buffers (C is
  *   read with two rows of halo on each side).  In the single-pass form the
  *   right-hand side never goes to memory: C is read once and X written once.
+ *   Where each of the five diagonals is the same in every row, bit for bit
+ *   (checked when the handle is made; I + sigma D4 is), the single pass
+ *   takes them as values instead of reading them per row (same results).
  * pent_cyclic_set_schedule: kind 0 automatic (single pass when every block
  *   of one 64-system tile fits on the device at once), kind 1 the E-solve
  *   followed by the update kernels (and, for the step, a separate stencil
