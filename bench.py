@@ -211,6 +211,10 @@ def all_configs(args, torch):
     prec = {}
     for sg in (1.0, 1e2, 1e4):
         prec[f"sigma={sg:g}"] = precision_compare(torch, sg)
+    # HBM bytes of one FP32-stream solve (k = 0) at N = 8192 x 131072 from the
+    # committed counters, against its 12 B per unknown
+    prec["fp32_stream_refine0_traffic"] = traffic_for("onepass64_f32", "precision",
+                                                      ("onepass.hip", "lookback.h"))
     prec["note"] = ("FP32 is the storage precision of the right-hand-side stream; the factors, "
                     "every operation and x are FP64, so the k=0 solve already has FP64 accuracy "
                     "(same eta as the FP64 solve) and is the form that beats FP64 (12 instead of "
@@ -767,7 +771,8 @@ def run_rewrite(args, torch):
                 config=dict(workload="rewrite", n=n, systems=batch,
                             matrices="one per system, refactored every call"),
                 roofline=dict(bound="hbm", achieved=gbs, peak=PEAK_HBM_GBS, unit="GB/s",
-                              frac=gbs / PEAK_HBM_GBS, traffic=None, bytes_per_unknown=56),
+                              frac=gbs / PEAK_HBM_GBS, bytes_per_unknown=56,
+                              traffic=traffic_for("rewrite_lane", "rewrite", ("rewrite.hip",))),
                 kernel_plan_roofline=dict(bytes_per_unknown=104, achieved=gbs104,
                                           frac=gbs104 / PEAK_HBM_GBS),
                 parity=dict(probe_systems=len(cols), max_rel_err_vs_oracle=err),
