@@ -281,9 +281,9 @@ def tiled_layout(torch, steps=50):
 
 def copy_ceiling(torch, reps=20):
     """Read+write bandwidth of plain copies of the hyperdiffusion state (2
-    GiB, FP64) in this run: torch's device copy, and the library's copy
-    through the single pass's blocks (64 systems x 64 rows per wave, four
-    waves down the rows, in place)."""
+    GiB, FP64) in this run: torch's device copy, the library's copy through
+    the single pass's blocks (64 systems x 64 rows per wave, four waves down
+    the rows, in place), and the same copy with other workgroup shapes."""
     from paper_1807_07382_amd import inputs
     from paper_1807_07382_amd import pentbatch as pb
     n, batch = inputs.HYPERDIFF["n"], inputs.HYPERDIFF["batch"]
@@ -298,6 +298,12 @@ def copy_ceiling(torch, reps=20):
     pb.stream_copy(dst, dst, stream)
     ms = _timed(torch, stream, lambda: pb.stream_copy(dst, dst, stream), reps)
     out["single_pass_blocks_GBs"] = nbytes / (ms / 1e3) / 1e9
+    # the same copy with other workgroup shapes (tiles side by side x waves
+    # down): what the block shape alone does to the bandwidth on this layout
+    for ta, wd in ((1, 2), (2, 2), (2, 1), (4, 1)):
+        pb.stream_copy_shaped(dst, dst, ta, wd, stream)
+        ms = _timed(torch, stream, lambda: pb.stream_copy_shaped(dst, dst, ta, wd, stream), reps)
+        out[f"blocks_{ta}_across_{wd}_down_GBs"] = nbytes / (ms / 1e3) / 1e9
     del src, dst
     torch.cuda.empty_cache()
     return out

@@ -469,6 +469,18 @@ int pent_query_schedule(pent_handle h, int64_t batch, int *kind, int *seg_rows);
 int pent_stream_copy(const double *src, int64_t ld_src, double *dst, int64_t ld_dst, int64_t n,
                      int64_t batch, void *stream);
 
+/* The same copy with another workgroup shape: tiles_across 64-system tiles
+ * side by side, each covered by waves_down waves of 64 rows, (tiles_across,
+ * waves_down) in {(1, 4), (1, 2), (2, 2), (2, 1), (4, 1)}; (1, 4) is
+ * pent_stream_copy.  Wider shapes read longer runs of each row at once and
+ * copy faster on the batch-fastest layout; a solve would pay for them with
+ * longer interface chains (more, shorter groups per tile).  Measurement
+ * only.  PENT_INVALID_VALUE for another shape or the arguments rejected by
+ * pent_stream_copy. */
+int pent_stream_copy_shaped(const double *src, int64_t ld_src, double *dst, int64_t ld_dst,
+                            int64_t n, int64_t batch, int tiles_across, int waves_down,
+                            void *stream);
+
 /* --------------------------------------------------------------- status -- */
 int pent_last_status(void);
 int64_t pent_last_pivot_row(void); /* row of the last PENT_ZERO_PIVOT, else -1 */

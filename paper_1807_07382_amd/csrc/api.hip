@@ -1861,6 +1861,20 @@ int pent_stream_copy(const double *src, int64_t ld_src, double *dst, int64_t ld_
     return ret(hip_status(launch_block_copy(src, dst, n, batch, ld_src, ld_dst, (hipStream_t)stream)));
 }
 
+int pent_stream_copy_shaped(const double *src, int64_t ld_src, double *dst, int64_t ld_dst,
+                            int64_t n, int64_t batch, int tiles_across, int waves_down,
+                            void *stream)
+{
+    const bool shape = (tiles_across == 1 && (waves_down == 2 || waves_down == 4)) ||
+                       (tiles_across == 2 && (waves_down == 1 || waves_down == 2)) ||
+                       (tiles_across == 4 && waves_down == 1);
+    if (!shape || n < 1 || batch < 0 || ld_src < batch || ld_dst < batch) return ret(PENT_INVALID_VALUE);
+    if (batch == 0) return ret(PENT_OK);
+    if (!src || !dst) return ret(PENT_INVALID_VALUE);
+    return ret(hip_status(launch_block_copy(src, dst, n, batch, ld_src, ld_dst, (hipStream_t)stream,
+                                            tiles_across, waves_down)));
+}
+
 int pent_last_status(void) { return g_status; }
 
 int64_t pent_last_pivot_row(void) { return g_pivot_row; }

@@ -375,7 +375,7 @@ hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *se
 
 // ---- measurement (copy.hip): dst = src through the single pass's blocks ----
 hipError_t launch_block_copy(const double *src, double *dst, int64_t n, int64_t batch, int64_t lds,
-                             int64_t ldd, hipStream_t s);
+                             int64_t ldd, hipStream_t s, int tiles_across = 1, int waves_down = 4);
 
 // ---- per-system matrices, refactored every call (rewrite.hip) ----
 // work: 256 bytes of header (first failing pivot key, system * n + row) and

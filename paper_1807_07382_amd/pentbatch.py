@@ -88,6 +88,7 @@ SIGNATURES = {
     "pent_check": (_I, [_P]),
     "pent_query_schedule": (_I, [_P, _I64, ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "pent_stream_copy": (_I, [_P, _I64, _P, _I64, _I64, _I64, _P]),
+    "pent_stream_copy_shaped": (_I, [_P, _I64, _P, _I64, _I64, _I64, _I, _I, _P]),
     "pent_last_status": (_I, []),
     "pent_last_pivot_row": (_I64, []),
     "pent_status_string": (ctypes.c_char_p, [_I]),
@@ -643,4 +644,20 @@ def stream_copy(src, dst, stream=None):
             raise ValueError("unit batch stride required")
     _check(lib().pent_stream_copy(_dptr(src, "float64"), max(src.stride(0), m), _dptr(dst, "float64"),
                                   max(dst.stride(0), m), n, m, _stream_ptr(stream)), "stream_copy")
+    return dst
+
+
+def stream_copy_shaped(src, dst, tiles_across: int, waves_down: int, stream=None):
+    """stream_copy with another workgroup shape (tiles side by side x waves
+    down the rows; see pent_stream_copy_shaped)."""
+    if src.shape != dst.shape or src.dim() != 2:
+        raise ValueError("src and dst must have one (n, batch) shape")
+    n, m = src.shape
+    for t in (src, dst):
+        if m > 1 and t.stride(1) != 1:
+            raise ValueError("unit batch stride required")
+    _check(lib().pent_stream_copy_shaped(_dptr(src, "float64"), max(src.stride(0), m),
+                                         _dptr(dst, "float64"), max(dst.stride(0), m), n, m,
+                                         int(tiles_across), int(waves_down), _stream_ptr(stream)),
+           "stream_copy_shaped")
     return dst

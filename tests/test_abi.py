@@ -143,3 +143,17 @@ def test_rewrite_rejects_bad_arguments_without_hip():
     assert L.pent_solve_rewrite(8, p, p, p, p, p, 4, p, 4, 4, p, need - 1, None) == pb.SIZE_MISMATCH
     assert L.pent_solve_rewrite(8, p, p, p, p, p, 4, p, 0, 4, p, need, None) == pb.OK
     assert L.pent_rewrite_check(None, 8, None, None) == pb.INVALID_VALUE
+
+
+def test_stream_copy_rejects_bad_arguments_without_hip():
+    L = pb.lib()
+    buf = (ctypes.c_double * 64)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    # shapes other than the five measured ones, bad sizes, null pointers
+    for ta, wd in ((1, 1), (3, 1), (4, 2), (1, 8), (0, 4), (2, 4)):
+        assert L.pent_stream_copy_shaped(p, 8, p, 8, 8, 8, ta, wd, None) == pb.INVALID_VALUE
+    assert L.pent_stream_copy_shaped(p, 8, p, 8, 0, 8, 1, 2, None) == pb.INVALID_VALUE
+    assert L.pent_stream_copy_shaped(p, 4, p, 8, 8, 8, 1, 2, None) == pb.INVALID_VALUE
+    assert L.pent_stream_copy_shaped(None, 8, p, 8, 8, 8, 2, 2, None) == pb.INVALID_VALUE
+    assert L.pent_stream_copy_shaped(p, 8, p, 8, 8, 0, 4, 1, None) == pb.OK  # empty batch: no-op
+    assert L.pent_stream_copy(p, 8, None, 8, 8, 8, None) == pb.INVALID_VALUE
