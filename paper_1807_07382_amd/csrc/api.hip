@@ -117,7 +117,9 @@ pent_plan *new_plan(int64_t n, int *st)
     }
     p->magic = 0;
     p->n = n;
-    p->npad = (n + kRecPad - 1) / kRecPad * kRecPad;
+    // past n, room for one more group of the many-matrix single pass (it
+    // reads whole groups of 4 x kGroupSegRows records)
+    p->npad = (n + 256 + kRecPad - 1) / kRecPad * kRecPad;
     p->d_diag = nullptr;
     p->d_fac = nullptr;
     p->d_anorm = nullptr;
@@ -214,7 +216,7 @@ pent_handle finish_factor(pent_plan *p)
 // any stream see the finished constants.
 const SegRec *seg_cache_locked(pent_plan *p, int seg_rows, int *st, bool sync = true)
 {
-    int slot = seg_rows == 16 ? 0 : seg_rows == 32 ? 1 : 2;
+    const int slot = seg_slot(seg_rows);
     SegCache &c = p->seg[slot];
     if (c.d_seg) {
         *st = PENT_OK;
@@ -780,6 +782,10 @@ int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64
         if (!seg64) return st;
         const GrpRec *grp64 = grp_cache(p, 64, 4, &st);
         if (!grp64) return st;
+        const SegRec *segp = seg_cache(p, kGroupSegRows, &st);
+        if (!segp) return st;
+        const GrpRec *grpp = grp_cache(p, kGroupSegRows, 4, &st);
+        if (!grpp) return st;
         int kind, seg_rows;
         io_schedule(p, batch[k], true, &kind, &seg_rows);
         if ((kind == 2 || kind == 4) && !seg_cache(p, seg_rows, &st)) return st;
@@ -788,7 +794,8 @@ int group_bind(pent_group g, double *const *F, const int64_t *batch, const int64
             const double *tr;
             if (!tile_cache(p, tile_rows_for(p->n), &sc, &tr, &st)) return st;
         }
-        mats[k] = GroupMat{p->d_fwd, p->d_bwd, seg64, grp64, F[k], p->n, p->npad, ld[k], batch[k]};
+        mats[k] = GroupMat{p->d_fwd, p->d_bwd, seg64, grp64, F[k], p->n, p->npad, ld[k], batch[k],
+                           segp, grpp};
     }
     for (size_t k = 0; k < cnt; k++)
         for (int64_t c0 = 0; c0 < batch[k]; c0 += 64)
@@ -1015,8 +1022,7 @@ bool tables_ready(pent_plan *p, int kind, int seg_rows)
         const int rows = tile_rows_for(p->n);
         return p->d_scan != nullptr && p->scan_rows == rows;
     }
-    const int slot = seg_rows == 16 ? 0 : seg_rows == 32 ? 1 : 2;
-    return p->seg[slot].d_seg != nullptr;
+    return p->seg[seg_slot(seg_rows)].d_seg != nullptr;
 }
 
 }  // namespace

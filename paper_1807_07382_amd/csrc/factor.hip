@@ -401,6 +401,9 @@ hipError_t launch_seg_prep(const FwdRec *d_fwd, const BwdRec *d_bwd, int64_t n, 
     case 16: hipLaunchKernelGGL(k_seg_prep<16>, grid, dim3(bs), 0, s, d_fwd, d_bwd, n, nseg, d_seg); break;
     case 32: hipLaunchKernelGGL(k_seg_prep<32>, grid, dim3(bs), 0, s, d_fwd, d_bwd, n, nseg, d_seg); break;
     case 64: hipLaunchKernelGGL(k_seg_prep<64>, grid, dim3(bs), 0, s, d_fwd, d_bwd, n, nseg, d_seg); break;
+    case kGroupSegRows:
+        hipLaunchKernelGGL(k_seg_prep<kGroupSegRows>, grid, dim3(bs), 0, s, d_fwd, d_bwd, n, nseg, d_seg);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -123,6 +123,8 @@ struct GroupMat {
     const GrpRec *grp64;  // group constants for 64-row segments, four per group
     double *F;          // right-hand sides, batch-fastest, overwritten in place
     int64_t n, npad, ld, batch;
+    const SegRec *segp;  // the single pass's segments (kGroupSegRows rows) ...
+    const GrpRec *grpp;  // ... and its group constants (four segments per group)
 };
 
 // One work item: up to 64 consecutive systems of one matrix.
@@ -157,7 +159,15 @@ struct GroupUnit {
     int64_t u0;
 };
 
-constexpr int kMaxSegCaches = 3;  // seg_rows 16, 32, 64
+constexpr int kMaxSegCaches = 4;  // seg_rows 16, 32, 64 and the group single pass's
+// Segment height of the many-matrix single pass (k_group_onepass): 56 rows
+// leave its wave 0 enough registers for the chain work beside the block
+// (64-row blocks spilled 11 of their rows around the wait, 18% more bytes).
+constexpr int kGroupSegRows = 56;
+inline int seg_slot(int seg_rows)
+{
+    return seg_rows == 16 ? 0 : seg_rows == 32 ? 1 : seg_rows == 64 ? 2 : 3;
+}
 constexpr int kSegPad = 16;       // segment records are padded to a multiple of this
 
 struct SegCache {
@@ -184,7 +194,7 @@ struct pent_plan {
     double *d_diag;          // 5n: a, b, c, d, e (zero-padded outside the matrix)
     double *d_fac;           // 4n: alpha, beta, gamma, delta
     double *d_anorm;         // 1: ||A||_inf
-    int64_t npad;            // record rows: n rounded up to kRecPad, rows >= n all zero
+    int64_t npad;            // record rows: n + 256 rounded up to kRecPad, rows >= n all zero
     pent::FwdRec *d_fwd;     // npad
     pent::BwdRec *d_bwd;     // npad
     int sched_kind;          // 0 auto, 1 lane, 2 partitioned, 3 resident tile, 4 single pass

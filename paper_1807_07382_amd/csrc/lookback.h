@@ -416,10 +416,13 @@ __device__ __forceinline__ void stage_records(const FwdRec *fwd, const BwdRec *b
     const int lane = threadIdx.x & 63;
     const char *fs = (const char *)(fwd + r0) + 16 * lane;
     const uint32_t fl = (uint32_t)(uintptr_t)lf;
+    // 1 KB per load; lanes past the block's records stay idle in the last
+    // (partial) one, so nothing lands past lf
 #pragma unroll
-    for (int c = 0; c < K * (int)sizeof(FwdRec) / 1024; c++)
-        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(fs + 1024 * c),
-                                         (__attribute__((address_space(3))) void *)(fl + 1024u * c), 16, 0, 0);
+    for (int c = 0; c < (K * (int)sizeof(FwdRec) + 1023) / 1024; c++)
+        if ((c + 1) * 1024 <= K * (int)sizeof(FwdRec) || 64 * c + lane < K * (int)sizeof(FwdRec) / 16)
+            __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(fs + 1024 * c),
+                                             (__attribute__((address_space(3))) void *)(fl + 1024u * c), 16, 0, 0);
     const char *bs = (const char *)(bwd + r0) + 16 * lane;
     if (K * (int)sizeof(BwdRec) >= 1024 || lane < K * (int)sizeof(BwdRec) / 16)
         __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)bs,

@@ -92,8 +92,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     const GroupMat m = mats[un.mat];
     const CFwd fwd = (CFwd)m.fwd;
     const CBwd bwd = (CBwd)m.bwd;
-    const CSeg seg = (CSeg)m.seg64;
-    const CGrp gtab = (CGrp)m.grp64;
+    const CSeg seg = (CSeg)m.segp;
+    const CGrp gtab = (CGrp)m.grpp;
     const int64_t j = un.col0 + lane;
     const bool act = j < m.batch;
     const int64_t jj = act ? j : un.col0;  // idle lanes read the tile's first column (its own lines)
@@ -691,8 +691,8 @@ hipError_t launch_onepass_fix(const FwdRec *fwd, const BwdRec *bwd, const SegRec
     return hipLaunchKernel(fn, dim3((unsigned)units), dim3(64 * kFixW), args, 0, s);
 }
 
-// ---- group variant 6: 64-row segments, four per workgroup
-constexpr int kGroupK = 64, kGroupW = 4;
+// ---- group variant 6: kGroupSegRows-row segments, four per workgroup
+constexpr int kGroupK = kGroupSegRows, kGroupW = 4;
 
 int group_onepass_rows() { return kGroupK * kGroupW; }
 
