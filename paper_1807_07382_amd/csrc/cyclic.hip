@@ -405,11 +405,23 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
         // formed in place with the two overwritten originals kept rolling.
         const int Lc = L + 2 < K ? L + 2 : K;
         double h0 = 0.0, h1 = 0.0, h2 = 0.0, h3 = 0.0;
+        // Halo rows held by a neighbouring wave of the group come through
+        // LDS: rows r0-2, r0-1 are the last two rows of wave w-1's full
+        // block; rows r0+K, r0+K+1 are the first two of wave w+1's when that
+        // wave has E rows (then this block is full and needs both).  The
+        // group's edge halos, and the border rows m, m+1 past a last E row,
+        // are read from memory.
+        const bool top_lds = w > 0;
+        const bool bot_lds = w < W - 1 && m > r0 + K;
         if (act && L > 0) {
-            h0 = col[wrap(r0 - 2, n) * ldf];
-            h1 = col[wrap(r0 - 1, n) * ldf];
-            if (L + 1 >= K) h2 = col[wrap(r0 + K, n) * ldf];
-            if (L + 2 >= K) h3 = col[wrap(r0 + K + 1, n) * ldf];
+            if (!top_lds) {
+                h0 = col[wrap(r0 - 2, n) * ldf];
+                h1 = col[wrap(r0 - 1, n) * ldf];
+            }
+            if (!bot_lds) {
+                if (L + 1 >= K) h2 = col[wrap(r0 + K, n) * ldf];
+                if (L + 2 >= K) h3 = col[wrap(r0 + K + 1, n) * ldf];
+            }
         }
         // rows r0 .. r0+Lc-1 <= m+1 never wrap (only the halo rows can)
         const double *base = col + (L > 0 ? r0 * ldf : 0);
@@ -419,6 +431,27 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
         } else {
 #pragma unroll
             for (int k = 0; k < K; k++) v[k] = (act && k < Lc) ? base[k * ldf] : 0.0;
+        }
+        {
+            // every wave's first and last two rows, through the look-back's
+            // staging area (W x 4 x 64 of its kStage x 128 doubles; the
+            // look-back first writes it after the barrier that follows the
+            // partial products, when every wave has read its halo)
+            static_assert(W * 4 * 64 <= kStage * 128, "the halo rows fit the staging area");
+            double (*hx)[4][64] = (double (*)[4][64])&agg[0][0];
+            hx[w][0][lane] = v[0];
+            hx[w][1][lane] = v[1];
+            hx[w][2][lane] = v[K - 2];
+            hx[w][3][lane] = v[K - 1];
+            __syncthreads();
+            if (top_lds && L > 0) {
+                h0 = hx[w - 1][2][lane];
+                h1 = hx[w - 1][3][lane];
+            }
+            if (bot_lds) {
+                h2 = hx[w + 1][0][lane];
+                h3 = hx[w + 1][1][lane];
+            }
         }
         if (last && w == 0) {
             const double cm2 = act ? col[(m - 2) * ldf] : 0.0, cm1 = act ? col[(m - 1) * ldf] : 0.0;
