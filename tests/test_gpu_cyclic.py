@@ -129,10 +129,14 @@ def test_cn_rhs_against_oracle(torch, sigma):
 
 @pytest.mark.parametrize("kind,seg", SCHEDULES)
 @pytest.mark.parametrize("sigma", [0.1, 21.5, 1e3])
-@pytest.mark.parametrize("n,batch", [(5, 3), (37, 65), (100, 130), (4097, 64)])
+@pytest.mark.parametrize("n,batch", [(5, 3), (37, 65), (66, 64), (68, 33), (100, 130), (194, 70),
+                                     (4097, 64)])
 def test_cn_step_against_oracle(torch, n, batch, sigma, kind, seg):
     """One Crank-Nicolson step X = A^{-1}(2C - AC) (the single-pass form
-    builds the right-hand side in registers) against the oracle's step."""
+    builds the right-hand side in registers) against the oracle's step.
+    n = 66, 68, 194: with 64-row blocks, a full block whose partner wave
+    has no E rows (its halo rows are the border rows m, m+1, read from
+    memory) or only two (they come from the partner's short block)."""
     print_case(test="cn_step", n=n, batch=batch, sigma=sigma, kind=kind, seg=seg)
     C = rhs(n, batch, seed=n + batch)
     ref = cyclic.cn_run(sigma, C, 1)
