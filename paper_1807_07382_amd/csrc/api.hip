@@ -394,7 +394,7 @@ void io_schedule(const pent_plan *p, int64_t batch, bool inplace64, int *kind, i
 // x = A^{-1} f with FP64 arithmetic; f FP32 or FP64; summ: scratch of
 // summ_bytes() for the chosen schedule.
 int solve_io(pent_plan *h, const void *f, bool f32, int64_t ldf, double *x, int64_t ldx,
-             int64_t batch, void *summ, hipStream_t s)
+             int64_t batch, void *summ, hipStream_t s, bool words_clear = false)
 {
     const bool inplace64 = !f32 && (const void *)x == f && ldx == ldf;
     int kind, seg_rows, st;
@@ -412,7 +412,7 @@ int solve_io(pent_plan *h, const void *f, bool f32, int64_t ldf, double *x, int6
     if (!seg) return st;
     if (kind == 4)
         return hip_status(launch_onepass(h->d_fwd, h->d_bwd, seg, h->n, seg_rows, f, f32, ldf, x,
-                                         ldx, batch, summ, h->d_err, s));
+                                         ldx, batch, summ, h->d_err, s, 64, 64, words_clear));
     const int64_t summ_ld = (batch + 63) / 64 * 64;
     return hip_status(launch_part_sweep_io(h->d_fwd, h->d_bwd, seg, h->n, h->npad, seg_rows, f,
                                            f32, ldf, x, ldx, batch, (double *)summ, summ_ld, s));
@@ -1552,31 +1552,53 @@ int pent_ch2d_step(pent_handle hx, pent_handle hy, double *C, double *R, int64_t
         ninst > 65535 || C == R)
         return ret(PENT_INVALID_VALUE);
     hipStream_t s = (hipStream_t)stream;
+    const int64_t batch = ny * ninst, ybatch = ninst * nx;
+    // the y sweeps' scratch comes first: where they run as a single pass
+    // after the single-pass x sweeps, the x-sweep kernel zeroes their
+    // status words, and the step needs no clearing kernel between the two
+    int ykind, yseg;
+    io_schedule(hy, ybatch, false, &ykind, &yseg);
+    const size_t ybytes = summ_bytes(hy, ykind, yseg, ybatch);
+    void *ybuf = nullptr;
+    if (ybytes) {
+        const hipError_t e = scratch_alloc(&ybuf, ybytes, s);
+        if (e != hipSuccess) return ret(hip_status(e));
+    }
+    int st = PENT_OK;
+    bool ywords_clear = false;
     // x sweeps, system (y, k) being nx contiguous values: the single pass
     // forms the explicit right-hand side from C itself where a tile of it
     // fits on the device; else the stencil pass writes it to R first
-    const int64_t batch = ny * ninst;
     if (hx->tst_cap == 0) hx->tst_cap = onepass_t_capacity(true);
     if (hx->tst_cap > 0 && onepass_t_groups(nx) <= hx->tst_cap / 4 &&
         (batch + 63) / 64 * onepass_t_groups(nx) <= (int64_t)UINT32_MAX / 2) {
-        int st;
         const SegRec *seg64 = seg_cache(hx, 64, &st);
-        if (!seg64) return ret(st);
-        void *xbuf = nullptr;
-        hipError_t e = scratch_alloc(&xbuf, onepass_t_scratch_bytes(nx, batch), s);
-        if (e != hipSuccess) return ret(hip_status(e));
-        e = launch_onepass_t_ch2d(hx->d_fwd, hx->d_bwd, seg64, nx, C, R, ny, ninst, dt, h, xbuf,
-                                  hx->d_err, s);
-        const hipError_t e2 = hipFreeAsync(xbuf, s);
-        if (e != hipSuccess || e2 != hipSuccess) return ret(hip_status(e != hipSuccess ? e : e2));
+        if (seg64) {
+            void *xbuf = nullptr;
+            hipError_t e = scratch_alloc(&xbuf, onepass_t_scratch_bytes(nx, batch), s);
+            if (e == hipSuccess) {
+                const bool clear = ykind == 4 &&
+                                   onepass_words(hy->n, yseg, ybatch) <= onepass_t_threads(nx, batch);
+                e = launch_onepass_t_ch2d(hx->d_fwd, hx->d_bwd, seg64, nx, C, R, ny, ninst, dt, h, xbuf,
+                                          hx->d_err, s, clear ? (unsigned int *)ybuf : nullptr,
+                                          clear ? onepass_words(hy->n, yseg, ybatch) : 0);
+                const hipError_t e2 = hipFreeAsync(xbuf, s);
+                if (e == hipSuccess) e = e2;
+                ywords_clear = clear && e == hipSuccess;
+            }
+            if (e != hipSuccess) st = hip_status(e);
+        }
     } else {
-        int st = pent_ch2d_rhs(C, R, ny, ninst, nx, dt, h, stream);
-        if (st != PENT_OK) return st;
-        st = pent_solve_strided(hx, R, batch, nx, stream);
-        if (st != PENT_OK) return st;
+        st = pent_ch2d_rhs(C, R, ny, ninst, nx, dt, h, stream);
+        if (st == PENT_OK) st = pent_solve_strided(hx, R, batch, nx, stream);
     }
     // y sweeps: batch-fastest over (k, x), read from R, written into C
-    return ret(solve_io_scratch(hy, R, ninst * nx, C, ninst * nx, ninst * nx, (hipStream_t)stream));
+    if (st == PENT_OK) st = solve_io(hy, R, false, ybatch, C, ybatch, ybatch, ybuf, s, ywords_clear);
+    if (ybuf) {
+        const hipError_t e = hipFreeAsync(ybuf, s);
+        if (st == PENT_OK && e != hipSuccess) st = hip_status(e);
+    }
+    return ret(st);
 }
 
 pent_cyclic pent_cyclic_factor(int64_t n, const double *a, const double *b, const double *c,

@@ -356,6 +356,9 @@ int onepass_waves(int seg_rows);                     // segments (waves) per wor
 int onepass_waves_override();
 int64_t onepass_groups(int64_t n, int seg_rows);     // workgroups per 64-system tile
 int64_t onepass_units(int64_t n, int seg_rows, int64_t batch);
+// status words (tickets, forward and backward statuses) at the start of the
+// scratch, which must be zero when the kernel starts
+int64_t onepass_words(int64_t n, int seg_rows, int64_t batch);
 size_t onepass_scratch_bytes(int64_t n, int seg_rows, int64_t batch);
 int onepass_capacity(int seg_rows);  // co-resident workgroups on the current device
 int onepass_t_capacity(bool stencil = false);
@@ -366,11 +369,16 @@ hipError_t launch_onepass_t(const FwdRec *fwd, const BwdRec *bwd, const SegRec *
                             hipStream_t s);
 // The x sweeps of a 2-D Cahn-Hilliard step with its explicit right-hand side
 // formed on the fly: grid C[y][k][x] (ny x ninst x nx, contiguous) in, the
-// swept R (same layout) out; systems (y, k), nx rows each (n == nx).
+// swept R (same layout) out; systems (y, k), nx rows each (n == nx).  The
+// kernel also zeroes clear_words words at clear (the status words of the
+// y sweeps' single pass, launched next on the stream), at most one word per
+// thread of its grid (onepass_t_threads).
+int64_t onepass_t_threads(int64_t n, int64_t batch);
 hipError_t launch_onepass_t_ch2d(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg64,
                                  int64_t n, const double *C, double *R, int64_t ny, int64_t ninst,
                                  const double *dt, double h, void *scratch, unsigned int *err,
-                                 hipStream_t s);
+                                 hipStream_t s, unsigned int *clear = nullptr,
+                                 int64_t clear_words = 0);
 int onepass_fix_capacity();
 int64_t onepass_fix_groups(int64_t n);
 size_t onepass_fix_scratch_bytes(int64_t n, int64_t batch);
@@ -381,7 +389,8 @@ hipError_t launch_onepass_fix(const FwdRec *fwd, const BwdRec *bwd, const SegRec
 hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg, int64_t n,
                           int seg_rows, const void *Fin, bool f32, int64_t ldf, double *X,
                           int64_t ldx, int64_t batch, void *scratch, unsigned int *err,
-                          hipStream_t s, int64_t tsf = 64, int64_t tsx = 64);
+                          hipStream_t s, int64_t tsf = 64, int64_t tsx = 64,
+                          bool words_clear = false);  // words_clear: the status words are zero already
 
 // ---- measurement (copy.hip): dst = src through the single pass's blocks ----
 hipError_t launch_block_copy(const double *src, double *dst, int64_t n, int64_t batch, int64_t lds,

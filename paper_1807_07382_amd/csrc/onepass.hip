@@ -222,9 +222,16 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(3))) voi
     const FwdRec *fwd_, const BwdRec *bwd_, const SegRec *seg_, int64_t n, int ngroups, double *F,
     int64_t ld, int64_t batch, unsigned int *ctr, unsigned int *fst, unsigned int *bst, double *ex,
     unsigned int *err, const double *Cin, int64_t ny, int64_t ninst, const double *dt,
-    double inv_h2)
+    double inv_h2, unsigned int *clr, int64_t nclr)
 {
     static_assert(!ST || K == 64, "the halo rows are held one per lane");
+    // status words of the launch that follows on the stream (nclr of them at
+    // clr, at most one per thread of the grid), cleared here so that it
+    // needs no clearing kernel of its own
+    {
+        const int64_t i = (int64_t)blockIdx.x * (64 * W) + threadIdx.x;
+        if (i < nclr) clr[i] = 0u;
+    }
     PENT_GROUP_LDS(W);
     __shared__ double tb[W][8][66];  // row stride 66: the transposing writes hit distinct banks
     __shared__ double xe[ST ? W : 1][2][64];  // ST: each block's first and last row of C
@@ -518,10 +525,15 @@ int64_t onepass_units(int64_t n, int seg_rows, int64_t batch)
     return (batch + 63) / 64 * onepass_groups(n, seg_rows);
 }
 
+int64_t onepass_words(int64_t n, int seg_rows, int64_t batch)
+{
+    return kTicketWords + 2 * onepass_units(n, seg_rows, batch);
+}
+
 size_t onepass_scratch_bytes(int64_t n, int seg_rows, int64_t batch)
 {
     const int64_t units = onepass_units(n, seg_rows, batch);
-    const size_t words = (size_t)(kTicketWords + 2 * units);
+    const size_t words = (size_t)onepass_words(n, seg_rows, batch);
     const size_t wbytes = (words * sizeof(unsigned int) + 255) / 256 * 256;
     return wbytes + (size_t)units * kExRows * 64 * sizeof(double);
 }
@@ -541,7 +553,7 @@ int onepass_capacity(int seg_rows)
 hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg, int64_t n,
                           int seg_rows, const void *Fin, bool f32, int64_t ldf, double *X,
                           int64_t ldx, int64_t batch, void *scratch, unsigned int *err,
-                          hipStream_t s, int64_t tsf, int64_t tsx)
+                          hipStream_t s, int64_t tsf, int64_t tsx, bool words_clear)
 {
     if (seg_rows != 32 && seg_rows != 64) return hipErrorInvalidValue;
     const int W = onepass_waves(seg_rows);
@@ -550,14 +562,17 @@ hipError_t launch_onepass(const FwdRec *fwd, const BwdRec *bwd, const SegRec *se
     // segment records exist for ngroups * W segments: the cache is padded to
     // a multiple of kSegPad, which W divides
     if (units > (int64_t)UINT32_MAX / 2 || kSegPad % W != 0) return hipErrorInvalidValue;
-    const int64_t words = kTicketWords + 2 * units;
+    const int64_t words = onepass_words(n, seg_rows, batch);
     unsigned int *w = (unsigned int *)scratch;
     unsigned int *ctr = w, *fst = w + kTicketWords, *bst = w + kTicketWords + units;
     const size_t wbytes = ((size_t)words * sizeof(unsigned int) + 255) / 256 * 256;
     double *ex = (double *)((char *)scratch + wbytes);
-    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, w, words);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    if (!words_clear) {
+        hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, w, words);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const void *fn = onepass_fn_kw(seg_rows, W, f32);
     const SegRec *segp = seg;
     int ng = (int)ngroups;
@@ -585,6 +600,11 @@ int onepass_t_capacity(bool stencil)
 
 int64_t onepass_t_groups(int64_t n) { return (n + kTK * kTW - 1) / (kTK * kTW); }
 
+int64_t onepass_t_threads(int64_t n, int64_t batch)
+{
+    return (batch + 63) / 64 * onepass_t_groups(n) * 64 * kTW;
+}
+
 size_t onepass_t_scratch_bytes(int64_t n, int64_t batch)
 {
     const int64_t units = (batch + 63) / 64 * onepass_t_groups(n);
@@ -598,7 +618,8 @@ namespace {
 hipError_t launch_t(bool stencil, const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg64,
                     int64_t n, double *F, int64_t batch, int64_t ld, void *scratch,
                     unsigned int *err, const double *Cin, int64_t ny, int64_t ninst,
-                    const double *dt, double inv_h2, hipStream_t s)
+                    const double *dt, double inv_h2, hipStream_t s, unsigned int *clr,
+                    int64_t nclr)
 {
     const int64_t ngroups = onepass_t_groups(n);
     const int64_t units = (batch + 63) / 64 * ngroups;
@@ -615,7 +636,7 @@ hipError_t launch_t(bool stencil, const FwdRec *fwd, const BwdRec *bwd, const Se
     void *args[] = {(void *)&fwd, (void *)&bwd, (void *)&seg64, (void *)&n,   (void *)&ng,
                     (void *)&F,   (void *)&ld,  (void *)&batch, (void *)&ctr, (void *)&fst,
                     (void *)&bst, (void *)&ex,  (void *)&err,   (void *)&Cin, (void *)&ny,
-                    (void *)&ninst, (void *)&dt, (void *)&inv_h2};
+                    (void *)&ninst, (void *)&dt, (void *)&inv_h2, (void *)&clr, (void *)&nclr};
     const void *fn = stencil ? (const void *)k_onepass_t<kTK, kTW, true>
                              : (const void *)k_onepass_t<kTK, kTW, false>;
     return hipLaunchKernel(fn, dim3((unsigned)units), dim3(64 * kTW), args, 0, s);
@@ -627,16 +648,19 @@ hipError_t launch_onepass_t(const FwdRec *fwd, const BwdRec *bwd, const SegRec *
                             double *F, int64_t batch, int64_t ld, void *scratch, unsigned int *err,
                             hipStream_t s)
 {
-    return launch_t(false, fwd, bwd, seg64, n, F, batch, ld, scratch, err, F, batch, 1, nullptr, 0.0, s);
+    return launch_t(false, fwd, bwd, seg64, n, F, batch, ld, scratch, err, F, batch, 1, nullptr, 0.0, s,
+                    nullptr, 0);
 }
 
 hipError_t launch_onepass_t_ch2d(const FwdRec *fwd, const BwdRec *bwd, const SegRec *seg64,
                                  int64_t n, const double *C, double *R, int64_t ny, int64_t ninst,
                                  const double *dt, double h, void *scratch, unsigned int *err,
-                                 hipStream_t s)
+                                 hipStream_t s, unsigned int *clear, int64_t clear_words)
 {
+    if (clear_words < 0 || (clear_words > 0 && !clear) || clear_words > onepass_t_threads(n, ny * ninst))
+        return hipErrorInvalidValue;
     return launch_t(true, fwd, bwd, seg64, n, R, ny * ninst, n, scratch, err, C, ny, ninst, dt,
-                    1.0 / (h * h), s);
+                    1.0 / (h * h), s, clear, clear_words);
 }
 
 // One fused refinement correction (k_onepass_fix): x += A^{-1}(f - A x).
